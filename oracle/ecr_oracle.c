@@ -1,0 +1,876 @@
+/*
+ * ecr_oracle.c -- plain FP64 CPU oracle of the ion PIC/MCC step of the ECRIS
+ * model of Mironov et al., Sec. II ("The model description").
+ *
+ * TEST INFRASTRUCTURE ONLY: it exists to check the GPU library.  It is built
+ * with -O2 -ffp-contract=off and no fast-math, keeps every particle in id
+ * order, and does each step of the method in the order the method states,
+ * with no blocking, fusion or reordering:
+ *
+ *   sort by cell (every sort_every steps) -> ion-ion Coulomb scattering
+ *   (Takizuka-Abe pairing, Nanbu angle) -> Boris push in the minimum-B field
+ *   -> wall / extraction-aperture loss with recycling -> electron-impact
+ *   ionisation or charge exchange -> cloud-in-cell deposit.
+ *
+ * Where the paper leaves a detail open, the oracle takes one stated reading;
+ * each one is named at the function that implements it.  Random numbers come
+ * from Philox4x32-10 (Salmon et al., SC'11) keyed by the run seed, with the
+ * counter (particle id, step, stream, call index), so that any implementation
+ * of the same definition draws the same numbers.
+ */
+#include "ecr_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* SI (CODATA 2018) constants */
+#define E_CHARGE 1.602176634e-19
+#define AMU 1.66053906660e-27
+#define EPS0 8.8541878128e-12
+#define PI 3.14159265358979323846
+#define EPS_WALL 1e-9 /* re-emission offset from a wall, m */
+
+/* Philox stream ids (third counter word) */
+enum { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4 };
+
+/* Nanbu A(s) table: nodes s = 2^e (1 + j/K) for e in [E_LO, E_HI], j in [0, K) */
+#define A_E_LO (-20)
+#define A_E_HI 2
+#define A_K 128
+#define A_NODES ((A_E_HI - A_E_LO + 1) * A_K + 1)
+#define S_LO 9.5367431640625e-07 /* 2^-20: below, A = 1/s */
+#define S_HI 8.0                 /* 2^3: at and above, isotropic scattering */
+
+struct orc_sim {
+  orc_params p;
+  int64_t N;
+  /* derived constants */
+  double M[ORC_MAXS];                /* species mass, kg */
+  double qmh[ORC_MAXS][ORC_MAXQ];    /* (Q e / M) dt / 2 */
+  double pion[ORC_MAXS][2][ORC_MAXQ];/* ionisation probability per step [outside, inside] */
+  double ccx[ORC_MAXS];              /* n0 sigma1 dt */
+  int cxok[ORC_MAXS][ORC_MAXQ];
+  double sig_w[ORC_MAXS], sig_n[ORC_MAXS], sig_i[ORC_MAXS], decx[ORC_MAXS];
+  int64_t sp_end[ORC_MAXS];          /* particle ids [sp_end[s-1], sp_end[s]) are species s */
+  double ia2, ic2, idx, idy, idz, hL, R0sq, rap2, nfac, Cs, w;
+  double c1, c2, c3, c4;
+  int nx1, ny1, nz1;
+  int64_t ncell, nnode;
+  double atab[A_NODES]; /* ln A at the nodes */
+  /* particle state, indexed by id */
+  double *x, *y, *z, *vx, *vy, *vz;
+  uint8_t *q, *sp, *ev;
+  uint32_t *cell;
+  /* cell order */
+  uint32_t *order, *cell_off;
+  int64_t step;
+  int need_sort;
+  orc_tallies t;
+  double *dens[3];
+  int64_t dens_steps;
+  /* scratch for the Coulomb pools */
+  uint32_t *pool;
+  uint32_t *pkey;
+};
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 and Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).       */
+/* One round maps (c0,c1,c2,c3) with key (k0,k1) to                           */
+/*   (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0));       */
+/* the key is bumped by the Weyl constants before every round but the first. */
+/* The 64-bit instance is built from the same macro and is checked against   */
+/* an independent implementation in the tests.                               */
+/* ------------------------------------------------------------------------ */
+static void mulhilo32(uint32_t a, uint32_t b, uint32_t *hi, uint32_t *lo) {
+  uint64_t p = (uint64_t)a * (uint64_t)b;
+  *hi = (uint32_t)(p >> 32);
+  *lo = (uint32_t)p;
+}
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+#define PHILOX_BODY(T, MULHILO, M0, M1, W0, W1)                                 \
+  T c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1]; \
+  for (int r = 0; r < 10; r++) {                                                \
+    T h0, l0, h1, l1;                                                           \
+    if (r > 0) {                                                                \
+      k0 += (T)(W0);                                                            \
+      k1 += (T)(W1);                                                            \
+    }                                                                           \
+    MULHILO((T)(M0), c0, &h0, &l0);                                             \
+    MULHILO((T)(M1), c2, &h1, &l1);                                             \
+    T n0 = h1 ^ c1 ^ k0, n1 = l1, n2 = h0 ^ c3 ^ k1, n3 = l0;                   \
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;                                         \
+  }                                                                             \
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  PHILOX_BODY(uint32_t, mulhilo32, 0xD2511F53u, 0xCD9E8D57u, 0x9E3779B9u, 0xBB67AE85u)
+}
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  PHILOX_BODY(uint64_t, mulhilo64, 0xD2E7470EE14C6C93ull, 0xCA5A826395121157ull,
+              0x9E3779B97F4A7C15ull, 0xBB67AE8584CAA73Bull)
+}
+
+/* uniform double in [0,1) from 27 + 26 random bits */
+double orc_u53(uint32_t a, uint32_t b) {
+  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+static void draw(const orc_sim *s, uint32_t id, uint32_t step, uint32_t stream, uint32_t k,
+                 uint32_t out[4]) {
+  uint32_t ctr[4] = {id, step, stream, k};
+  uint32_t key[2] = {(uint32_t)s->p.seed, (uint32_t)(s->p.seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* Box-Muller: two standard normals from two uniforms in [0,1) */
+static void box_muller(double ua, double ub, double *n1, double *n2) {
+  double r = sqrt(-2.0 * log(1.0 - ua));
+  double th = 2.0 * PI * ub;
+  *n1 = r * cos(th);
+  *n2 = r * sin(th);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Magnetic field (Sec. II, hexapole formulas and the solenoid description). */
+/* Solenoid: on-axis Bz(z) = B0 (1 + k (2z/L)^2), continued off axis to      */
+/* second order (Br = -(r/2) dBz/dz, Bz(r,z) = Bz(z) - (r^2/4) d2Bz/dz2), so  */
+/* the field is divergence- and curl-free.  Hexapole without edge effects:   */
+/* Bx += BH sin(2 theta) R^2/R0^2 = (BH/R0^2) 2xy,                           */
+/* By += BH cos(2 theta) R^2/R0^2 = (BH/R0^2)(x^2 - y^2).                    */
+/* ------------------------------------------------------------------------ */
+static void field_B(const orc_sim *s, double x, double y, double z, double *bx, double *by,
+                    double *bz) {
+  double xx = x * x, yy = y * y, zz = z * z, xy = x * y;
+  *bx = s->c2 * xy - (s->c1 * x) * z;
+  *by = s->c3 * (xx - yy) - (s->c1 * y) * z;
+  *bz = (s->p.B0 + s->c1 * zz) - s->c4 * (xx + yy);
+}
+
+void orc_field(const orc_sim *s, double x, double y, double z, double B[3]) {
+  field_B(s, x, y, z, &B[0], &B[1], &B[2]);
+}
+
+/* cell-in-cell index helpers on the box [-R0,R0]^2 x [-L/2,L/2] */
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+uint32_t orc_cell_of(const orc_sim *s, double x, double y, double z) {
+  int ix = clampi((int)floor((x + s->p.R0) * s->idx), 0, s->p.nx - 1);
+  int iy = clampi((int)floor((y + s->p.R0) * s->idy), 0, s->p.ny - 1);
+  int iz = clampi((int)floor((z + s->hL) * s->idz), 0, s->p.nz - 1);
+  return (uint32_t)ix + (uint32_t)s->p.nx * ((uint32_t)iy + (uint32_t)s->p.ny * (uint32_t)iz);
+}
+
+/* CIC: lower node index along each axis and the fractional offset */
+static void cic_axis(double pos, double origin, double inv_h, int ncell, int *i, double *t) {
+  double f = (pos + origin) * inv_h;
+  int k = clampi((int)floor(f), 0, ncell - 1);
+  *i = k;
+  *t = f - (double)k;
+}
+
+/* trilinear interpolation of the node E field at (x,y,z) */
+static void gather_E(const orc_sim *s, double x, double y, double z, double E[3]) {
+  int ix, iy, iz;
+  double tx, ty, tz;
+  cic_axis(x, s->p.R0, s->idx, s->p.nx, &ix, &tx);
+  cic_axis(y, s->p.R0, s->idy, s->p.ny, &iy, &ty);
+  cic_axis(z, s->hL, s->idz, s->p.nz, &iz, &tz);
+  double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
+  for (int c = 0; c < 3; c++) {
+    const double *F = s->p.efield + (int64_t)c * s->nnode;
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; dz++)
+      for (int dy = 0; dy < 2; dy++)
+        for (int dx = 0; dx < 2; dx++) {
+          int64_t node = (int64_t)(ix + dx) + (int64_t)s->nx1 * ((iy + dy) + (int64_t)s->ny1 * (iz + dz));
+          acc = acc + ((wx[dx] * wy[dy]) * wz[dz]) * F[node];
+        }
+    E[c] = acc;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boris push (standard leapfrog rotation): v- = v + hE; t = hB;             */
+/* s = 2t/(1+t.t); v' = v- + v- x t; v+ = v- + v' x s; v = v+ + hE;          */
+/* x += v dt, with h = (Q e / M) dt/2.  Q = 0 gives a straight line (atoms). */
+/* ------------------------------------------------------------------------ */
+static void boris(const orc_sim *s, double h, const double *E, double *x, double *y, double *z,
+                  double *vx, double *vy, double *vz) {
+  double bx, by, bz;
+  field_B(s, *x, *y, *z, &bx, &by, &bz);
+  double vmx = *vx, vmy = *vy, vmz = *vz;
+  if (E) {
+    vmx = vmx + h * E[0];
+    vmy = vmy + h * E[1];
+    vmz = vmz + h * E[2];
+  }
+  double tx = h * bx, ty = h * by, tz = h * bz;
+  double t2 = (tx * tx + ty * ty) + tz * tz;
+  double f = 2.0 / (1.0 + t2);
+  double sx = f * tx, sy = f * ty, sz = f * tz;
+  double vpx = vmx + (vmy * tz - vmz * ty);
+  double vpy = vmy + (vmz * tx - vmx * tz);
+  double vpz = vmz + (vmx * ty - vmy * tx);
+  double nvx = vmx + (vpy * sz - vpz * sy);
+  double nvy = vmy + (vpz * sx - vpx * sz);
+  double nvz = vmz + (vpx * sy - vpy * sx);
+  if (E) {
+    nvx = nvx + h * E[0];
+    nvy = nvy + h * E[1];
+    nvz = nvz + h * E[2];
+  }
+  *vx = nvx;
+  *vy = nvy;
+  *vz = nvz;
+  *x = *x + nvx * s->p.dt;
+  *y = *y + nvy * s->p.dt;
+  *z = *z + nvz * s->p.dt;
+}
+
+void orc_boris(const orc_sim *s, int species, int q, const double E[3], double x[3], double v[3]) {
+  boris(s, s->qmh[species][q], E, &x[0], &x[1], &x[2], &v[0], &v[1], &v[2]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nanbu's A(s): the root of coth(A) - 1/A = exp(-s).  The root is found by  */
+/* bisection on a form of the equation that has no cancellation:             */
+/*   s >= 1: N(A)/(A sinh A) = exp(-s), N(A) = A cosh A - sinh A summed as    */
+/*           the all-positive series sum_k 2k A^(2k+1)/(2k+1)!  (A < 3), else */
+/*           coth(A) - 1/A;                                                   */
+/*   s <  1: 1/A - 2/expm1(2A) = -expm1(-s)  (this is 1 - (coth A - 1/A)).    */
+/* ------------------------------------------------------------------------ */
+static double langevin(double a) {
+  if (a < 3.0) {
+    double term = a * a * a / 3.0; /* k = 1: 2 a^3 / 3! */
+    double sum = term;
+    for (int k = 2; k < 60; k++) {
+      /* term_k / term_{k-1} = (2k / (2k-2)) * a^2 / ((2k)(2k+1)) */
+      term = term * (a * a) / ((double)(2 * k - 2) * (double)(2 * k + 1));
+      sum += term;
+      if (term < 1e-20 * sum) break;
+    }
+    return sum / (a * sinh(a));
+  }
+  return 1.0 / tanh(a) - 1.0 / a;
+}
+
+double orc_nanbu_A_root(double sv) {
+  double lo, hi;
+  if (sv >= 1.0) {
+    double target = exp(-sv);
+    lo = 0.0;
+    hi = 3.5;
+    for (int it = 0; it < 400; it++) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (langevin(mid) < target) lo = mid; else hi = mid;
+    }
+  } else {
+    double target = -expm1(-sv);
+    lo = 0.5;
+    hi = 1.0 / sv + 2.0;
+    for (int it = 0; it < 400; it++) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      double g = 1.0 / mid - 2.0 / expm1(2.0 * mid); /* decreasing in A */
+      if (g > target) lo = mid; else hi = mid;
+    }
+  }
+  return 0.5 * (lo + hi);
+}
+
+static void build_atab(orc_sim *s) {
+  for (int e = A_E_LO; e <= A_E_HI; e++)
+    for (int j = 0; j < A_K; j++) {
+      double sv = ldexp(1.0 + (double)j / (double)A_K, e);
+      s->atab[(e - A_E_LO) * A_K + j] = log(orc_nanbu_A_root(sv));
+    }
+  s->atab[A_NODES - 1] = log(orc_nanbu_A_root(S_HI));
+}
+
+/* A(s) on [2^-20, 8): ln A interpolated linearly in s between the table
+ * nodes (ln A is close to linear in s at both ends: -ln s + s/2 for small s,
+ * ln 3 - s for large s), then exponentiated. */
+double orc_nanbu_A(const orc_sim *s, double sv) {
+  int ex;
+  double m = frexp(sv, &ex); /* sv = m 2^ex, m in [0.5, 1) */
+  int e = ex - 1;            /* sv = (2m) 2^e, 2m in [1, 2) */
+  double t = (2.0 * m - 1.0) * (double)A_K;
+  int j = (int)t;
+  double fr = t - (double)j;
+  int i = (e - A_E_LO) * A_K + j;
+  return exp(s->atab[i] + fr * (s->atab[i + 1] - s->atab[i]));
+}
+
+/* 1 - cos(chi) of Nanbu's scattering angle for a uniform u in [0,1):
+ * cos chi = ln(exp(-A) + 2u sinh A)/A, rewritten as
+ * 1 - cos chi = -log1p(u expm1(-2A)) / A, which cannot overflow. */
+double orc_nanbu_omc(const orc_sim *s, double sv, double u) {
+  double omc;
+  if (sv >= S_HI) {
+    omc = 2.0 * u; /* isotropic */
+  } else {
+    double A = (sv < S_LO) ? 1.0 / sv : orc_nanbu_A(s, sv);
+    omc = -log1p(u * expm1(-2.0 * A)) / A;
+  }
+  if (omc < 0.0) omc = 0.0;
+  if (omc > 2.0) omc = 2.0;
+  return omc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Setup                                                                      */
+/* ------------------------------------------------------------------------ */
+static int species_of(const orc_sim *s, int64_t id) {
+  for (int k = 0; k < s->p.n_species; k++)
+    if (id < s->sp_end[k]) return k;
+  return s->p.n_species - 1;
+}
+
+int orc_create(const orc_params *p, orc_sim **out) {
+  if (!p || !out) return -1;
+  if (p->n < 0 || p->n > 0x7fffffff || p->n_species < 1 || p->n_species > ORC_MAXS) return -1;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->sort_every < 1 || !(p->dt > 0.0)) return -1;
+  orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+  if (!s) return -2;
+  s->p = *p;
+  s->N = p->n;
+  double dt = p->dt;
+  int64_t acc = 0;
+  for (int k = 0; k < p->n_species; k++) {
+    const orc_species *sp = &p->sp[k];
+    if (sp->z_max < 0 || sp->z_max >= ORC_MAXQ) { free(s); return -1; }
+    s->M[k] = sp->mass_amu * AMU;
+    for (int Q = 0; Q < ORC_MAXQ; Q++) {
+      s->qmh[k][Q] = ((double)Q * E_CHARGE / s->M[k]) * (dt * 0.5);
+      /* probability of one ionisation in dt: 1 - exp(-n_e k dt) */
+      s->pion[k][1][Q] = (Q < sp->z_max) ? -expm1(-(p->ne_in * sp->k_in[Q]) * dt) : 0.0;
+      s->pion[k][0][Q] = (Q < sp->z_max) ? -expm1(-(p->ne_out * sp->k_out[Q]) * dt) : 0.0;
+      s->cxok[k][Q] = (Q >= 1 && Q <= sp->z_max && !((sp->cx_forbidden_mask >> Q) & 1u));
+    }
+    s->ccx[k] = (sp->n0 * sp->sigma_cx1) * dt;
+    s->sig_w[k] = sqrt(p->T_wall_eV * E_CHARGE / s->M[k]);
+    s->sig_n[k] = sqrt(p->T_n_eV * E_CHARGE / s->M[k]);
+    s->sig_i[k] = sqrt(p->Ti0_eV * E_CHARGE / s->M[k]);
+    s->decx[k] = 4.0 * p->dE_cx_eV * E_CHARGE / s->M[k];
+    if (k == p->n_species - 1) acc = p->n;
+    else acc += (int64_t)floor(sp->fraction * (double)p->n + 0.5);
+    if (acc > p->n) acc = p->n;
+    s->sp_end[k] = acc;
+  }
+  s->ia2 = 1.0 / (p->zone_a * p->zone_a);
+  s->ic2 = 1.0 / (p->zone_c * p->zone_c);
+  s->idx = (double)p->nx / (2.0 * p->R0);
+  s->idy = (double)p->ny / (2.0 * p->R0);
+  s->idz = (double)p->nz / p->L;
+  s->hL = 0.5 * p->L;
+  s->R0sq = p->R0 * p->R0;
+  s->rap2 = p->r_ap * p->r_ap;
+  s->c1 = ((4.0 * p->mirror_k) * p->B0) / (p->L * p->L);
+  s->c2 = (2.0 * p->BH) / (p->R0 * p->R0);
+  s->c3 = p->BH / (p->R0 * p->R0);
+  s->c4 = ((2.0 * p->mirror_k) * p->B0) / (p->L * p->L);
+  /* macro-particle weight: quasi-neutral zone at t = 0 unless given */
+  double vzone = (4.0 / 3.0) * PI * (p->zone_a * p->zone_a) * p->zone_c;
+  s->w = (p->weight > 0.0) ? p->weight : (p->n > 0 ? p->ne_in * vzone / (double)p->n : 0.0);
+  double vcell = ((2.0 * p->R0 / p->nx) * (2.0 * p->R0 / p->ny)) * (p->L / p->nz);
+  s->nfac = s->w / vcell;
+  s->Cs = p->lnL * (E_CHARGE * E_CHARGE) * (E_CHARGE * E_CHARGE) / (4.0 * PI * EPS0 * EPS0);
+  s->nx1 = p->nx + 1;
+  s->ny1 = p->ny + 1;
+  s->nz1 = p->nz + 1;
+  s->ncell = (int64_t)p->nx * p->ny * p->nz;
+  s->nnode = (int64_t)s->nx1 * s->ny1 * s->nz1;
+  build_atab(s);
+
+  int64_t N = p->n;
+  size_t nd = (size_t)(N > 0 ? N : 1);
+  s->x = calloc(nd, 8); s->y = calloc(nd, 8); s->z = calloc(nd, 8);
+  s->vx = calloc(nd, 8); s->vy = calloc(nd, 8); s->vz = calloc(nd, 8);
+  s->q = calloc(nd, 1); s->sp = calloc(nd, 1); s->ev = calloc(nd, 1);
+  s->cell = calloc(nd, 4); s->order = calloc(nd, 4);
+  s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4);
+  s->cell_off = calloc((size_t)s->ncell + 1, 4);
+  for (int f = 0; f < 3; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
+  if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
+      !s->cell || !s->order || !s->pool || !s->pkey || !s->cell_off || !s->dens[0] ||
+      !s->dens[1] || !s->dens[2]) {
+    orc_destroy(s);
+    return -2;
+  }
+  for (int64_t i = 0; i < N; i++) s->sp[i] = (uint8_t)species_of(s, i);
+  s->need_sort = 1;
+  *out = s;
+  return 0;
+}
+
+void orc_destroy(orc_sim *s) {
+  if (!s) return;
+  free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
+  free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order);
+  free(s->pool); free(s->pkey); free(s->cell_off);
+  for (int f = 0; f < 3; f++) free(s->dens[f]);
+  free(s);
+}
+
+double orc_weight(const orc_sim *s) { return s->w; }
+
+static void zero_accumulators(orc_sim *s) {
+  memset(&s->t, 0, sizeof(s->t));
+  for (int f = 0; f < 3; f++) memset(s->dens[f], 0, (size_t)s->nnode * 8);
+  s->dens_steps = 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial ions: uniform in the zone ellipsoid (rejection sampling in its    */
+/* bounding box), Maxwellian velocities at Ti0, all Q = 1.                   */
+/* ------------------------------------------------------------------------ */
+int orc_init_ions(orc_sim *s) {
+  double a = s->p.zone_a, c = s->p.zone_c;
+  for (int64_t i = 0; i < s->N; i++) {
+    uint32_t id = (uint32_t)i;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    for (uint32_t j = 0; j < 64; j++) {
+      uint32_t A[4], B[4];
+      draw(s, id, 0xFFFFFFFFu, S_INIT, 2 * j, A);
+      draw(s, id, 0xFFFFFFFFu, S_INIT, 2 * j + 1, B);
+      double u0 = orc_u53(A[0], A[1]), u1 = orc_u53(A[2], A[3]), u2 = orc_u53(B[0], B[1]);
+      double tx = a * (2.0 * u0 - 1.0), ty = a * (2.0 * u1 - 1.0), tz = c * (2.0 * u2 - 1.0);
+      if (((tx * tx) * s->ia2 + (ty * ty) * s->ia2) + (tz * tz) * s->ic2 < 1.0) {
+        px = tx; py = ty; pz = tz;
+        break;
+      }
+    }
+    uint32_t C[4], D[4];
+    draw(s, id, 0xFFFFFFFFu, S_INIT, 0x10000u, C);
+    draw(s, id, 0xFFFFFFFFu, S_INIT, 0x10001u, D);
+    double n0, n1, n2, ndis;
+    box_muller(orc_u53(C[0], C[1]), orc_u53(C[2], C[3]), &n0, &n1);
+    box_muller(orc_u53(D[0], D[1]), orc_u53(D[2], D[3]), &n2, &ndis);
+    double sg = s->sig_i[s->sp[i]];
+    s->x[i] = px; s->y[i] = py; s->z[i] = pz;
+    s->vx[i] = sg * n0; s->vy[i] = sg * n1; s->vz[i] = sg * n2;
+    s->q[i] = 1;
+    s->ev[i] = ORC_EV_NONE;
+  }
+  s->step = 0;
+  s->need_sort = 1;
+  zero_accumulators(s);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sort by cell: counting sort, stable in particle id.  Each particle keeps  */
+/* the cell it is sorted into as its collision cell until the next sort.     */
+/* ------------------------------------------------------------------------ */
+static void sort_from_cells(orc_sim *s) {
+  memset(s->cell_off, 0, ((size_t)s->ncell + 1) * 4);
+  for (int64_t i = 0; i < s->N; i++) s->cell_off[s->cell[i] + 1]++;
+  for (int64_t c = 0; c < s->ncell; c++) s->cell_off[c + 1] += s->cell_off[c];
+  uint32_t *fill = (uint32_t *)malloc(((size_t)s->ncell + 1) * 4);
+  memcpy(fill, s->cell_off, ((size_t)s->ncell + 1) * 4);
+  for (int64_t i = 0; i < s->N; i++) s->order[fill[s->cell[i]]++] = (uint32_t)i;
+  free(fill);
+}
+
+static void sort_particles(orc_sim *s) {
+  for (int64_t i = 0; i < s->N; i++) s->cell[i] = orc_cell_of(s, s->x[i], s->y[i], s->z[i]);
+  sort_from_cells(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ion-ion Coulomb scattering (Sec. II): Takizuka-Abe random pairing inside */
+/* each collision cell, Nanbu's scattering angle with ln(Lambda) = 10.       */
+/* Reading: one pool per cell of every ion with Q >= 1 (all species), put in */
+/* random order by a 32-bit key drawn per particle and step (ties by id);    */
+/* even pool: pairs (0,1),(2,3),...; odd pool: (0,1),(1,2),(2,0) with dt/2   */
+/* each, in that order, then (3,4),...  The pool density is m w / V_cell.    */
+/* Nanbu: s = lnL e^4 (Qa Qb)^2 n dt / (4 pi eps0^2 mu^2 g^3).               */
+/* ------------------------------------------------------------------------ */
+static uint32_t *g_sort_key; /* qsort comparator context (single-threaded oracle) */
+static int cmp_pool(const void *a, const void *b) {
+  uint32_t ia = *(const uint32_t *)a, ib = *(const uint32_t *)b;
+  uint32_t ka = g_sort_key[ia], kb = g_sort_key[ib];
+  if (ka != kb) return ka < kb ? -1 : 1;
+  return ia < ib ? -1 : (ia > ib ? 1 : 0);
+}
+
+static void coulomb_pair(orc_sim *s, uint32_t ia, uint32_t ib, double nc, double dtp) {
+  uint32_t W[4];
+  draw(s, ia, (uint32_t)s->step, S_COUL, 0, W);
+  double u = orc_u53(W[0], W[1]), u2 = orc_u53(W[2], W[3]);
+  double ux = s->vx[ia] - s->vx[ib];
+  double uy = s->vy[ia] - s->vy[ib];
+  double uz = s->vz[ia] - s->vz[ib];
+  double g2 = (ux * ux + uy * uy) + uz * uz;
+  if (g2 == 0.0) return;
+  double g = sqrt(g2);
+  double ma = s->M[s->sp[ia]], mb = s->M[s->sp[ib]];
+  double mu = (ma * mb) / (ma + mb);
+  double qq = (double)s->q[ia] * (double)s->q[ib];
+  double num = ((s->Cs * (qq * qq)) * nc) * dtp;
+  double den = (mu * mu) * (g2 * g);
+  double sv = num / den;
+  double omc = orc_nanbu_omc(s, sv, u);
+  double sinchi = sqrt(omc * (2.0 - omc));
+  double phi = 2.0 * PI * u2;
+  double ca = sinchi * cos(phi), cb = sinchi * sin(phi);
+  double uperp = sqrt(ux * ux + uy * uy);
+  double dux, duy, duz;
+  if (uperp > 0.0) {
+    dux = (((ux / uperp) * uz) * ca - ((uy / uperp) * g) * cb) - ux * omc;
+    duy = (((uy / uperp) * uz) * ca + ((ux / uperp) * g) * cb) - uy * omc;
+    duz = -(uperp * ca) - uz * omc;
+  } else {
+    dux = g * ca;
+    duy = g * cb;
+    duz = -(g * omc);
+  }
+  double ra = mu / ma, rb = mu / mb;
+  s->vx[ia] = s->vx[ia] + ra * dux;
+  s->vy[ia] = s->vy[ia] + ra * duy;
+  s->vz[ia] = s->vz[ia] + ra * duz;
+  s->vx[ib] = s->vx[ib] - rb * dux;
+  s->vy[ib] = s->vy[ib] - rb * duy;
+  s->vz[ib] = s->vz[ib] - rb * duz;
+}
+
+static void pool_moments(const orc_sim *s, const uint32_t *pool, int64_t m, double mom[4]) {
+  mom[0] = mom[1] = mom[2] = mom[3] = 0.0;
+  for (int64_t k = 0; k < m; k++) {
+    uint32_t i = pool[k];
+    double M = s->M[s->sp[i]];
+    mom[0] += M * s->vx[i];
+    mom[1] += M * s->vy[i];
+    mom[2] += M * s->vz[i];
+    mom[3] += 0.5 * M * ((s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i]);
+  }
+}
+
+static void coulomb(orc_sim *s) {
+  /* per-particle pairing key of this step: word 2 of the STEP draw */
+  for (int64_t i = 0; i < s->N; i++) {
+    uint32_t W[4];
+    draw(s, (uint32_t)i, (uint32_t)s->step, S_STEP, 0, W);
+    s->pkey[i] = W[2];
+  }
+  g_sort_key = s->pkey;
+  for (int64_t c = 0; c < s->ncell; c++) {
+    int64_t m = 0;
+    for (uint32_t k = s->cell_off[c]; k < s->cell_off[c + 1]; k++) {
+      uint32_t i = s->order[k];
+      if (s->q[i] >= 1) s->pool[m++] = i;
+    }
+    if (m < 2) continue;
+    qsort(s->pool, (size_t)m, sizeof(uint32_t), cmp_pool);
+    double before[4], after[4];
+    pool_moments(s, s->pool, m, before);
+    double nc = (double)m * s->nfac;
+    int64_t start = 0;
+    if (m % 2 == 1) {
+      double h = 0.5 * s->p.dt;
+      coulomb_pair(s, s->pool[0], s->pool[1], nc, h);
+      coulomb_pair(s, s->pool[1], s->pool[2], nc, h);
+      coulomb_pair(s, s->pool[2], s->pool[0], nc, h);
+      start = 3;
+    }
+    for (int64_t k = start; k + 1 < m; k += 2) coulomb_pair(s, s->pool[k], s->pool[k + 1], nc, s->p.dt);
+    pool_moments(s, s->pool, m, after);
+    for (int d = 0; d < 3; d++) s->t.coul_dp[d] += after[d] - before[d];
+    s->t.coul_de += after[3] - before[3];
+    s->t.coul_e += before[3];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wall and aperture (Sec. II): the first crossing of the step's segment    */
+/* x0 -> x1 with the flanges z = +-L/2 or the cylinder r = R0 wins (ties go  */
+/* to the flange).  A crossing of z = +L/2 within r_ap of the axis is an     */
+/* extraction: the particle is counted and returned at the gas inlet as an   */
+/* atom.  Any other crossing neutralises it at the wall: full accommodation, */
+/* cosine-law (flux-Maxwellian) re-emission at the wall temperature.         */
+/* ------------------------------------------------------------------------ */
+enum { X_NONE = 0, X_EXT_FLANGE = 1, X_INJ_FLANGE = 2, X_CYL = 3 };
+
+static int segment_exit(const orc_sim *s, double x0, double y0, double z0, double x1, double y1,
+                        double z1, double *fout) {
+  double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
+  double best = 2.0;
+  int kind = X_NONE;
+  if (z1 > s->hL) {
+    best = (s->hL - z0) / dz;
+    kind = X_EXT_FLANGE;
+  } else if (z1 < -s->hL) {
+    best = (-s->hL - z0) / dz;
+    kind = X_INJ_FLANGE;
+  }
+  if (x1 * x1 + y1 * y1 > s->R0sq) {
+    double a = dx * dx + dy * dy;
+    double b = x0 * dx + y0 * dy;
+    double c = (x0 * x0 + y0 * y0) - s->R0sq;
+    double D = b * b - a * c;
+    if (D < 0.0) D = 0.0;
+    double sq = sqrt(D);
+    double f = (b > 0.0) ? (-c) / (b + sq) : (sq - b) / a;
+    if (kind == X_NONE || f < best) {
+      best = f;
+      kind = X_CYL;
+    }
+  }
+  if (best < 0.0) best = 0.0;
+  if (best > 1.0) best = 1.0;
+  *fout = best;
+  return kind;
+}
+
+int orc_segment_exit(const orc_sim *s, const double x0[3], const double x1[3], double *f) {
+  return segment_exit(s, x0[0], x0[1], x0[2], x1[0], x1[1], x1[2], f);
+}
+
+/* flux-Maxwellian re-emission about the inward normal n, tangents t1, t2 */
+static void reemit(orc_sim *s, int64_t i, const double n[3], const double t1[3], const double t2[3]) {
+  uint32_t W[4], V[4];
+  draw(s, (uint32_t)i, (uint32_t)s->step, S_BND, 0, W);
+  draw(s, (uint32_t)i, (uint32_t)s->step, S_BND, 1, V);
+  double sg = s->sig_w[s->sp[i]];
+  double vn = sg * sqrt(-2.0 * log(1.0 - orc_u53(W[0], W[1])));
+  double na, nb;
+  box_muller(orc_u53(W[2], W[3]), orc_u53(V[0], V[1]), &na, &nb);
+  double sa = sg * na, sb = sg * nb;
+  s->vx[i] = (vn * n[0] + sa * t1[0]) + sb * t2[0];
+  s->vy[i] = (vn * n[1] + sa * t1[1]) + sb * t2[1];
+  s->vz[i] = (vn * n[2] + sa * t1[2]) + sb * t2[2];
+}
+
+static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
+  double f;
+  int kind = segment_exit(s, x0, y0, z0, s->x[i], s->y[i], s->z[i], &f);
+  if (kind == X_NONE) return ORC_EV_NONE;
+  int sp = s->sp[i], Q = s->q[i];
+  double dx = s->x[i] - x0, dy = s->y[i] - y0, dz = s->z[i] - z0;
+  double xc = x0 + f * dx, yc = y0 + f * dy, zc = z0 + f * dz;
+  static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, pz[3] = {0, 0, 1}, mz[3] = {0, 0, -1};
+  if (kind == X_EXT_FLANGE && xc * xc + yc * yc <= s->rap2) {
+    s->t.extracted[sp][Q]++;
+    s->t.recycled++;
+    s->q[i] = 0;
+    s->x[i] = s->p.inlet_x;
+    s->y[i] = s->p.inlet_y;
+    s->z[i] = -s->hL + EPS_WALL;
+    reemit(s, i, pz, ex, ey);
+    return ORC_EV_EXTRACT;
+  }
+  s->t.wall[sp][Q]++;
+  s->q[i] = 0;
+  if (kind == X_EXT_FLANGE) {
+    s->x[i] = xc; s->y[i] = yc; s->z[i] = s->hL - EPS_WALL;
+    reemit(s, i, mz, ex, ey);
+  } else if (kind == X_INJ_FLANGE) {
+    s->x[i] = xc; s->y[i] = yc; s->z[i] = -s->hL + EPS_WALL;
+    reemit(s, i, pz, ex, ey);
+  } else {
+    double rc = sqrt(xc * xc + yc * yc);
+    double n[3] = {-xc / rc, -yc / rc, 0.0};
+    double t1[3] = {yc / rc, -xc / rc, 0.0};
+    double sc = (s->p.R0 - EPS_WALL) / rc;
+    s->x[i] = xc * sc; s->y[i] = yc * sc; s->z[i] = zc;
+    reemit(s, i, n, t1, pz);
+  }
+  return ORC_EV_WALL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Monte-Carlo collisions with electrons and neutrals (Sec. II).             */
+/* One uniform u decides: u < P_ion -> Q+1; u < P_ion + P_cx -> charge       */
+/* exchange.  P_ion = 1 - exp(-n_e k_Q dt) with the zone's n_e and rate;     */
+/* P_cx = n0 (Q sigma1) |v| dt (cross-section scaled linearly with Q, no     */
+/* exchange for forbidden Q such as Ar2+).  Exchange with a neutral drawn    */
+/* from a Maxwellian at T_n: Q = 1 takes the neutral's velocity (resonant);  */
+/* Q >= 3 goes to Q-1 and the energy release dE is shared equally in the     */
+/* centre-of-mass frame of the two equal-mass partners.                      */
+/* ------------------------------------------------------------------------ */
+static int mcc(orc_sim *s, int64_t i) {
+  uint32_t W[4];
+  draw(s, (uint32_t)i, (uint32_t)s->step, S_STEP, 0, W);
+  double u = orc_u53(W[0], W[1]);
+  int sp = s->sp[i], Q = s->q[i];
+  double x = s->x[i], y = s->y[i], z = s->z[i];
+  int zone = (((x * x) * s->ia2 + (y * y) * s->ia2) + (z * z) * s->ic2) < 1.0;
+  double pi = (s->p.process_mask & ORC_P_IONIZE) ? s->pion[sp][zone][Q] : 0.0;
+  double pc = 0.0;
+  if ((s->p.process_mask & ORC_P_CX) && s->cxok[sp][Q]) {
+    double sp2 = (s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i];
+    pc = (s->ccx[sp] * (double)Q) * sqrt(sp2);
+  }
+  double pt = pi + pc;
+  if (pt > 0.1) s->t.anomalies++;
+  if (u < pi) {
+    s->t.ionized[sp][Q]++;
+    s->q[i] = (uint8_t)(Q + 1);
+    return ORC_EV_IONIZE;
+  }
+  if (u < pt) {
+    s->t.cx[sp][Q]++;
+    uint32_t G[4], H[4];
+    draw(s, (uint32_t)i, (uint32_t)s->step, S_CX, 0, G);
+    draw(s, (uint32_t)i, (uint32_t)s->step, S_CX, 1, H);
+    double n0, n1, n2, ndis;
+    box_muller(orc_u53(G[0], G[1]), orc_u53(G[2], G[3]), &n0, &n1);
+    box_muller(orc_u53(H[0], H[1]), orc_u53(H[2], H[3]), &n2, &ndis);
+    double sg = s->sig_n[sp];
+    double wx = sg * n0, wy = sg * n1, wz = sg * n2;
+    if (Q == 1) {
+      s->vx[i] = wx; s->vy[i] = wy; s->vz[i] = wz;
+    } else {
+      uint32_t I[4];
+      draw(s, (uint32_t)i, (uint32_t)s->step, S_CX, 2, I);
+      double ct = 1.0 - 2.0 * orc_u53(I[0], I[1]);
+      double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
+      double ph = 2.0 * PI * orc_u53(I[2], I[3]);
+      double nxv = st * cos(ph), nyv = st * sin(ph), nzv = ct;
+      double gx = s->vx[i] - wx, gy = s->vy[i] - wy, gz = s->vz[i] - wz;
+      double g2 = (gx * gx + gy * gy) + gz * gz + s->decx[sp];
+      double hg = 0.5 * sqrt(g2);
+      s->vx[i] = (s->vx[i] + wx) * 0.5 + hg * nxv;
+      s->vy[i] = (s->vy[i] + wy) * 0.5 + hg * nyv;
+      s->vz[i] = (s->vz[i] + wz) * 0.5 + hg * nzv;
+      s->q[i] = (uint8_t)(Q - 1);
+      s->t.cx_products[sp]++;
+    }
+    return ORC_EV_CX;
+  }
+  return ORC_EV_NONE;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cloud-in-cell deposit on the (nx+1)(ny+1)(nz+1) node grid (the mesh of   */
+/* Sec. II), accumulated over steps.                                         */
+/* ------------------------------------------------------------------------ */
+static void deposit(orc_sim *s) {
+  uint32_t dm = s->p.deposit_mask;
+  for (int64_t i = 0; i < s->N; i++) {
+    int Q = s->q[i];
+    int ion = Q >= 1;
+    if (!((ion && (dm & 3u)) || (!ion && (dm & 4u)))) continue;
+    int ix, iy, iz;
+    double tx, ty, tz;
+    cic_axis(s->x[i], s->p.R0, s->idx, s->p.nx, &ix, &tx);
+    cic_axis(s->y[i], s->p.R0, s->idy, s->p.ny, &iy, &ty);
+    cic_axis(s->z[i], s->hL, s->idz, s->p.nz, &iz, &tz);
+    double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
+    for (int dz = 0; dz < 2; dz++)
+      for (int dy = 0; dy < 2; dy++)
+        for (int dx = 0; dx < 2; dx++) {
+          int64_t node = (int64_t)(ix + dx) + (int64_t)s->nx1 * ((iy + dy) + (int64_t)s->ny1 * (iz + dz));
+          double w = (wx[dx] * wy[dy]) * wz[dz];
+          if (ion) {
+            if (dm & 1u) s->dens[ORC_F_ION_N][node] += w;
+            if (dm & 2u) s->dens[ORC_F_ION_Q][node] += (double)Q * w;
+          } else {
+            s->dens[ORC_F_ATOM_N][node] += w;
+          }
+        }
+  }
+  s->dens_steps++;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step: sort (every sort_every steps) -> Coulomb -> per particle push,  */
+/* boundary, and (without a boundary event) MCC -> deposit.                  */
+/* ------------------------------------------------------------------------ */
+int orc_step(orc_sim *s, int64_t n_steps) {
+  uint32_t pm = s->p.process_mask;
+  for (int64_t it = 0; it < n_steps; it++) {
+    if (s->need_sort || s->step % s->p.sort_every == 0) {
+      sort_particles(s);
+      s->need_sort = 0;
+    }
+    if (pm & ORC_P_COULOMB) coulomb(s);
+    for (int64_t i = 0; i < s->N; i++) {
+      int ev = ORC_EV_NONE;
+      if (pm & ORC_P_PUSH) {
+        double x0 = s->x[i], y0 = s->y[i], z0 = s->z[i];
+        double E[3];
+        if (s->p.efield) gather_E(s, x0, y0, z0, E);
+        boris(s, s->qmh[s->sp[i]][s->q[i]], s->p.efield ? E : NULL, &s->x[i], &s->y[i], &s->z[i],
+              &s->vx[i], &s->vy[i], &s->vz[i]);
+        ev = boundary(s, i, x0, y0, z0);
+      }
+      if (ev == ORC_EV_NONE && (pm & (ORC_P_IONIZE | ORC_P_CX))) ev = mcc(s, i);
+      s->ev[i] = (uint8_t)ev;
+      if (!(isfinite(s->x[i]) && isfinite(s->y[i]) && isfinite(s->z[i]) && isfinite(s->vx[i]) &&
+            isfinite(s->vy[i]) && isfinite(s->vz[i])))
+        s->t.anomalies++;
+    }
+    if (pm & ORC_P_DEPOSIT) deposit(s);
+    s->step++;
+    s->t.steps++;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* State and accumulator access                                              */
+/* ------------------------------------------------------------------------ */
+int orc_set_state(orc_sim *s, int64_t step, const double *x, const double *y, const double *z,
+                  const double *vx, const double *vy, const double *vz, const uint8_t *q,
+                  const uint32_t *cell) {
+  for (int64_t i = 0; i < s->N; i++) {
+    if (q[i] > s->p.sp[s->sp[i]].z_max) return -1;
+    if (cell && cell[i] >= (uint32_t)s->ncell) return -1;
+  }
+  for (int64_t i = 0; i < s->N; i++) {
+    s->x[i] = x[i]; s->y[i] = y[i]; s->z[i] = z[i];
+    s->vx[i] = vx[i]; s->vy[i] = vy[i]; s->vz[i] = vz[i];
+    s->q[i] = q[i];
+    s->ev[i] = ORC_EV_NONE;
+  }
+  s->step = step;
+  if (cell) {
+    memcpy(s->cell, cell, (size_t)s->N * 4);
+    sort_from_cells(s);
+    s->need_sort = 0;
+  } else {
+    s->need_sort = 1;
+  }
+  zero_accumulators(s);
+  return 0;
+}
+
+int orc_get_state(const orc_sim *s, int64_t *step, double *x, double *y, double *z, double *vx,
+                  double *vy, double *vz, uint8_t *q, uint8_t *species, uint32_t *cell) {
+  size_t n8 = (size_t)s->N * 8;
+  if (step) *step = s->step;
+  if (x) memcpy(x, s->x, n8);
+  if (y) memcpy(y, s->y, n8);
+  if (z) memcpy(z, s->z, n8);
+  if (vx) memcpy(vx, s->vx, n8);
+  if (vy) memcpy(vy, s->vy, n8);
+  if (vz) memcpy(vz, s->vz, n8);
+  if (q) memcpy(q, s->q, (size_t)s->N);
+  if (species) memcpy(species, s->sp, (size_t)s->N);
+  if (cell) memcpy(cell, s->cell, (size_t)s->N * 4);
+  return 0;
+}
+
+int orc_get_tallies(const orc_sim *s, orc_tallies *t) {
+  *t = s->t;
+  return 0;
+}
+
+int orc_get_density(const orc_sim *s, int field, double *out, int64_t *steps) {
+  if (field < 0 || field > 2) return -1;
+  memcpy(out, s->dens[field], (size_t)s->nnode * 8);
+  if (steps) *steps = s->dens_steps;
+  return 0;
+}
+
+int orc_get_events(const orc_sim *s, uint8_t *out) {
+  memcpy(out, s->ev, (size_t)s->N);
+  return 0;
+}

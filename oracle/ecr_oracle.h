@@ -1,0 +1,118 @@
+/*
+ * ecr_oracle.h -- plain FP64 CPU oracle of the ion PIC/MCC step of the ECRIS
+ * model (Mironov et al., "Numerical model of Electron Cyclotron Resonance Ion
+ * Source", Sec. II).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against a slow, obviously correct implementation.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant generator with the GPU library.
+ *
+ * Units are SI throughout (m, s, kg, T, m^-3, m^3/s, m^2); temperatures and
+ * energies carry an _eV suffix.  Particle arrays are indexed by particle id.
+ */
+#ifndef ECR_ORACLE_H
+#define ECR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAXS 4   /* species */
+#define ORC_MAXQ 32  /* charge-state slots per species, Q = 0..31 */
+
+/* process switches */
+#define ORC_P_PUSH 1u      /* Boris push + wall/aperture boundary */
+#define ORC_P_IONIZE 2u    /* electron-impact ionisation Q -> Q+1 */
+#define ORC_P_CX 4u        /* charge exchange with background neutrals */
+#define ORC_P_COULOMB 8u   /* ion-ion Coulomb scattering (TA pairing, Nanbu angle) */
+#define ORC_P_DEPOSIT 16u  /* cloud-in-cell density deposit */
+
+/* deposit fields */
+#define ORC_F_ION_N 0  /* sum of CIC weights of ions (Q >= 1) */
+#define ORC_F_ION_Q 1  /* sum of Q * CIC weight of ions */
+#define ORC_F_ATOM_N 2 /* sum of CIC weights of atoms (Q = 0) */
+
+/* per-particle event codes of the last step */
+#define ORC_EV_NONE 0
+#define ORC_EV_IONIZE 1
+#define ORC_EV_CX 2
+#define ORC_EV_WALL 3
+#define ORC_EV_EXTRACT 4
+
+typedef struct {
+  double mass_amu;
+  int32_t z_max;              /* highest charge state (<= 31) */
+  uint32_t cx_forbidden_mask; /* bit Q set: no charge exchange from Q */
+  double fraction;            /* share of the particles, assigned in id order */
+  double k_in[ORC_MAXQ];      /* ionisation rate Q->Q+1 inside the zone, m^3/s */
+  double k_out[ORC_MAXQ];     /* same, outside the zone */
+  double sigma_cx1;           /* charge-exchange cross-section of Q=1, m^2 */
+  double n0;                  /* background neutral density, m^-3 */
+} orc_species;
+
+typedef struct {
+  uint64_t seed;
+  int64_t n;                  /* number of macro-particles */
+  double dt;
+  int32_t sort_every;
+  uint32_t process_mask;
+  uint32_t deposit_mask;      /* bit f: deposit field f */
+  int32_t nx, ny, nz;
+  double R0, L, r_ap, inlet_x, inlet_y;
+  double B0, mirror_k, BH;
+  double zone_a, zone_c, ne_in, ne_out;
+  double Ti0_eV, T_wall_eV, T_n_eV, dE_cx_eV, lnL, weight;
+  const double *efield;       /* [3][(nx+1)(ny+1)(nz+1)] node field, V/m, or NULL */
+  int32_t n_species;
+  orc_species sp[ORC_MAXS];
+} orc_params;
+
+typedef struct {
+  uint64_t extracted[ORC_MAXS][ORC_MAXQ];
+  uint64_t wall[ORC_MAXS][ORC_MAXQ];
+  uint64_t ionized[ORC_MAXS][ORC_MAXQ];
+  uint64_t cx[ORC_MAXS][ORC_MAXQ];
+  uint64_t cx_products[ORC_MAXS];
+  uint64_t recycled;
+  uint64_t anomalies;
+  int64_t steps;
+  double coul_dp[3];  /* total momentum change from Coulomb collisions, kg m/s */
+  double coul_de;     /* total kinetic-energy change, J */
+  double coul_e;      /* total kinetic energy of the collision pools before, J */
+} orc_tallies;
+
+typedef struct orc_sim orc_sim;
+
+int orc_create(const orc_params *p, orc_sim **out);
+void orc_destroy(orc_sim *s);
+int orc_init_ions(orc_sim *s);
+int orc_step(orc_sim *s, int64_t n_steps);
+/* arrays indexed by particle id; cell may be NULL (then the next step sorts) */
+int orc_set_state(orc_sim *s, int64_t step, const double *x, const double *y, const double *z,
+                  const double *vx, const double *vy, const double *vz, const uint8_t *q,
+                  const uint32_t *cell);
+int orc_get_state(const orc_sim *s, int64_t *step, double *x, double *y, double *z, double *vx,
+                  double *vy, double *vz, uint8_t *q, uint8_t *species, uint32_t *cell);
+int orc_get_tallies(const orc_sim *s, orc_tallies *t);
+int orc_get_density(const orc_sim *s, int field, double *out, int64_t *steps);
+int orc_get_events(const orc_sim *s, uint8_t *out);
+double orc_weight(const orc_sim *s);
+
+/* unit entry points used by the pin tests */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double orc_u53(uint32_t a, uint32_t b);
+void orc_field(const orc_sim *s, double x, double y, double z, double B[3]);
+void orc_boris(const orc_sim *s, int species, int q, const double E[3], double x[3], double v[3]);
+double orc_nanbu_A(const orc_sim *s, double sv);
+double orc_nanbu_A_root(double sv);
+double orc_nanbu_omc(const orc_sim *s, double sv, double u);
+int orc_segment_exit(const orc_sim *s, const double x0[3], const double x1[3], double *f);
+uint32_t orc_cell_of(const orc_sim *s, double x, double y, double z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

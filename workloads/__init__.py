@@ -1,0 +1,136 @@
+"""Synthetic ECRIS-shaped workloads and seeded input generators.
+
+This module is the only code shared by the GPU library's tests/benchmark and
+the CPU oracle's tests.  It holds parameter presets and seeded random inputs
+and none of the method's arithmetic: every derived constant (ionisation
+probabilities, Boris factors, collision constants) is computed by each side
+from these raw inputs on its own.
+
+Units are SI: metres, seconds, tesla, m^-3, m^3/s, m^2; temperatures and
+energies in eV.  The paper's own inputs (Superfish field maps, rate and
+cross-section datasets) are not available, so the presets below are
+synthetic stand-ins of the same shape (Sec. II of the paper and Table I):
+an analytic minimum-B field, a fixed electron background in an ellipsoidal
+ECR zone, argon (and oxygen) ions born Q=1.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# process switches (same bit meaning on both sides of the boundary)
+P_PUSH = 1
+P_IONIZE = 2
+P_CX = 4
+P_COULOMB = 8
+P_DEPOSIT = 16
+P_ALL = P_PUSH | P_IONIZE | P_CX | P_COULOMB | P_DEPOSIT
+
+F_ION_N, F_ION_Q, F_ATOM_N = 0, 1, 2
+
+EV_NONE, EV_IONIZE, EV_CX, EV_WALL, EV_EXTRACT = 0, 1, 2, 3, 4
+
+PREC_FP64, PREC_FP32 = 0, 1
+
+# Ionisation potentials in eV of Ar^Q+ and O^Q+ (NIST atomic spectra database,
+# ground states).  Used only to shape the synthetic rate table below.
+AR_IP_EV = [15.760, 27.630, 40.735, 59.58, 74.84, 91.29, 124.41, 143.457, 422.60,
+            479.76, 540.4, 619.0, 685.5, 755.13, 855.5, 918.375, 4120.666, 4426.224]
+O_IP_EV = [13.618, 35.121, 54.936, 77.414, 113.899, 138.120, 739.293, 871.410]
+
+K0_CM3S = 1.0e-7  # Ar0 -> Ar1+ rate at keV electron temperature quoted in Sec. III.B
+
+
+def synthetic_rates(ip_ev, k0_cm3s=K0_CM3S, exponent=1.5):
+    """Synthetic single-ionisation rate table in m^3/s, one entry per Q.
+
+    The paper's rates come from datasets that are not available here.  This
+    stand-in is anchored at k(Q=0) = k0 and falls with the ionisation
+    potential as (I_0/I_Q)^1.5; the entry at Q = z_max is 0.  It is a stated
+    synthetic input, not physics data.
+    """
+    z_max = len(ip_ev)
+    k = [0.0] * 32
+    for q in range(z_max):
+        k[q] = k0_cm3s * 1e-6 * (ip_ev[0] / ip_ev[q]) ** exponent
+    return k
+
+
+SIGMA_CX1_M2 = 5.0e-19  # synthetic Ar+ + Ar charge-exchange cross-section (5e-15 cm^2)
+
+
+def argon(fraction=1.0, n0_m3=1.0e17, sigma_cx1_m2=SIGMA_CX1_M2, outside_rates=False):
+    k = synthetic_rates(AR_IP_EV)
+    return dict(mass_amu=39.948, z_max=18, cx_forbidden_mask=1 << 2, fraction=fraction,
+                k_in=k, k_out=(list(k) if outside_rates else [0.0] * 32),
+                sigma_cx1=sigma_cx1_m2, n0=n0_m3)
+
+
+def oxygen(fraction=1.0, n0_m3=1.0e17, sigma_cx1_m2=SIGMA_CX1_M2, outside_rates=False):
+    k = synthetic_rates(O_IP_EV, k0_cm3s=K0_CM3S * (O_IP_EV[0] / AR_IP_EV[0]) ** -1.5)
+    return dict(mass_amu=15.999, z_max=8, cx_forbidden_mask=0, fraction=fraction,
+                k_in=k, k_out=(list(k) if outside_rates else [0.0] * 32),
+                sigma_cx1=sigma_cx1_m2, n0=n0_m3)
+
+
+def base_params(n, nx, ny, nz, seed=0, precision=PREC_FP64):
+    """Shared geometry and plasma of every preset (a KVI-AECRIS-sized source)."""
+    R0 = 0.035
+    return dict(
+        precision=precision, process_mask=P_ALL, deposit_mask=(1 << F_ION_N) | (1 << F_ION_Q),
+        seed=seed, n=n, dt=1.0e-9, sort_every=50, nx=nx, ny=ny, nz=nz,
+        R0=R0, L=0.30, r_ap=0.01, inlet_x=R0 / 2, inlet_y=0.0,
+        B0=0.5, mirror_k=3.0, BH=1.0,
+        zone_a=0.015, zone_c=0.05, ne_in=1.0e18, ne_out=0.0, Te_in_eV=1000.0, Te_out_eV=5.0,
+        Ti0_eV=0.5, T_wall_eV=0.025, T_n_eV=0.025, dE_cx_eV=10.0, lnL=10.0, weight=0.0,
+        efield=None, species=[argon()])
+
+
+def config(name):
+    """Named workloads.  Returns (params, steps)."""
+    name = name.lower()
+    if name == "c1":   # 20k Ar ions, FP64, grid 32x32x64, 1000 steps
+        return base_params(20_000, 32, 32, 64), 1000
+    if name == "c2":   # 2M Ar ions, FP64, grid 64x64x128, 10k steps, sort every 50
+        return base_params(2_000_000, 64, 64, 128), 10_000
+    if name == "c3":   # c1 in FP32 push with FP64 accumulators, 10k steps
+        return base_params(20_000, 32, 32, 64, precision=PREC_FP32), 10_000
+    if name == "c4":   # 10M two-species (70% O, 30% Ar), n0 = 3e11 cm^-3 split 70/30
+        p = base_params(10_000_000, 128, 128, 256, precision=PREC_FP32)
+        p["species"] = [oxygen(0.7, n0_m3=0.7 * 3e17), argon(0.3, n0_m3=0.3 * 3e17)]
+        return p, 5000
+    raise KeyError(name)
+
+
+def with_(params, **kw):
+    q = copy.deepcopy(params)
+    q.update(kw)
+    return q
+
+
+def random_state(params, seed, q_max=None, frac_atoms=0.1, v_ev=0.5, radius_frac=0.95, mass_amu=39.948):
+    """Seeded synthetic particle state, indexed by particle id.
+
+    Positions uniform in the cylinder r < radius_frac R0, |z| < radius_frac L/2;
+    velocities Maxwellian with sigma = sqrt(v_ev e / m) for a mass of mass_amu;
+    charge states uniform in [1, q_max] (default: the smallest z_max of the
+    species), then a fraction frac_atoms set to Q = 0.
+    """
+    rng = np.random.default_rng(seed)
+    n = params["n"]
+    R0, L = params["R0"], params["L"]
+    r = radius_frac * R0 * np.sqrt(rng.random(n))
+    th = 2 * np.pi * rng.random(n)
+    x = r * np.cos(th)
+    y = r * np.sin(th)
+    z = (rng.random(n) * 2 - 1) * radius_frac * L / 2
+    sig = math.sqrt(v_ev * 1.602176634e-19 / (mass_amu * 1.66053906660e-27))
+    vx = rng.normal(size=n) * sig
+    vy = rng.normal(size=n) * sig
+    vz = rng.normal(size=n) * sig
+    qm = min(s["z_max"] for s in params["species"]) if q_max is None else q_max
+    q = (1 + np.floor(rng.random(n) * qm)).astype(np.uint8)
+    q[rng.random(n) < frac_atoms] = 0
+    return dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, q=q)
