@@ -1,0 +1,156 @@
+"""Benchmark of the ion PIC/MCC step on one MI355X.
+
+Workload: 2M argon ions in FP64 on the 64x64x128 mesh (sort every 50 steps,
+dt = 1e-9 s, synthetic ECRIS-shaped inputs).  A step is one pass of the whole
+path: sort (every 50th step), Coulomb collisions, push + wall/aperture loss +
+ionisation/charge exchange, and the density deposit.  The ions are created
+on the GPU before the timed region.
+
+Prints one JSON line: throughput in particle-steps/s, the roofline of the
+dominant kernel (algorithmic bytes per launch / its mean launch time, timed
+with HIP events on the run's stream), and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic HBM bytes per particle per launch (FP64 structure of arrays:
+# x y z vx vy vz 8 B each, qs 1 B, pid 4 B, collision cell 4 B)
+ALG_BYTES_FP64 = {
+    # read x, v, qs, pid; write x, v, qs
+    "push": 48 + 1 + 4 + 48 + 1,
+    # read qs, pid, cell; read and write v (every slot counted)
+    "coulomb": 1 + 4 + 4 + 48 + 48,
+    # read x, qs
+    "deposit": 24 + 1,
+    # count pass (read x; write key, rank) + scatter (read record, key, rank; write record, cell)
+    "sort": (24 + 8) + (53 + 8) + (53 + 4),
+    "fused": 48 + 1 + 4 + 4 + 48 + 1,
+}
+ALG_BYTES_FP32 = {
+    "push": 24 + 1 + 4 + 24 + 1,
+    "coulomb": 1 + 4 + 4 + 24 + 24,
+    "deposit": 12 + 1,
+    "sort": (12 + 8) + (29 + 8) + (29 + 4),
+    "fused": 24 + 1 + 4 + 4 + 24 + 1,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(params, steps):
+    from oracle.binding import OracleSim
+    o = OracleSim(params)
+    o.init_ions()
+    o.step(1)  # includes the first sort
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=params["n"] * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{params['n']} ions, {params['nx']}x{params['ny']}x{params['nz']} mesh, steps 1..{steps} "
+                       f"after init (one sort), single-threaded FP64 C oracle, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--prof-steps", type=int, default=500)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the ion step is not "
+              "sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1507_03392_amd as ecr
+    import workloads as W
+
+    params, _ = W.config(args.workload)
+    n = params["n"]
+    fp32 = params.get("precision", 0) == ecr.FP32_MIXED
+    log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")
+    run = ecr.Run(params)
+    run.init_ions()
+    run.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"bench: warmup {args.warmup} steps done")
+    t0 = time.perf_counter()
+    run.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = n * args.steps / elapsed
+    log(f"bench: timed {args.steps} steps in {elapsed:.3f} s ({value:.3e} particle-steps/s)")
+    tal = run.tallies()
+
+    # per-kernel launch times (HIP events around every launch on the run's stream)
+    run.profile(True)
+    run.step(args.prof_steps)
+    kt = run.kernel_times()
+    run.profile(False)
+    per = {k: (ms / c if c else 0.0, c) for k, (ms, c) in kt.items()}
+    tot = {k: ms for k, (ms, c) in kt.items()}
+    dom = max(tot, key=lambda k: tot[k])
+    alg = (ALG_BYTES_FP32 if fp32 else ALG_BYTES_FP64)[dom] * n
+    avg_s = per[dom][0] * 1e-3
+    achieved = alg / avg_s / 1e9
+    kernels = {k: {"avg_us": round(per[k][0] * 1e3, 2), "launches": per[k][1],
+                   "share": round(tot[k] / max(1e-12, sum(tot.values())), 3)} for k in tot if per[k][1]}
+    log(f"bench: kernels {json.dumps(kernels)}")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"bench: CPU oracle sample, {args.cpu_steps} steps of the same workload")
+        cpu = cpu_baseline(params, args.cpu_steps)
+
+    out = {
+        "metric": "ion particle-steps/s (push+MCC+deposit) at 2M ions",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if fp32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n} Ar ions born Q=1 in the ECR-zone ellipsoid, "
+                               f"{'FP32-mixed' if fp32 else 'FP64'}, mesh {params['nx']}x{params['ny']}x{params['nz']}, "
+                               f"dt 1e-9 s, sort every {params['sort_every']}, all processes on",
+                   "n_particles": n, "mesh": [params["nx"], params["ny"], params["nz"]],
+                   "sort_every": params["sort_every"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6},
+        "kernels": kernels,
+        "tallies": {"ionized": int(tal["ionized"].sum()), "wall": int(tal["wall"].sum()),
+                    "extracted": int(tal["extracted"].sum()), "cx": int(tal["cx"].sum()),
+                    "anomalies": tal["anomalies"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * ecrpic.h -- C ABI of the MI355X (gfx950) ion PIC/MCC step of the ECRIS
+ * model of Mironov et al., "Numerical model of Electron Cyclotron Resonance
+ * Ion Source", Sec. II.
+ *
+ * The paper states the problem as: for a given magnetic configuration and
+ * chamber (Sec. II, Table I), macro-particle ions and atoms are moved in the
+ * field, collide (ion-ion Coulomb scattering, electron-impact ionisation,
+ * charge exchange with atoms), are neutralised at the walls or leave through
+ * the extraction aperture and are recycled at the gas inlet; the outputs are
+ * the extracted charge-state distribution and gas flow (Sec. II, III.C) and
+ * the density distributions (Sec. III.B).  The calls below follow that
+ * statement: create a run, initialise its ions, advance N steps, read the
+ * extracted-ion tallies and the density grid.
+ *
+ * Conventions
+ *  - Every call returns ecr_status; 0 is success.  Nothing throws across the
+ *    boundary.  ECR_EINVAL means a bad argument and leaves the run unchanged.
+ *  - Units are SI (m, s, kg, T, m^-3, m^3/s, m^2, V/m); temperatures and
+ *    energies carry an _eV suffix.
+ *  - Device memory: the caller owns one device buffer (the arena) of at
+ *    least ecr_footprint() bytes and a HIP stream; the library carves the
+ *    arena and never allocates device memory itself.  Host buffers passed to
+ *    read/get/set calls belong to the caller and are only used during the
+ *    call.  ecr_destroy frees the host handle only.
+ *  - ecr_step and ecr_init_ions are asynchronous on the run's stream; the
+ *    read/get/set calls synchronise that stream.
+ *  - A handle is not thread-safe; distinct handles may be used concurrently
+ *    on distinct streams.
+ */
+#ifndef ECRPIC_H
+#define ECRPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ECR_ABI_VERSION 1u
+#define ECR_MAX_SPECIES 4
+#define ECR_MAX_Q 32 /* charge-state slots per species: Q = 0..31 */
+
+typedef enum {
+  ECR_OK = 0,
+  ECR_EINVAL = -1,   /* bad argument; nothing changed */
+  ECR_ENOMEM = -2,   /* arena smaller than ecr_footprint() */
+  ECR_EDEVICE = -3,  /* a HIP call failed; the run is now unusable except read/destroy */
+  ECR_ESTATE = -4,   /* call not valid in the run's state */
+  ECR_ENUMERIC = -5, /* anomalies counted (non-finite state, or per-step collision probability > 0.1) */
+  ECR_EDT = -6,      /* time step too large for first-order Monte-Carlo collisions */
+  ECR_EABI = -7      /* abi_version mismatch */
+} ecr_status;
+
+typedef enum { ECR_FP64 = 0, ECR_FP32_MIXED = 1 } ecr_precision;
+
+/* process switches (process_mask) */
+enum {
+  ECR_P_PUSH = 1,     /* Boris push in the magnetic (and optional electric) field + wall/aperture loss */
+  ECR_P_IONIZE = 2,   /* electron-impact ionisation Q -> Q+1 */
+  ECR_P_CX = 4,       /* charge exchange with the background neutral gas */
+  ECR_P_COULOMB = 8,  /* ion-ion Coulomb scattering: Takizuka-Abe pairing, Nanbu angle */
+  ECR_P_DEPOSIT = 16, /* cloud-in-cell density deposit */
+  ECR_P_ALL = 31
+};
+
+/* density fields (bit f of deposit_mask enables field f) */
+enum { ECR_F_ION_N = 0, ECR_F_ION_Q = 1, ECR_F_ATOM_N = 2, ECR_N_FIELDS = 3 };
+
+/* run flags */
+enum { ECR_FLAG_EVENTS = 1 /* record each particle's event code of the last step */ };
+
+/* event codes returned by ecr_event_log */
+enum { ECR_EV_NONE = 0, ECR_EV_IONIZE = 1, ECR_EV_CX = 2, ECR_EV_WALL = 3, ECR_EV_EXTRACT = 4 };
+
+/* One ion species (the paper models argon, Sec. II; a second species is allowed). */
+typedef struct {
+  double mass_amu;
+  int32_t z_max;                      /* highest charge state, <= 31 */
+  uint32_t cx_forbidden_mask;         /* bit Q set: no charge exchange from Q (argon: Q = 2) */
+  double fraction;                    /* share of particles; ids are assigned in order */
+  double k_ion_in_m3s[ECR_MAX_Q];     /* ionisation rate Q -> Q+1 inside the ECR zone */
+  double k_ion_out_m3s[ECR_MAX_Q];    /* same, outside the zone */
+  double sigma_cx1_m2;                /* charge-exchange cross-section of Q = 1; Q scales it linearly */
+  double n0_m3;                       /* background neutral density (charge-exchange target) */
+} ecr_species;
+
+typedef struct {
+  uint32_t abi_version;               /* ECR_ABI_VERSION */
+  int32_t precision;                  /* ecr_precision */
+  uint32_t process_mask;              /* ECR_P_* */
+  uint32_t deposit_mask;              /* bits of ECR_F_* */
+  uint32_t flags;                     /* ECR_FLAG_* */
+  int32_t sort_every;                 /* steps between sorts by cell (>= 1) */
+  uint64_t seed;                      /* Philox key */
+  int64_t n_particles;                /* 0 .. 2^31-1 */
+  double dt_s;
+  int32_t nx, ny, nz;                 /* cells of the mesh over [-R0,R0]^2 x [-L/2,L/2] */
+  int32_t n_species;                  /* 1 .. ECR_MAX_SPECIES */
+  double R0_m, L_m;                   /* chamber radius and length; extraction flange at z = +L/2 */
+  double r_ap_m;                      /* extraction aperture radius */
+  double inlet_x_m, inlet_y_m;        /* gas inlet on the injection flange z = -L/2 */
+  double B0_T, mirror_k, BH_T;        /* on-axis Bz = B0 (1 + k (2z/L)^2); hexapole BH at r = R0 */
+  double zone_a_m, zone_c_m;          /* ECR zone: ellipsoid x^2/a^2 + y^2/a^2 + z^2/c^2 < 1 */
+  double ne_in_m3, ne_out_m3;         /* electron density inside / outside the zone */
+  double Ti0_eV;                      /* initial ion temperature */
+  double T_wall_eV;                   /* wall re-emission temperature */
+  double T_n_eV;                      /* neutral gas temperature (charge-exchange partners) */
+  double dE_cx_eV;                    /* energy release of multiply-charged charge exchange */
+  double lnL_ii;                      /* ion-ion Coulomb logarithm */
+  double weight;                      /* real ions per macro-particle; 0: n_e,in V_zone / N */
+  const double *efield_nodes;         /* host, [3][(nx+1)(ny+1)(nz+1)] V/m node field, or NULL (E = 0) */
+  ecr_species species[ECR_MAX_SPECIES];
+} ecr_params;
+
+typedef struct {
+  uint64_t extracted[ECR_MAX_SPECIES][ECR_MAX_Q]; /* left through the aperture, by charge at exit */
+  uint64_t wall[ECR_MAX_SPECIES][ECR_MAX_Q];      /* neutralised at a wall, by charge at impact */
+  uint64_t ionized[ECR_MAX_SPECIES][ECR_MAX_Q];   /* ionisation events, by charge before */
+  uint64_t cx[ECR_MAX_SPECIES][ECR_MAX_Q];        /* charge-exchange events, by charge before */
+  uint64_t cx_products[ECR_MAX_SPECIES];          /* untracked singly-charged products of Q >= 3 exchange */
+  uint64_t recycled;                              /* particles returned at the gas inlet */
+  uint64_t anomalies;
+  int64_t steps;                                  /* steps since init_ions / set_state */
+  double coul_dp[3];                              /* total momentum change in Coulomb collisions, kg m/s */
+  double coul_de;                                 /* total kinetic-energy change in Coulomb collisions, J */
+  double coul_e;                                  /* kinetic energy of the collision pools before, J */
+} ecr_tallies;
+
+/* Host particle arrays indexed by particle id (length n). */
+typedef struct {
+  double *x, *y, *z, *vx, *vy, *vz;
+  uint8_t *q;        /* charge state */
+  uint8_t *species;  /* get only (ignored by set: species follow the id order) */
+  uint32_t *cell;    /* collision cell (cell of the last sort); set: may be NULL -> sorted at the next step */
+  int64_t n;
+  int64_t step;      /* step counter (Philox counter word 1) */
+} ecr_state_view;
+
+typedef struct ecr_run ecr_run;
+
+/* Device bytes a run with these parameters needs.  ECR_EINVAL on bad params. */
+ecr_status ecr_footprint(const ecr_params *params, size_t *device_bytes);
+
+/* Create a run in a caller-owned device arena, bound to a caller-owned HIP
+ * stream (NULL: the null stream).  Copies params (and the E-field nodes, if
+ * given) and uploads the derived tables.  ECR_EDT if the per-step ionisation
+ * plus charge-exchange probability can exceed 0.1. */
+ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena_bytes,
+                      void *hip_stream, ecr_run **out);
+
+/* Initial ions: uniform in the ECR-zone ellipsoid, Maxwellian at Ti0, Q = 1
+ * (Sec. II); zeroes tallies and density; step counter 0. */
+ecr_status ecr_init_ions(ecr_run *run);
+
+/* Advance n_steps steps (sort every sort_every steps, then Coulomb, push,
+ * wall/aperture, ionisation/charge exchange, deposit).  Asynchronous. */
+ecr_status ecr_step(ecr_run *run, int64_t n_steps);
+
+/* Advance several independent runs that share one stream by n_steps each. */
+ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps, void *hip_stream);
+
+/* Tallies since the last init/set_state.  Synchronises.  ECR_ENUMERIC (with
+ * the tallies filled in) when anomalies > 0. */
+ecr_status ecr_read_tallies(ecr_run *run, ecr_tallies *host_out);
+
+/* Time-integrated CIC deposit of one field: (nx+1)(ny+1)(nz+1) doubles in
+ * x-fastest node order, plus the number of deposited steps.  Synchronises. */
+ecr_status ecr_read_density(ecr_run *run, uint32_t field, double *host_out, int64_t *steps_accum);
+
+/* Particle state by id (checkpoint and parity).  Synchronises. */
+ecr_status ecr_get_state(ecr_run *run, ecr_state_view *host_out);
+
+/* Replace the particle state (by id), set the step counter, zero tallies and
+ * density.  ECR_EINVAL if a charge state exceeds its species' z_max or a cell
+ * is out of range.  Synchronises. */
+ecr_status ecr_set_state(ecr_run *run, const ecr_state_view *host_in);
+
+/* Event codes (ECR_EV_*) of the last step, by particle id; needs
+ * ECR_FLAG_EVENTS (else ECR_ESTATE).  Synchronises. */
+ecr_status ecr_event_log(ecr_run *run, uint8_t *host_out);
+
+/* Macro-particle weight in use (real ions per macro-particle). */
+ecr_status ecr_weight(const ecr_run *run, double *weight);
+
+/* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
+ * the run's stream; ecr_kernel_times returns, per kernel kind (ECR_K_*), the
+ * summed milliseconds and the launch count since the last reset. */
+enum { ECR_K_SORT = 0, ECR_K_COULOMB = 1, ECR_K_PUSH = 2, ECR_K_DEPOSIT = 3, ECR_K_FUSED = 4, ECR_N_KERNELS = 5 };
+ecr_status ecr_profile(ecr_run *run, int32_t enable);
+ecr_status ecr_kernel_times(ecr_run *run, double *ms_out, int64_t *launches_out);
+
+/* Message of the last error on this run (NULL run: of the calling thread). */
+const char *ecr_last_error(const ecr_run *run);
+
+ecr_status ecr_destroy(ecr_run *run);
+
+/* Self-test entry points (device buffers, run on the given stream):
+ * Philox4x32-10 of counters (c0 = i + ctr0, c1, c2, c3) for i < n with key
+ * (seed lo, seed hi) into out[4*i..4*i+3]; and the binary64 quotient and
+ * square root a[i]/b[i], sqrt(a[i]) into q[i], r[i]. */
+ecr_status ecr_selftest_philox(uint64_t seed, uint32_t ctr0, uint32_t c1, uint32_t c2, uint32_t c3,
+                               int64_t n, uint32_t *out_dev, void *hip_stream);
+ecr_status ecr_selftest_divsqrt(const double *a_dev, const double *b_dev, int64_t n, double *q_dev,
+                                double *r_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -78,6 +78,9 @@ def lib():
         L.orc_segment_exit.restype = C.c_int
         L.orc_cell_of.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.orc_cell_of.restype = C.c_uint32
+        L.orc_set_ids.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_philox_fill.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64,
+                                      C.c_void_p]
         _lib = L
     return _lib
 
@@ -140,6 +143,12 @@ class OracleSim:
 
     def init_ions(self):
         lib().orc_init_ions(self.h)
+
+    def set_ids(self, ids, species):
+        a = np.ascontiguousarray(ids, dtype=np.uint32)
+        b = np.ascontiguousarray(species, dtype=np.uint8)
+        if lib().orc_set_ids(self.h, _ptr(a), _ptr(b)) != 0:
+            raise ValueError("bad species")
 
     def step(self, n=1):
         lib().orc_step(self.h, n)
@@ -239,6 +248,12 @@ def philox4x64(ctr, key):
 
 def u53(a, b):
     return lib().orc_u53(a, b)
+
+
+def philox_fill(seed, ctr0, c1, c2, c3, n):
+    out = np.empty(4 * n, dtype=np.uint32)
+    lib().orc_philox_fill(seed, ctr0, c1, c2, c3, n, _ptr(out))
+    return out.reshape(n, 4)
 
 
 def tallies_to_dict(t):

@@ -58,7 +58,9 @@ struct orc_sim {
   int nx1, ny1, nz1;
   int64_t ncell, nnode;
   double atab[A_NODES]; /* ln A at the nodes */
-  /* particle state, indexed by id */
+  /* particle state, indexed by position i; id[i] is the particle's id (its
+   * Philox counter word and pairing tie-break), i unless set by orc_set_ids */
+  uint32_t *id;
   double *x, *y, *z, *vx, *vy, *vz;
   uint8_t *q, *sp, *ev;
   uint32_t *cell;
@@ -393,17 +395,20 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->x = calloc(nd, 8); s->y = calloc(nd, 8); s->z = calloc(nd, 8);
   s->vx = calloc(nd, 8); s->vy = calloc(nd, 8); s->vz = calloc(nd, 8);
   s->q = calloc(nd, 1); s->sp = calloc(nd, 1); s->ev = calloc(nd, 1);
-  s->cell = calloc(nd, 4); s->order = calloc(nd, 4);
+  s->cell = calloc(nd, 4); s->order = calloc(nd, 4); s->id = calloc(nd, 4);
   s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4);
   s->cell_off = calloc((size_t)s->ncell + 1, 4);
   for (int f = 0; f < 3; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
-      !s->cell || !s->order || !s->pool || !s->pkey || !s->cell_off || !s->dens[0] ||
+      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->cell_off || !s->dens[0] ||
       !s->dens[1] || !s->dens[2]) {
     orc_destroy(s);
     return -2;
   }
-  for (int64_t i = 0; i < N; i++) s->sp[i] = (uint8_t)species_of(s, i);
+  for (int64_t i = 0; i < N; i++) {
+    s->sp[i] = (uint8_t)species_of(s, i);
+    s->id[i] = (uint32_t)i;
+  }
   s->need_sort = 1;
   *out = s;
   return 0;
@@ -412,7 +417,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
 void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
-  free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order);
+  free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order); free(s->id);
   free(s->pool); free(s->pkey); free(s->cell_off);
   for (int f = 0; f < 3; f++) free(s->dens[f]);
   free(s);
@@ -433,7 +438,7 @@ static void zero_accumulators(orc_sim *s) {
 int orc_init_ions(orc_sim *s) {
   double a = s->p.zone_a, c = s->p.zone_c;
   for (int64_t i = 0; i < s->N; i++) {
-    uint32_t id = (uint32_t)i;
+    uint32_t id = s->id[i];
     double px = 0.0, py = 0.0, pz = 0.0;
     for (uint32_t j = 0; j < 64; j++) {
       uint32_t A[4], B[4];
@@ -492,17 +497,18 @@ static void sort_particles(orc_sim *s) {
 /* each, in that order, then (3,4),...  The pool density is m w / V_cell.    */
 /* Nanbu: s = lnL e^4 (Qa Qb)^2 n dt / (4 pi eps0^2 mu^2 g^3).               */
 /* ------------------------------------------------------------------------ */
-static uint32_t *g_sort_key; /* qsort comparator context (single-threaded oracle) */
+static uint32_t *g_sort_key, *g_sort_id; /* qsort comparator context (single-threaded oracle) */
 static int cmp_pool(const void *a, const void *b) {
   uint32_t ia = *(const uint32_t *)a, ib = *(const uint32_t *)b;
   uint32_t ka = g_sort_key[ia], kb = g_sort_key[ib];
   if (ka != kb) return ka < kb ? -1 : 1;
-  return ia < ib ? -1 : (ia > ib ? 1 : 0);
+  uint32_t da = g_sort_id[ia], db = g_sort_id[ib];
+  return da < db ? -1 : (da > db ? 1 : 0);
 }
 
 static void coulomb_pair(orc_sim *s, uint32_t ia, uint32_t ib, double nc, double dtp) {
   uint32_t W[4];
-  draw(s, ia, (uint32_t)s->step, S_COUL, 0, W);
+  draw(s, s->id[ia], (uint32_t)s->step, S_COUL, 0, W);
   double u = orc_u53(W[0], W[1]), u2 = orc_u53(W[2], W[3]);
   double ux = s->vx[ia] - s->vx[ib];
   double uy = s->vy[ia] - s->vy[ib];
@@ -556,10 +562,11 @@ static void coulomb(orc_sim *s) {
   /* per-particle pairing key of this step: word 2 of the STEP draw */
   for (int64_t i = 0; i < s->N; i++) {
     uint32_t W[4];
-    draw(s, (uint32_t)i, (uint32_t)s->step, S_STEP, 0, W);
+    draw(s, s->id[i], (uint32_t)s->step, S_STEP, 0, W);
     s->pkey[i] = W[2];
   }
   g_sort_key = s->pkey;
+  g_sort_id = s->id;
   for (int64_t c = 0; c < s->ncell; c++) {
     int64_t m = 0;
     for (uint32_t k = s->cell_off[c]; k < s->cell_off[c + 1]; k++) {
@@ -635,8 +642,8 @@ int orc_segment_exit(const orc_sim *s, const double x0[3], const double x1[3], d
 /* flux-Maxwellian re-emission about the inward normal n, tangents t1, t2 */
 static void reemit(orc_sim *s, int64_t i, const double n[3], const double t1[3], const double t2[3]) {
   uint32_t W[4], V[4];
-  draw(s, (uint32_t)i, (uint32_t)s->step, S_BND, 0, W);
-  draw(s, (uint32_t)i, (uint32_t)s->step, S_BND, 1, V);
+  draw(s, s->id[i], (uint32_t)s->step, S_BND, 0, W);
+  draw(s, s->id[i], (uint32_t)s->step, S_BND, 1, V);
   double sg = s->sig_w[s->sp[i]];
   double vn = sg * sqrt(-2.0 * log(1.0 - orc_u53(W[0], W[1])));
   double na, nb;
@@ -696,7 +703,7 @@ static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
 /* ------------------------------------------------------------------------ */
 static int mcc(orc_sim *s, int64_t i) {
   uint32_t W[4];
-  draw(s, (uint32_t)i, (uint32_t)s->step, S_STEP, 0, W);
+  draw(s, s->id[i], (uint32_t)s->step, S_STEP, 0, W);
   double u = orc_u53(W[0], W[1]);
   int sp = s->sp[i], Q = s->q[i];
   double x = s->x[i], y = s->y[i], z = s->z[i];
@@ -717,8 +724,8 @@ static int mcc(orc_sim *s, int64_t i) {
   if (u < pt) {
     s->t.cx[sp][Q]++;
     uint32_t G[4], H[4];
-    draw(s, (uint32_t)i, (uint32_t)s->step, S_CX, 0, G);
-    draw(s, (uint32_t)i, (uint32_t)s->step, S_CX, 1, H);
+    draw(s, s->id[i], (uint32_t)s->step, S_CX, 0, G);
+    draw(s, s->id[i], (uint32_t)s->step, S_CX, 1, H);
     double n0, n1, n2, ndis;
     box_muller(orc_u53(G[0], G[1]), orc_u53(G[2], G[3]), &n0, &n1);
     box_muller(orc_u53(H[0], H[1]), orc_u53(H[2], H[3]), &n2, &ndis);
@@ -728,7 +735,7 @@ static int mcc(orc_sim *s, int64_t i) {
       s->vx[i] = wx; s->vy[i] = wy; s->vz[i] = wz;
     } else {
       uint32_t I[4];
-      draw(s, (uint32_t)i, (uint32_t)s->step, S_CX, 2, I);
+      draw(s, s->id[i], (uint32_t)s->step, S_CX, 2, I);
       double ct = 1.0 - 2.0 * orc_u53(I[0], I[1]);
       double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
       double ph = 2.0 * PI * orc_u53(I[2], I[3]);
@@ -856,6 +863,28 @@ int orc_get_state(const orc_sim *s, int64_t *step, double *x, double *y, double 
   if (species) memcpy(species, s->sp, (size_t)s->N);
   if (cell) memcpy(cell, s->cell, (size_t)s->N * 4);
   return 0;
+}
+
+/* Give the particles explicit ids and species: lets a test step a subset of
+ * a larger run (whole collision cells) with the draws the full run makes. */
+int orc_set_ids(orc_sim *s, const uint32_t *ids, const uint8_t *species) {
+  for (int64_t i = 0; i < s->N; i++)
+    if (species[i] >= s->p.n_species) return -1;
+  for (int64_t i = 0; i < s->N; i++) {
+    s->id[i] = ids[i];
+    s->sp[i] = species[i];
+  }
+  return 0;
+}
+
+/* Philox4x32-10 of counters (ctr0 + i, c1, c2, c3), i < n, into out[4n] */
+void orc_philox_fill(uint64_t seed, uint32_t ctr0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                     uint32_t *out) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int64_t i = 0; i < n; i++) {
+    uint32_t ctr[4] = {ctr0 + (uint32_t)i, c1, c2, c3};
+    orc_philox4x32_10(ctr, key, out + 4 * i);
+  }
 }
 
 int orc_get_tallies(const orc_sim *s, orc_tallies *t) {

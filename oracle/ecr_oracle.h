@@ -99,6 +99,10 @@ int orc_get_tallies(const orc_sim *s, orc_tallies *t);
 int orc_get_density(const orc_sim *s, int field, double *out, int64_t *steps);
 int orc_get_events(const orc_sim *s, uint8_t *out);
 double orc_weight(const orc_sim *s);
+/* explicit particle ids (Philox counter word, pairing tie-break) and species */
+int orc_set_ids(orc_sim *s, const uint32_t *ids, const uint8_t *species);
+void orc_philox_fill(uint64_t seed, uint32_t ctr0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                     uint32_t *out);
 
 /* unit entry points used by the pin tests */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -1,0 +1,747 @@
+// runtime.hip -- host runtime behind the C ABI in ecrpic.h: parameter
+// checks, derived tables, arena layout, the step loop, read-back, profiling.
+//
+// Device memory layout (one caller-owned arena, every region 256-B aligned):
+//   SoA A and SoA B (double buffer for the sort): x y z vx vy vz (R each),
+//   qs (u8), pid (u32); key, rank, cellid (u32 per slot); count and cell_off
+//   (u32 per cell, +1); scan block sums; density grids (3 fields of FP64 per
+//   node); accumulators (tallies, FP64 Coulomb moments, error bits); tables
+//   (Boris factors, ionisation probabilities, Nanbu ln A); the optional node
+//   E field; the optional per-slot event log.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ecr_kernels.hpp"
+#include "ecrpic.h"
+
+using namespace ecr;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t soa[2][8];  // offsets of x y z vx vy vz qs pid in buffer A and B
+  size_t key, rank, cellid, count, cell_off, bsum, dens, acc, tables, efield, evlog;
+  size_t total;
+};
+
+int64_t ncells(const ecr_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
+int64_t nnodes(const ecr_params *p) { return (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1); }
+
+Layout make_layout(const ecr_params *p) {
+  Layout L{};
+  const size_t N = (size_t)(p->n_particles > 0 ? p->n_particles : 1);
+  const size_t rs = p->precision == ECR_FP32_MIXED ? 4 : 8;
+  size_t o = 0;
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 6; ++k) {
+      L.soa[b][k] = o;
+      o = align_up(o + rs * N);
+    }
+    L.soa[b][6] = o;
+    o = align_up(o + N);
+    L.soa[b][7] = o;
+    o = align_up(o + 4 * N);
+  }
+  L.key = o;
+  o = align_up(o + 4 * N);
+  L.rank = o;
+  o = align_up(o + 4 * N);
+  L.cellid = o;
+  o = align_up(o + 4 * N);
+  L.count = o;
+  o = align_up(o + 4 * (size_t)(ncells(p) + 1));
+  L.cell_off = o;
+  o = align_up(o + 4 * (size_t)(ncells(p) + 1));
+  L.bsum = o;
+  o = align_up(o + 4 * scan_blocksums_len(ncells(p)));
+  L.dens = o;
+  o = align_up(o + 8 * (size_t)ECR_N_FIELDS * (size_t)nnodes(p));
+  L.acc = o;
+  o = align_up(o + sizeof(DevAccum));
+  L.tables = o;
+  o = align_up(o + sizeof(Tables));
+  L.efield = o;
+  if (p->efield_nodes) o = align_up(o + 8 * 3 * (size_t)nnodes(p));
+  L.evlog = o;
+  if (p->flags & ECR_FLAG_EVENTS) o = align_up(o + N);
+  L.total = o + kAlign;  // slack so the arena base may be realigned
+  return L;
+}
+
+// Nanbu's A(s): root of coth(A) - 1/A = exp(-s) by Newton's method on
+// F(A) = ln(coth A - 1/A) + s, with coth A - 1/A evaluated without
+// cancellation: for A < 2 from its odd power series (Bernoulli numbers
+// through A^41), else directly.  Returns ln A.
+double langevin_lib(double a, double *deriv) {
+  // L(a) = coth a - 1/a; L'(a) = 1/a^2 - 1/sinh(a)^2
+  double L, dL;
+  if (a < 2.0) {
+    // coth a - 1/a = sum_k 2^(2k) B_2k a^(2k-1) / (2k)!, convergent for
+    // |a| < pi; the coefficients come from the Bernoulli numbers, computed once
+    static double coef[24];
+    static bool init = false;
+    if (!init) {
+      // B_2k via the recurrence sum_{j=0}^{m} C(m+1, j) B_j = 0
+      double B[50] = {0};
+      B[0] = 1.0;
+      for (int m = 1; m < 50; ++m) {
+        double s = 0.0, binom = 1.0;  // C(m+1, 0)
+        for (int j = 0; j < m; ++j) {
+          s += binom * B[j];
+          binom = binom * (double)(m + 1 - j) / (double)(j + 1);
+        }
+        B[m] = -s / (double)(m + 1);
+      }
+      double fact = 1.0, pow2 = 1.0;
+      for (int k = 1; k <= 24; ++k) {
+        fact *= (double)(2 * k - 1) * (double)(2 * k);
+        pow2 *= 4.0;
+        coef[k - 1] = pow2 * B[2 * k] / fact;
+      }
+      init = true;
+    }
+    double a2 = a * a, p = a, sum = 0.0, dsum = 0.0;
+    for (int k = 1; k <= 24; ++k) {
+      sum += coef[k - 1] * p;                     // a^(2k-1)
+      dsum += coef[k - 1] * (double)(2 * k - 1) * (p / a);
+      p *= a2;
+    }
+    L = sum;
+    dL = dsum;
+  } else {
+    L = 1.0 / tanh(a) - 1.0 / a;
+    const double sh = sinh(a);
+    dL = 1.0 / (a * a) - 1.0 / (sh * sh);
+  }
+  *deriv = dL;
+  return L;
+}
+
+double nanbu_lnA_lib(double s) {
+  // start from the asymptotes and polish with Newton on G(t) = ln L(e^t) + s, t = ln A
+  double A = (s < 1.0) ? 1.0 / (-expm1(-s)) : 3.0 * exp(-s) + 1e-300;
+  if (s >= 0.5 && s < 3.0) A = 1.0 / s;  // any start in range; Newton below is safeguarded
+  double lo = 1e-6, hi = 2.0 / s + 4.0;
+  double t = log(A);
+  for (int it = 0; it < 200; ++it) {
+    const double a = exp(t);
+    double G, dG;
+    if (s < 1.0) {
+      // 1 - L(a) = 1/a - 2/expm1(2a), target 1 - exp(-s) = -expm1(-s); use the log of the complement
+      const double e2 = expm1(2.0 * a);
+      const double comp = 1.0 / a - 2.0 / e2;
+      const double dcomp = -1.0 / (a * a) + 4.0 * (e2 + 1.0) / (e2 * e2);
+      G = log(comp) - log(-expm1(-s));
+      dG = dcomp / comp * a;
+    } else {
+      double dL;
+      const double L = langevin_lib(a, &dL);
+      G = log(L) + s;
+      dG = dL / L * a;
+    }
+    if (G > 0.0) {  // s < 1: complement too large -> a too small; s >= 1: L too large -> a too large
+      if (s < 1.0) lo = fmax(lo, a); else hi = fmin(hi, a);
+    } else {
+      if (s < 1.0) hi = fmin(hi, a); else lo = fmax(lo, a);
+    }
+    double tn = t - G / dG;
+    if (!(tn > log(lo) && tn < log(hi))) tn = 0.5 * (log(lo) + log(hi));
+    if (fabs(tn - t) <= 1e-17 * fmax(1.0, fabs(t))) {
+      t = tn;
+      break;
+    }
+    t = tn;
+  }
+  return t;
+}
+
+}  // namespace
+
+struct ecr_run {
+  ecr_params p;
+  KParams kp;
+  hipStream_t stream;
+  char *base;
+  Layout L;
+  bool fp32;
+  double weight;
+  int64_t ncell, nnode;
+  int64_t step;
+  int64_t steps;
+  int64_t dens_steps;
+  bool need_sort;
+  bool initialized;
+  bool failed;
+  int cur;  // which SoA buffer is current
+  std::string err;
+  // profiling
+  bool prof;
+  double ms[ECR_N_KERNELS];
+  int64_t launches[ECR_N_KERNELS];
+  std::vector<hipEvent_t> free_events;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+};
+
+namespace {
+
+template <typename T>
+T *at(ecr_run *r, size_t off) {
+  return reinterpret_cast<T *>(r->base + off);
+}
+
+template <typename R>
+Soa<R> soa(ecr_run *r, int b) {
+  Soa<R> s;
+  s.x = at<R>(r, r->L.soa[b][0]);
+  s.y = at<R>(r, r->L.soa[b][1]);
+  s.z = at<R>(r, r->L.soa[b][2]);
+  s.vx = at<R>(r, r->L.soa[b][3]);
+  s.vy = at<R>(r, r->L.soa[b][4]);
+  s.vz = at<R>(r, r->L.soa[b][5]);
+  s.qs = at<uint8_t>(r, r->L.soa[b][6]);
+  s.pid = at<uint32_t>(r, r->L.soa[b][7]);
+  return s;
+}
+
+ecr_status fail(ecr_run *r, ecr_status st, const std::string &msg) {
+  if (r) r->err = msg; else g_thread_err = msg;
+  return st;
+}
+
+ecr_status check_hip(ecr_run *r, hipError_t e, const char *what) {
+  if (e == hipSuccess) return ECR_OK;
+  r->failed = true;
+  return fail(r, ECR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+std::string validate(const ecr_params *p) {
+  if (!p) return "params is NULL";
+  if (p->abi_version != ECR_ABI_VERSION) return "abi_version mismatch";
+  if (p->precision != ECR_FP64 && p->precision != ECR_FP32_MIXED) return "precision must be ECR_FP64 or ECR_FP32_MIXED";
+  if (p->n_particles < 0 || p->n_particles > 0x7fffffffLL) return "n_particles out of range";
+  if (!(p->dt_s > 0.0) || !isfinite(p->dt_s)) return "dt_s must be positive";
+  if (p->sort_every < 1) return "sort_every must be >= 1";
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "mesh dimensions must be >= 1";
+  if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 31) - 1) return "mesh too large";
+  if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 30)) return "mesh too large for 64-bit pairing keys";
+  if (p->n_species < 1 || p->n_species > ECR_MAX_SPECIES) return "n_species must be 1..4";
+  if (!(p->R0_m > 0.0) || !(p->L_m > 0.0)) return "R0_m and L_m must be positive";
+  if (!(p->zone_a_m > 0.0) || !(p->zone_c_m > 0.0)) return "zone semi-axes must be positive";
+  if (p->r_ap_m < 0.0) return "r_ap_m must be >= 0";
+  if (p->inlet_x_m * p->inlet_x_m + p->inlet_y_m * p->inlet_y_m >= p->R0_m * p->R0_m) return "gas inlet outside the chamber";
+  if (p->weight < 0.0 || p->lnL_ii < 0.0 || p->Ti0_eV < 0.0 || p->T_wall_eV < 0.0 || p->T_n_eV < 0.0)
+    return "negative weight, Coulomb logarithm or temperature";
+  if (p->ne_in_m3 < 0.0 || p->ne_out_m3 < 0.0) return "negative electron density";
+  double fsum = 0.0;
+  for (int s = 0; s < p->n_species; ++s) {
+    const ecr_species &sp = p->species[s];
+    if (!(sp.mass_amu > 0.0)) return "species mass must be positive";
+    if (sp.z_max < 0 || sp.z_max >= ECR_MAX_Q) return "z_max must be 0..31";
+    if (sp.fraction < 0.0) return "species fraction must be >= 0";
+    if (sp.sigma_cx1_m2 < 0.0 || sp.n0_m3 < 0.0) return "negative cross-section or neutral density";
+    for (int q = 0; q < ECR_MAX_Q; ++q)
+      if (sp.k_ion_in_m3s[q] < 0.0 || sp.k_ion_out_m3s[q] < 0.0) return "negative ionisation rate";
+    fsum += sp.fraction;
+  }
+  (void)fsum;
+  return "";
+}
+
+// derived constants and tables, computed on the host in binary64
+void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
+  memset(&K, 0, sizeof(K));
+  memset(&T, 0, sizeof(T));
+  const double dt = p->dt_s;
+  K.R0 = p->R0_m;
+  K.hL = 0.5 * p->L_m;
+  K.R0sq = p->R0_m * p->R0_m;
+  K.rap2 = p->r_ap_m * p->r_ap_m;
+  K.inlet_x = p->inlet_x_m;
+  K.inlet_y = p->inlet_y_m;
+  K.idx = (double)p->nx / (2.0 * p->R0_m);
+  K.idy = (double)p->ny / (2.0 * p->R0_m);
+  K.idz = (double)p->nz / p->L_m;
+  K.zone_a = p->zone_a_m;
+  K.zone_c = p->zone_c_m;
+  K.ia2 = 1.0 / (p->zone_a_m * p->zone_a_m);
+  K.ic2 = 1.0 / (p->zone_c_m * p->zone_c_m);
+  K.B0 = p->B0_T;
+  const double L2 = p->L_m * p->L_m, R02 = p->R0_m * p->R0_m;
+  K.c1 = ((4.0 * p->mirror_k) * p->B0_T) / L2;
+  K.c2 = (2.0 * p->BH_T) / R02;
+  K.c3 = p->BH_T / R02;
+  K.c4 = ((2.0 * p->mirror_k) * p->B0_T) / L2;
+  K.dt = dt;
+  const double vzone = (4.0 / 3.0) * kPi * (p->zone_a_m * p->zone_a_m) * p->zone_c_m;
+  weight = p->weight > 0.0 ? p->weight
+                           : (p->n_particles > 0 ? p->ne_in_m3 * vzone / (double)p->n_particles : 0.0);
+  const double vcell = ((2.0 * p->R0_m / p->nx) * (2.0 * p->R0_m / p->ny)) * (p->L_m / p->nz);
+  K.nfac = weight / vcell;
+  K.Cs = p->lnL_ii * (kE * kE) * (kE * kE) / (4.0 * kPi * kEps0 * kEps0);
+  int64_t end = 0;
+  for (int s = 0; s < p->n_species; ++s) {
+    const ecr_species &sp = p->species[s];
+    const double M = sp.mass_amu * kAmu;
+    K.mass[s] = M;
+    K.sig_w[s] = sqrt(p->T_wall_eV * kE / M);
+    K.sig_n[s] = sqrt(p->T_n_eV * kE / M);
+    K.sig_i[s] = sqrt(p->Ti0_eV * kE / M);
+    K.decx[s] = 4.0 * p->dE_cx_eV * kE / M;
+    K.ccx[s] = (sp.n0_m3 * sp.sigma_cx1_m2) * dt;
+    uint32_t ok = 0;
+    for (int q = 0; q < kMaxQ; ++q) {
+      T.qmh[s][q] = ((double)q * kE / M) * (dt * 0.5);
+      if (q < sp.z_max) {
+        T.pion[s][1][q] = -expm1(-(p->ne_in_m3 * sp.k_ion_in_m3s[q]) * dt);
+        T.pion[s][0][q] = -expm1(-(p->ne_out_m3 * sp.k_ion_out_m3s[q]) * dt);
+      }
+      if (q >= 1 && q <= sp.z_max && !((sp.cx_forbidden_mask >> q) & 1u)) ok |= 1u << q;
+    }
+    K.cxok[s] = ok;
+    if (s == p->n_species - 1) end = p->n_particles;
+    else end += (int64_t)floor(sp.fraction * (double)p->n_particles + 0.5);
+    if (end > p->n_particles) end = p->n_particles;
+    K.sp_end[s] = end;
+  }
+  for (int e = kAeLo; e <= kAeHi; ++e)
+    for (int j = 0; j < kAK; ++j) T.lnA[(e - kAeLo) * kAK + j] = nanbu_lnA_lib(ldexp(1.0 + (double)j / kAK, e));
+  T.lnA[kANodes - 1] = nanbu_lnA_lib(kSHi);
+  K.n = p->n_particles;
+  K.nnode = nnodes(p);
+  K.nx = p->nx;
+  K.ny = p->ny;
+  K.nz = p->nz;
+  K.nx1 = p->nx + 1;
+  K.ny1 = p->ny + 1;
+  K.nspecies = p->n_species;
+  K.seed_lo = (uint32_t)p->seed;
+  K.seed_hi = (uint32_t)(p->seed >> 32);
+  K.pmask = p->process_mask;
+  K.dmask = p->deposit_mask;
+  K.flags = p->flags;
+}
+
+// largest per-step collision probability, with charge exchange bounded at a
+// speed cap of 10 sqrt(2 T e / M), T = max(Ti0, T_wall, 10 eV)
+double max_probability(const ecr_params *p, const KParams &K, const Tables &T) {
+  double worst = 0.0;
+  for (int s = 0; s < p->n_species; ++s) {
+    const double Tm = fmax(fmax(p->Ti0_eV, p->T_wall_eV), 10.0);
+    const double vcap = 10.0 * sqrt(2.0 * Tm * kE / K.mass[s]);
+    for (int q = 0; q <= p->species[s].z_max; ++q)
+      for (int z = 0; z < 2; ++z) {
+        double pi = (p->process_mask & ECR_P_IONIZE) ? T.pion[s][z][q] : 0.0;
+        double pc = ((p->process_mask & ECR_P_CX) && ((K.cxok[s] >> q) & 1u)) ? K.ccx[s] * q * vcap : 0.0;
+        worst = fmax(worst, pi + pc);
+      }
+  }
+  return worst;
+}
+
+// ---- profiling ----
+hipEvent_t get_event(ecr_run *r) {
+  if (!r->free_events.empty()) {
+    hipEvent_t e = r->free_events.back();
+    r->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void harvest(ecr_run *r) {
+  if (r->pending.empty()) return;
+  (void)hipStreamSynchronize(r->stream);
+  for (auto &pd : r->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+      r->ms[pd.kind] += ms;
+      r->launches[pd.kind] += 1;
+    }
+    r->free_events.push_back(pd.a);
+    r->free_events.push_back(pd.b);
+  }
+  r->pending.clear();
+}
+
+struct ProfScope {
+  ecr_run *r;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(ecr_run *r_, int k) : r(r_), kind(k) {
+    if (r->prof) {
+      a = get_event(r);
+      b = get_event(r);
+      (void)hipEventRecord(a, r->stream);
+    }
+  }
+  ~ProfScope() {
+    if (r->prof) {
+      (void)hipEventRecord(b, r->stream);
+      r->pending.push_back({kind, a, b});
+      if (r->pending.size() >= 4096) harvest(r);
+    }
+  }
+};
+
+template <typename R>
+void do_sort(ecr_run *r, const uint32_t *given) {
+  ProfScope ps(r, ECR_K_SORT);
+  const int a = r->cur, b = 1 - r->cur;
+  launch_sort<R>(r->kp, soa<R>(r, a), soa<R>(r, b), given, at<uint32_t>(r, r->L.key), at<uint32_t>(r, r->L.rank),
+                 at<uint32_t>(r, r->L.count), at<uint32_t>(r, r->L.cell_off), at<uint32_t>(r, r->L.bsum),
+                 at<uint32_t>(r, r->L.cellid), r->ncell, r->stream);
+  r->cur = b;
+}
+
+template <typename R>
+void do_step(ecr_run *r) {
+  const uint32_t pm = r->p.process_mask;
+  if (r->need_sort || r->step % r->p.sort_every == 0) {
+    do_sort<R>(r, nullptr);
+    r->need_sort = false;
+  }
+  const uint32_t stepw = (uint32_t)r->step;
+  DevAccum *acc = at<DevAccum>(r, r->L.acc);
+  const Tables *T = at<Tables>(r, r->L.tables);
+  if (pm & ECR_P_COULOMB) {
+    ProfScope ps(r, ECR_K_COULOMB);
+    launch_coulomb<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off),
+                      r->ncell, acc, stepw, r->stream);
+  }
+  {
+    ProfScope ps(r, ECR_K_PUSH);
+    launch_push<R>(r->kp, T, soa<R>(r, r->cur), r->p.efield_nodes ? at<double>(r, r->L.efield) : nullptr,
+                   (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc, stepw, r->stream);
+  }
+  if (pm & ECR_P_DEPOSIT) {
+    ProfScope ps(r, ECR_K_DEPOSIT);
+    launch_deposit<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
+    r->dens_steps++;
+  }
+  r->step++;
+  r->steps++;
+}
+
+void zero_accumulators(ecr_run *r) {
+  launch_fill_f64(at<double>(r, r->L.dens), 0.0, (int64_t)ECR_N_FIELDS * r->nnode, r->stream);
+  launch_fill_u32(at<uint32_t>(r, r->L.acc), 0u, (int64_t)(sizeof(DevAccum) / 4), r->stream);
+  r->steps = 0;
+  r->dens_steps = 0;
+}
+
+}  // namespace
+
+namespace {
+template <typename R>
+ecr_status get_state_t(ecr_run *r, ecr_state_view *v) {
+  const int64_t n = r->kp.n;
+  std::vector<R> buf[6];
+  std::vector<uint8_t> qs(n);
+  std::vector<uint32_t> pid(n), cell(n);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+    buf[k].resize(n);
+    e = hipMemcpyAsync(buf[k].data(), r->base + r->L.soa[r->cur][k], sizeof(R) * n, hipMemcpyDeviceToHost, r->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(qs.data(), r->base + r->L.soa[r->cur][6], n, hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pid.data(), r->base + r->L.soa[r->cur][7], 4 * n, hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(cell.data(), r->base + r->L.cellid, 4 * n, hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) return check_hip(r, e, "get_state");
+  double *dst[6] = {v->x, v->y, v->z, v->vx, v->vy, v->vz};
+  for (int64_t j = 0; j < n; ++j) {
+    const uint32_t i = pid[j];
+    if (i >= (uint32_t)n) return fail(r, ECR_ESTATE, "corrupt particle ids");
+    for (int k = 0; k < 6; ++k)
+      if (dst[k]) dst[k][i] = (double)buf[k][j];
+    if (v->q) v->q[i] = qs[j] & 31;
+    if (v->species) v->species[i] = qs[j] >> 5;
+    if (v->cell) v->cell[i] = cell[j];
+  }
+  v->step = r->step;
+  return ECR_OK;
+}
+
+template <typename R>
+ecr_status set_state_t(ecr_run *r, const ecr_state_view *v) {
+  const int64_t n = r->kp.n;
+  std::vector<R> buf[6];
+  const double *src[6] = {v->x, v->y, v->z, v->vx, v->vy, v->vz};
+  std::vector<uint8_t> qs(n);
+  std::vector<uint32_t> pid(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int s = r->kp.nspecies - 1;
+    for (int k = r->kp.nspecies - 1; k >= 0; --k)
+      if (i < r->kp.sp_end[k]) s = k;
+    if (v->q[i] > r->p.species[s].z_max) return fail(r, ECR_EINVAL, "charge state above z_max");
+    if (v->cell && v->cell[i] >= (uint32_t)r->ncell) return fail(r, ECR_EINVAL, "cell out of range");
+    qs[i] = (uint8_t)(v->q[i] | (s << 5));
+    pid[i] = (uint32_t)i;
+  }
+  for (int k = 0; k < 6; ++k) {
+    buf[k].resize(n);
+    for (int64_t i = 0; i < n; ++i) buf[k][i] = (R)src[k][i];
+  }
+  r->cur = 0;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 6 && e == hipSuccess; ++k)
+    e = hipMemcpyAsync(r->base + r->L.soa[0][k], buf[k].data(), sizeof(R) * n, hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->base + r->L.soa[0][6], qs.data(), n, hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->base + r->L.soa[0][7], pid.data(), 4 * n, hipMemcpyHostToDevice, r->stream);
+  // given collision cells (by id) are staged in buffer B's id array: the
+  // sort's count pass reads them before its scatter overwrites buffer B
+  if (e == hipSuccess && v->cell)
+    e = hipMemcpyAsync(r->base + r->L.soa[1][7], v->cell, 4 * n, hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) return check_hip(r, e, "set_state");
+  return ECR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ecr_status ecr_footprint(const ecr_params *params, size_t *device_bytes) {
+  const std::string v = validate(params);
+  if (!v.empty()) return fail(nullptr, params && params->abi_version != ECR_ABI_VERSION ? ECR_EABI : ECR_EINVAL, v);
+  if (!device_bytes) return fail(nullptr, ECR_EINVAL, "device_bytes is NULL");
+  *device_bytes = make_layout(params).total;
+  return ECR_OK;
+}
+
+ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena_bytes, void *hip_stream,
+                      ecr_run **out) {
+  if (!out) return fail(nullptr, ECR_EINVAL, "out is NULL");
+  *out = nullptr;
+  const std::string v = validate(params);
+  if (!v.empty()) return fail(nullptr, params && params->abi_version != ECR_ABI_VERSION ? ECR_EABI : ECR_EINVAL, v);
+  const Layout L = make_layout(params);
+  if (!device_arena) return fail(nullptr, ECR_EINVAL, "device_arena is NULL");
+  if (arena_bytes < L.total) return fail(nullptr, ECR_ENOMEM, "arena smaller than ecr_footprint()");
+  KParams K;
+  Tables T;
+  double w;
+  derive(params, K, T, w);
+  if (max_probability(params, K, T) >= 0.1)
+    return fail(nullptr, ECR_EDT, "per-step ionisation + charge-exchange probability can reach 0.1: reduce dt_s");
+  ecr_run *r = new ecr_run();
+  r->p = *params;
+  r->kp = K;
+  r->stream = (hipStream_t)hip_stream;
+  r->base = (char *)(((uintptr_t)device_arena + kAlign - 1) / kAlign * kAlign);
+  r->L = L;
+  r->fp32 = params->precision == ECR_FP32_MIXED;
+  r->weight = w;
+  r->ncell = ncells(params);
+  r->nnode = nnodes(params);
+  r->cur = 0;
+  r->need_sort = true;
+  r->prof = false;
+  for (int k = 0; k < ECR_N_KERNELS; ++k) {
+    r->ms[k] = 0.0;
+    r->launches[k] = 0;
+  }
+  hipError_t e = hipMemcpyAsync(at<Tables>(r, L.tables), &T, sizeof(Tables), hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess && params->efield_nodes)
+    e = hipMemcpyAsync(at<double>(r, L.efield), params->efield_nodes, 8 * 3 * (size_t)r->nnode,
+                       hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) {
+    g_thread_err = std::string("upload failed: ") + hipGetErrorString(e);
+    delete r;
+    return ECR_EDEVICE;
+  }
+  r->p.efield_nodes = params->efield_nodes ? (const double *)1 : nullptr;  // only its presence is kept
+  zero_accumulators(r);
+  *out = r;
+  return ECR_OK;
+}
+
+ecr_status ecr_init_ions(ecr_run *r) {
+  if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
+  if (r->failed) return fail(r, ECR_ESTATE, "run failed earlier");
+  r->cur = 0;
+  if (r->fp32) launch_init<float>(r->kp, soa<float>(r, 0), r->stream);
+  else launch_init<double>(r->kp, soa<double>(r, 0), r->stream);
+  if (r->p.flags & ECR_FLAG_EVENTS) launch_fill_u8(at<uint8_t>(r, r->L.evlog), 0, r->kp.n, r->stream);
+  zero_accumulators(r);
+  r->step = 0;
+  r->need_sort = true;
+  r->initialized = true;
+  return check_hip(r, hipGetLastError(), "init_ions launch");
+}
+
+ecr_status ecr_step(ecr_run *r, int64_t n_steps) {
+  if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
+  if (n_steps < 0) return fail(r, ECR_EINVAL, "n_steps < 0");
+  if (r->failed) return fail(r, ECR_ESTATE, "run failed earlier");
+  if (!r->initialized) return fail(r, ECR_ESTATE, "call ecr_init_ions or ecr_set_state first");
+  for (int64_t i = 0; i < n_steps; ++i) {
+    if (r->fp32) do_step<float>(r);
+    else do_step<double>(r);
+  }
+  return check_hip(r, hipGetLastError(), "step launch");
+}
+
+ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps, void *hip_stream) {
+  if (!runs || n_runs < 0 || n_steps < 0) return fail(nullptr, ECR_EINVAL, "bad batch arguments");
+  for (int32_t k = 0; k < n_runs; ++k)
+    if (!runs[k] || runs[k]->failed || !runs[k]->initialized || runs[k]->stream != (hipStream_t)hip_stream)
+      return fail(nullptr, ECR_EINVAL, "every run must be initialised and bound to the batch stream");
+  for (int64_t i = 0; i < n_steps; ++i)
+    for (int32_t k = 0; k < n_runs; ++k) {
+      ecr_run *r = runs[k];
+      if (r->fp32) do_step<float>(r);
+      else do_step<double>(r);
+    }
+  for (int32_t k = 0; k < n_runs; ++k) {
+    const ecr_status st = check_hip(runs[k], hipGetLastError(), "batch step launch");
+    if (st != ECR_OK) return st;
+  }
+  return ECR_OK;
+}
+
+ecr_status ecr_read_tallies(ecr_run *r, ecr_tallies *out) {
+  if (!r || !out) return fail(r, ECR_EINVAL, "NULL argument");
+  DevAccum h;
+  hipError_t e = hipMemcpyAsync(&h, at<DevAccum>(r, r->L.acc), sizeof(DevAccum), hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) return check_hip(r, e, "read_tallies");
+  *out = h.t;
+  out->steps = r->steps;
+  if (h.err & ERR_COUL_OVERFLOW) {
+    r->err = "a Coulomb chunk exceeded the LDS capacity; its cells were skipped";
+    out->anomalies += 1;
+  }
+  if (out->anomalies > 0) return fail(r, ECR_ENUMERIC, r->err.empty() ? "anomalies counted" : r->err);
+  return ECR_OK;
+}
+
+ecr_status ecr_read_density(ecr_run *r, uint32_t field, double *out, int64_t *steps_accum) {
+  if (!r || !out) return fail(r, ECR_EINVAL, "NULL argument");
+  if (field >= ECR_N_FIELDS) return fail(r, ECR_EINVAL, "field out of range");
+  hipError_t e = hipMemcpyAsync(out, at<double>(r, r->L.dens) + (size_t)field * r->nnode, 8 * (size_t)r->nnode,
+                                hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) return check_hip(r, e, "read_density");
+  if (steps_accum) *steps_accum = r->dens_steps;
+  return ECR_OK;
+}
+
+
+ecr_status ecr_get_state(ecr_run *r, ecr_state_view *v) {
+  if (!r || !v) return fail(r, ECR_EINVAL, "NULL argument");
+  if (v->n != r->kp.n) return fail(r, ECR_EINVAL, "view length differs from n_particles");
+  if (!r->initialized) return fail(r, ECR_ESTATE, "no state yet");
+  return r->fp32 ? get_state_t<float>(r, v) : get_state_t<double>(r, v);
+}
+
+ecr_status ecr_set_state(ecr_run *r, const ecr_state_view *v) {
+  if (!r || !v) return fail(r, ECR_EINVAL, "NULL argument");
+  if (r->failed) return fail(r, ECR_ESTATE, "run failed earlier");
+  if (v->n != r->kp.n) return fail(r, ECR_EINVAL, "view length differs from n_particles");
+  if (!v->x || !v->y || !v->z || !v->vx || !v->vy || !v->vz || !v->q) return fail(r, ECR_EINVAL, "NULL array");
+  if (v->step < 0) return fail(r, ECR_EINVAL, "negative step");
+  ecr_status st = r->fp32 ? set_state_t<float>(r, v) : set_state_t<double>(r, v);
+  if (st != ECR_OK) return st;
+  r->step = v->step;
+  zero_accumulators(r);
+  if (r->p.flags & ECR_FLAG_EVENTS) launch_fill_u8(at<uint8_t>(r, r->L.evlog), 0, r->kp.n, r->stream);
+  if (v->cell) {
+    // sort with the given collision cells, staged by set_state_t
+    const uint32_t *stage = at<uint32_t>(r, r->L.soa[1][7]);
+    if (r->fp32) do_sort<float>(r, stage);
+    else do_sort<double>(r, stage);
+    r->need_sort = false;
+  } else {
+    r->need_sort = true;
+  }
+  r->initialized = true;
+  return check_hip(r, hipGetLastError(), "set_state");
+}
+
+ecr_status ecr_event_log(ecr_run *r, uint8_t *out) {
+  if (!r || !out) return fail(r, ECR_EINVAL, "NULL argument");
+  if (!(r->p.flags & ECR_FLAG_EVENTS)) return fail(r, ECR_ESTATE, "run created without ECR_FLAG_EVENTS");
+  const int64_t n = r->kp.n;
+  std::vector<uint8_t> ev(n);
+  std::vector<uint32_t> pid(n);
+  hipError_t e = hipMemcpyAsync(ev.data(), r->base + r->L.evlog, n, hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pid.data(), r->base + r->L.soa[r->cur][7], 4 * n, hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) return check_hip(r, e, "event_log");
+  for (int64_t j = 0; j < n; ++j) out[pid[j]] = ev[j];
+  return ECR_OK;
+}
+
+ecr_status ecr_weight(const ecr_run *r, double *w) {
+  if (!r || !w) return fail(nullptr, ECR_EINVAL, "NULL argument");
+  *w = r->weight;
+  return ECR_OK;
+}
+
+ecr_status ecr_profile(ecr_run *r, int32_t enable) {
+  if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
+  harvest(r);
+  r->prof = enable != 0;
+  for (int k = 0; k < ECR_N_KERNELS; ++k) {
+    r->ms[k] = 0.0;
+    r->launches[k] = 0;
+  }
+  return ECR_OK;
+}
+
+ecr_status ecr_kernel_times(ecr_run *r, double *ms_out, int64_t *launches_out) {
+  if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
+  harvest(r);
+  for (int k = 0; k < ECR_N_KERNELS; ++k) {
+    if (ms_out) ms_out[k] = r->ms[k];
+    if (launches_out) launches_out[k] = r->launches[k];
+  }
+  return ECR_OK;
+}
+
+const char *ecr_last_error(const ecr_run *r) { return r ? r->err.c_str() : g_thread_err.c_str(); }
+
+ecr_status ecr_destroy(ecr_run *r) {
+  if (!r) return ECR_OK;
+  harvest(r);
+  for (auto e : r->free_events) (void)hipEventDestroy(e);
+  delete r;
+  return ECR_OK;
+}
+
+ecr_status ecr_selftest_philox(uint64_t seed, uint32_t ctr0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                               uint32_t *out_dev, void *hip_stream) {
+  if (n < 0 || (n > 0 && !out_dev)) return fail(nullptr, ECR_EINVAL, "bad arguments");
+  launch_selftest_philox(seed, ctr0, c1, c2, c3, n, out_dev, (hipStream_t)hip_stream);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ECR_OK : fail(nullptr, ECR_EDEVICE, hipGetErrorString(e));
+}
+
+ecr_status ecr_selftest_divsqrt(const double *a_dev, const double *b_dev, int64_t n, double *q_dev, double *r_dev,
+                                void *hip_stream) {
+  if (n < 0 || (n > 0 && (!a_dev || !b_dev || !q_dev || !r_dev))) return fail(nullptr, ECR_EINVAL, "bad arguments");
+  launch_selftest_divsqrt(a_dev, b_dev, n, q_dev, r_dev, (hipStream_t)hip_stream);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ECR_OK : fail(nullptr, ECR_EDEVICE, hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+Bar (binary64 path): from identical input state, per-step event codes,
+charge states and integer tallies are bit-exact; positions agree within
+1e-12 relative to max(|x|, R0) and velocities within 1e-12 relative to
+max(|v|, 1 km/s); density grids within 1e-12 of the largest node value.
+Sizes span several workgroups with a ragged tail; the full-size case runs
+2M ions in the benchmark's launch configuration and checks whole sampled
+collision cells against the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+XTOL = 1e-12
+VSCALE = 1e3
+
+
+def gpu_run(params, **kw):
+    import paper_1507_03392_amd as ecr
+    return ecr.Run(params, **kw)
+
+
+def oracle(params):
+    from oracle.binding import OracleSim
+    return OracleSim(params)
+
+
+def assert_state_close(a, b, params, ids=None, what=""):
+    sel = slice(None) if ids is None else ids
+    assert np.array_equal(a["q"][sel], b["q"]), f"{what}: charge states differ"
+    for k in ("x", "y", "z"):
+        d = np.abs(a[k][sel] - b[k]) / np.maximum(np.abs(b[k]), params["R0"])
+        assert d.max(initial=0) <= XTOL, f"{what}: {k} rel err {d.max()}"
+    for k in ("vx", "vy", "vz"):
+        d = np.abs(a[k][sel] - b[k]) / np.maximum(np.abs(b[k]), VSCALE)
+        assert d.max(initial=0) <= XTOL, f"{what}: {k} rel err {d.max()}"
+
+
+def assert_tallies_equal(tg, to, what=""):
+    for k in ("extracted", "wall", "ionized", "cx", "cx_products"):
+        assert np.array_equal(tg[k], to[k]), f"{what}: tally {k} differs"
+    for k in ("recycled", "anomalies", "steps"):
+        assert tg[k] == to[k], f"{what}: {k} {tg[k]} vs {to[k]}"
+
+
+def boosted(params, n0=2e19):
+    p = W.with_(params)
+    sp = dict(p["species"][0])
+    sp["n0"] = n0
+    p["species"] = [sp]
+    return p
+
+
+def run_pair(params, st, steps, step0=0, cell=None):
+    g = gpu_run(params, events=True)
+    g.set_state(st, step=step0, cell=cell)
+    g.step(steps)
+    o = oracle(params)
+    o.set_state(st, step=step0, cell=cell)
+    o.step(steps)
+    return g, o
+
+
+def test_philox_bitwise():
+    import paper_1507_03392_amd as ecr
+    from oracle.binding import philox_fill
+    for seed, c in ((0, (0, 0, 0, 0)), (0x123456789ABCDEF, (7, 99, 1, 0)), (2**64 - 1, (2**32 - 5000, 2**32 - 1, 4, 3))):
+        g = ecr.selftest_philox(seed, c[0], c[1], c[2], c[3], 200_000)
+        o = philox_fill(seed, c[0], c[1], c[2], c[3], 200_000)
+        assert np.array_equal(g, o)
+
+
+def test_division_and_sqrt_correctly_rounded():
+    import paper_1507_03392_amd as ecr
+    rng = np.random.default_rng(0)
+    n = 2_000_000
+    a = np.exp(rng.uniform(-700, 700, n)) * rng.choice([1.0], n)
+    b = np.exp(rng.uniform(-700, 700, n)) * rng.choice([-1.0, 1.0], n)
+    a[:6] = [0.0, 1.0, 2.0, 5e-324, 1.7976931348623157e308, 2.2250738585072014e-308]
+    b[:6] = [3.0, 3.0, 7.0, 3.0, 0.7, 3.0]
+    q, r = ecr.selftest_divsqrt(a, b)
+    assert np.array_equal(q.view(np.uint64), (a / b).view(np.uint64))
+    assert np.array_equal(r.view(np.uint64), np.sqrt(a).view(np.uint64))
+
+
+@pytest.mark.parametrize("n", [1, 257, 20_011])
+def test_init_ions_parity(n):
+    params = W.base_params(n, 32, 32, 64)
+    g = gpu_run(params)
+    g.init_ions()
+    o = oracle(params)
+    o.init_ions()
+    a, b = g.get_state(), o.get_state()
+    # positions come from + - * only: bit-exact
+    for k in ("x", "y", "z"):
+        assert np.array_equal(a[k], b[k]), k
+    assert_state_close(a, b, params, what="init")
+    assert g.weight == o.weight
+
+
+CASES = {
+    "push": dict(mask=W.P_PUSH, v_ev=0.5),
+    "push_walls": dict(mask=W.P_PUSH, v_ev=300.0, dt=5e-9, rf=0.9995),
+    "ionize": dict(mask=W.P_IONIZE, v_ev=0.5),
+    "cx": dict(mask=W.P_CX, v_ev=50.0, n0=1e20),
+    "coulomb": dict(mask=W.P_COULOMB, v_ev=0.5),
+    "all": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20),
+    "all_walls": dict(mask=W.P_ALL, v_ev=200.0, dt=5e-9, rf=0.9995),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("seed", [0, 1])
+def test_single_step_parity(case, seed):
+    c = CASES[case]
+    params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
+    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=7, weight=4e9)
+    # a large zone with a dense electron background so ionisation fires in one step
+    params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
+    st = W.random_state(params, seed=100 + seed, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95))
+    g, o = run_pair(params, st, 1, step0=17 + seed)
+    a, b = g.get_state(), o.get_state()
+    assert np.array_equal(g.events(), o.events()), "events differ"
+    assert_state_close(a, b, params, what=case)
+    assert np.array_equal(a["cell"], b["cell"])
+    tg, to = g.tallies(), o.tallies()
+    assert_tallies_equal(tg, to, case)
+    ev = o.events()
+    if case in ("push_walls", "all_walls"):
+        assert (ev == W.EV_WALL).sum() > 20
+    if case in ("ionize", "all"):
+        assert (ev == W.EV_IONIZE).sum() > 5
+    if case == "cx":
+        assert (ev == W.EV_CX).sum() > 10
+    if c["mask"] & W.P_COULOMB:
+        assert abs(tg["coul_de"]) <= 1e-12 * tg["coul_e"]
+        assert tg["coul_e"] == pytest.approx(to["coul_e"], rel=1e-12)
+    if c["mask"] & W.P_DEPOSIT:
+        for f in (W.F_ION_N, W.F_ION_Q, W.F_ATOM_N):
+            dg, sg = g.density(f)
+            do, so = o.density(f)
+            assert sg == so == 1
+            assert np.abs(dg - do).max() <= 1e-12 * max(1.0, np.abs(do).max())
+
+
+def test_extraction_aperture_parity():
+    # ions just below the extraction flange heading out: some through the
+    # aperture (recycled at the inlet), some onto the flange around it
+    n = 6007
+    params = W.base_params(n, 16, 16, 32)
+    params.update(process_mask=W.P_ALL, dt=2e-9)
+    rng = np.random.default_rng(12)
+    r = 2 * params["r_ap"] * np.sqrt(rng.random(n))
+    th = 2 * np.pi * rng.random(n)
+    st = dict(x=r * np.cos(th), y=r * np.sin(th), z=params["L"] / 2 - rng.random(n) * 4e-5,
+              vx=rng.normal(size=n) * 300, vy=rng.normal(size=n) * 300, vz=np.abs(rng.normal(size=n)) * 2e4,
+              q=rng.integers(0, 9, n).astype(np.uint8))
+    g, o = run_pair(params, st, 2, step0=5)
+    ev = o.events()
+    assert np.array_equal(g.events(), ev)
+    assert_state_close(g.get_state(), o.get_state(), params, what="extract")
+    tg, to = g.tallies(), o.tallies()
+    assert_tallies_equal(tg, to, "extract")
+    assert to["recycled"] > 500 and to["wall"].sum() > 500
+
+
+def test_efield_push_parity():
+    params = W.base_params(5003, 8, 8, 16)
+    nn = 9 * 9 * 17
+    rng = np.random.default_rng(3)
+    ef = rng.normal(size=(3, nn)) * 2000.0
+    params.update(process_mask=W.P_PUSH, efield=ef)
+    st = W.random_state(params, seed=5, q_max=10, v_ev=5.0)
+    g, o = run_pair(params, st, 3)
+    assert_state_close(g.get_state(), o.get_state(), params, what="efield")
+    assert np.array_equal(g.events(), o.events())
+
+
+def test_multi_step_c1_from_init():
+    # the C1 workload (20k Ar ions, FP64, grid 32x32x64) for 120 steps, across two sorts
+    params, _ = W.config("c1")
+    g = gpu_run(params, events=True)
+    g.init_ions()
+    o = oracle(params)
+    o.init_ions()
+    for chunk in (1, 49, 1, 69):
+        g.step(chunk)
+        o.step(chunk)
+        a, b = g.get_state(), o.get_state()
+        assert np.array_equal(g.events(), o.events())
+        assert_state_close(a, b, params, what=f"c1 step {a['step']}")
+        assert np.array_equal(a["cell"], b["cell"])
+    assert_tallies_equal(g.tallies(), o.tallies(), "c1")
+    for f in (W.F_ION_N, W.F_ION_Q):
+        dg, _ = g.density(f)
+        do, _ = o.density(f)
+        assert np.abs(dg - do).max() <= 1e-12 * np.abs(do).max()
+
+
+def test_given_cells_and_resume_bitwise():
+    params = boosted(W.base_params(30_000, 16, 16, 32, seed=4))
+    params.update(dt=2e-9)
+    st = W.random_state(params, seed=9, q_max=8, v_ev=30.0)
+    a = gpu_run(params)
+    a.set_state(st)
+    a.step(130)
+    b = gpu_run(params)
+    b.set_state(st)
+    b.step(70)
+    mid = b.get_state()
+    c = gpu_run(params)
+    c.set_state(mid, step=mid["step"], cell=mid["cell"])
+    c.step(60)
+    sa, sc = a.get_state(), c.get_state()
+    for k in ("x", "y", "z", "vx", "vy", "vz", "q", "cell"):
+        assert np.array_equal(sa[k], sc[k]), k
+
+
+def test_determinism_two_runs():
+    params, _ = W.config("c1")
+    outs = []
+    for _ in range(2):
+        g = gpu_run(params)
+        g.init_ions()
+        g.step(60)
+        outs.append((g.get_state(), g.tallies()))
+    for k in ("x", "vx", "q"):
+        assert np.array_equal(outs[0][0][k], outs[1][0][k])
+    assert_tallies_equal(outs[0][1], outs[1][1])
+
+
+def test_edge_sizes_zero_one_and_tiny_grid():
+    for n in (0, 1, 2, 3):
+        params = W.base_params(n, 1, 1, 1)
+        params.update(process_mask=W.P_ALL)
+        g = gpu_run(params, events=True)
+        g.init_ions()
+        g.step(5)
+        t = g.tallies()
+        assert t["steps"] == 5
+        if n:
+            o = oracle(params)
+            o.init_ions()
+            o.step(5)
+            assert_state_close(g.get_state(), o.get_state(), params, what=f"n={n}")
+            assert_tallies_equal(t, o.tallies())
+
+
+def test_edt_rejected_and_bad_state():
+    import paper_1507_03392_amd as ecr
+    params = boosted(W.base_params(100, 8, 8, 16), n0=1e23)
+    with pytest.raises(ecr.EcrError) as e:
+        gpu_run(params)
+    assert e.value.status == -6
+    params = W.base_params(10, 8, 8, 16)
+    g = gpu_run(params)
+    st = W.random_state(params, seed=1)
+    st["q"][3] = 25
+    with pytest.raises(ecr.EcrError) as e:
+        g.set_state(st)
+    assert e.value.status == -1
+    st["q"][3] = 1
+    st["vx"][4] = np.nan
+    g.set_state(st)
+    g.step(1)
+    with pytest.raises(ecr.EcrError) as e:
+        g.tallies(allow_anomalies=False)
+    assert e.value.status == -5
+
+
+def test_full_size_c2_sampled_cells():
+    # 2M ions on the 64x64x128 grid, the benchmark's launch configuration:
+    # after 60 steps, whole collision cells are stepped once more by the oracle
+    from oracle.binding import OracleSim
+    params, _ = W.config("c2")
+    g = gpu_run(params, events=True)
+    g.init_ions()
+    g.step(60)
+    before = g.get_state()
+    g.step(1)
+    after = g.get_state()
+    ev = g.events()
+    rng = np.random.default_rng(0)
+    cells = np.unique(before["cell"])
+    pick = rng.choice(cells, size=min(400, len(cells)), replace=False)
+    ids = np.nonzero(np.isin(before["cell"], pick))[0]
+    sub = W.with_(params, n=len(ids), weight=g.weight)
+    o = OracleSim(sub)
+    o.set_ids(ids, before["species"][ids])
+    o.set_state({k: before[k][ids] for k in ("x", "y", "z", "vx", "vy", "vz", "q")}, step=60,
+                cell=before["cell"][ids])
+    o.step(1)
+    ob = o.get_state()
+    assert_state_close(after, ob, params, ids=ids, what="c2 sampled")
+    assert np.array_equal(ev[ids], o.events())
+    assert len(ids) > 10_000
+    t = g.tallies()
+    assert t["anomalies"] == 0
+    # charge bookkeeping over the whole run
+    zz = np.arange(32)
+    lost = int((zz * (t["extracted"][0] + t["wall"][0])).sum())
+    assert int(after["q"].astype(np.int64).sum()) + lost + int(t["cx_products"][0]) == \
+        params["n"] + int(t["ionized"][0].sum())

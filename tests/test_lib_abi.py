@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point that include/ecrpic.h
+declares; host-side parameter checks work without a GPU (ecr_footprint makes
+no device call)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1507_03392_amd as ecr
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ecrpic.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_is_built():
+    assert ecr.lib_available(), "build the library first (python __graft_entry__.py)"
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", ecr.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (ecr_[a-z_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = ecr.lib()
+    for n in names:
+        assert hasattr(lib, n)
+    assert sorted(ecr.EXPORTS) == names
+
+
+def test_footprint_and_parameter_checks():
+    p, _ = W.config("c2")
+    nb = ecr.footprint(p)
+    # two FP64 SoA buffers of 53 B per particle dominate
+    assert 2 * 53 * p["n"] < nb < 2 * 53 * p["n"] + 64 * p["n"] + 64 << 20
+    p32 = W.with_(p, precision=ecr.FP32_MIXED)
+    assert ecr.footprint(p32) < nb
+    with pytest.raises(ecr.EcrError) as e:
+        ecr.footprint(W.with_(p, dt=-1.0))
+    assert e.value.status == -1
+    with pytest.raises(ecr.EcrError):
+        ecr.footprint(W.with_(p, nx=0))
+    with pytest.raises(ecr.EcrError):
+        ecr.footprint(W.with_(p, species=[]))
+    bad = W.with_(p)
+    bad["species"][0]["z_max"] = 40
+    with pytest.raises(ecr.EcrError):
+        ecr.footprint(bad)
+    P, _keep = ecr.make_params(p)
+    P.abi_version = 99
+    import ctypes as C
+    n = C.c_size_t()
+    assert ecr.lib().ecr_footprint(C.byref(P), C.byref(n)) == -7
+    assert b"abi" in ecr.lib().ecr_last_error(None)
+
+
+def test_struct_layout_matches_header_sizes():
+    # sizes the C compiler gives the public structs
+    import ctypes as C
+    src = (f'#include "{HEADER}"\n#include <stdio.h>\n#include <stddef.h>\n'
+           'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(ecr_params), sizeof(ecr_species),'
+           ' sizeof(ecr_tallies), sizeof(ecr_state_view), offsetof(ecr_params, species));return 0;}')
+    exe = os.path.join("/tmp", f"ecr_sizes_{os.getpid()}")
+    subprocess.run(["gcc", "-x", "c", "-", "-o", exe], input=src, text=True, check=True)
+    got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    os.unlink(exe)
+    assert got == [C.sizeof(ecr.Params), C.sizeof(ecr.Species), C.sizeof(ecr.Tallies), C.sizeof(ecr.StateView),
+                   ecr.Params.species.offset]
