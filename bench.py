@@ -36,14 +36,15 @@ ALG_BYTES_FP64 = {
     "deposit": 24 + 1,
     # count pass (read x; write key, rank) + scatter (read record, key, rank; write record, cell)
     "sort": (24 + 8) + (53 + 8) + (53 + 4),
-    "fused": 48 + 1 + 4 + 4 + 48 + 1,
+    # push + deposit in one kernel: the deposit reads nothing more from HBM
+    "push_deposit": 48 + 1 + 4 + 48 + 1,
 }
 ALG_BYTES_FP32 = {
     "push": 24 + 1 + 4 + 24 + 1,
     "coulomb": 1 + 4 + 4 + 24 + 24,
     "deposit": 12 + 1,
     "sort": (12 + 8) + (29 + 8) + (29 + 4),
-    "fused": 24 + 1 + 4 + 4 + 24 + 1,
+    "push_deposit": 24 + 1 + 4 + 24 + 1,
 }
 
 
@@ -73,6 +74,8 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=500)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the ion step is not "
@@ -83,6 +86,15 @@ def main():
 
     import paper_1507_03392_amd as ecr
     import workloads as W
+
+    if args.copy_mb > 0:
+        a = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_mb} MiB device to device (counter calibration)")
+        del a, b
 
     params, _ = W.config(args.workload)
     n = params["n"]

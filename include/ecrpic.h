@@ -69,7 +69,10 @@ enum {
 enum { ECR_F_ION_N = 0, ECR_F_ION_Q = 1, ECR_F_ATOM_N = 2, ECR_N_FIELDS = 3 };
 
 /* run flags */
-enum { ECR_FLAG_EVENTS = 1 /* record each particle's event code of the last step */ };
+enum {
+  ECR_FLAG_EVENTS = 1, /* record each particle's event code of the last step */
+  ECR_FLAG_SPLIT = 2   /* deposit in its own kernel instead of inside the push kernel (per-kernel timing) */
+};
 
 /* event codes returned by ecr_event_log */
 enum { ECR_EV_NONE = 0, ECR_EV_IONIZE = 1, ECR_EV_CX = 2, ECR_EV_WALL = 3, ECR_EV_EXTRACT = 4 };
@@ -187,7 +190,14 @@ ecr_status ecr_weight(const ecr_run *run, double *weight);
 /* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
  * the run's stream; ecr_kernel_times returns, per kernel kind (ECR_K_*), the
  * summed milliseconds and the launch count since the last reset. */
-enum { ECR_K_SORT = 0, ECR_K_COULOMB = 1, ECR_K_PUSH = 2, ECR_K_DEPOSIT = 3, ECR_K_FUSED = 4, ECR_N_KERNELS = 5 };
+enum {
+  ECR_K_SORT = 0,    /* the sort by cell (count, scan, scatter) */
+  ECR_K_COULOMB = 1, /* Coulomb pairing and scattering */
+  ECR_K_PUSH = 2,    /* push + wall/aperture + ionisation/charge exchange */
+  ECR_K_DEPOSIT = 3, /* deposit alone (ECR_FLAG_SPLIT) */
+  ECR_K_FUSED = 4,   /* push + wall/aperture + ionisation/charge exchange + deposit in one kernel */
+  ECR_N_KERNELS = 5
+};
 ecr_status ecr_profile(ecr_run *run, int32_t enable);
 ecr_status ecr_kernel_times(ecr_run *run, double *ms_out, int64_t *launches_out);
 

@@ -20,9 +20,9 @@ MAXS, MAXQ = 4, 32
 FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL = 1, 2, 4, 8, 16, 31
 F_ION_N, F_ION_Q, F_ATOM_N, N_FIELDS = 0, 1, 2, 3
-FLAG_EVENTS = 1
+FLAG_EVENTS, FLAG_SPLIT = 1, 2
 K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, N_KERNELS = 0, 1, 2, 3, 4, 5
-KERNEL_NAMES = ["sort", "coulomb", "push", "deposit", "fused"]
+KERNEL_NAMES = ["sort", "coulomb", "push", "deposit", "push_deposit"]
 
 STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4: "ECR_ESTATE",
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}
@@ -117,14 +117,14 @@ def _check(st, handle=None):
         raise EcrError(st, msg.decode() if msg else "")
 
 
-def make_params(p, events=False):
+def make_params(p, events=False, split=False):
     """Fill the library's ecr_params from a workload dict (SI units)."""
     P = Params()
     P.abi_version = ABI_VERSION
     P.precision = p.get("precision", FP64)
     P.process_mask = p["process_mask"]
     P.deposit_mask = p["deposit_mask"]
-    P.flags = FLAG_EVENTS if events else 0
+    P.flags = (FLAG_EVENTS if events else 0) | (FLAG_SPLIT if split else 0)
     P.sort_every = p["sort_every"]
     P.seed = p["seed"]
     P.n_particles = p["n"]
@@ -177,7 +177,7 @@ def tallies_to_dict(t):
 class Run:
     """One simulation run on the GPU: arena and stream from torch, all compute in libecrpic."""
 
-    def __init__(self, params, events=False, device=None, stream=None, arena=None):
+    def __init__(self, params, events=False, split=False, device=None, stream=None, arena=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the ion step runs only in the HIP library")
@@ -185,7 +185,7 @@ class Run:
         self.n = params["n"]
         self.nnode = (params["nx"] + 1) * (params["ny"] + 1) * (params["nz"] + 1)
         self.events_enabled = events
-        P, keep = make_params(params, events)
+        P, keep = make_params(params, events, split)
         nbytes = C.c_size_t()
         _check(lib().ecr_footprint(C.byref(P), C.byref(nbytes)))
         self.nbytes = nbytes.value

@@ -10,32 +10,55 @@
 namespace ecr {
 
 // Coulomb chunking: a workgroup owns the cells whose first sorted slot falls
-// in [b*kCoulCap, (b+1)*kCoulCap); it sorts up to kCoulMaxE entries in LDS.
-constexpr int kCoulCap = 512;
-constexpr int kCoulMaxE = 2048;
+// in [b*kCoulCap, (b+1)*kCoulCap); it orders up to kCoulMaxE slots in LDS.
+constexpr int kCoulCap = 256;
+constexpr int kCoulMaxE = 1024;
 
 // Error bits raised by kernels (read back with the tallies).
 enum : uint32_t { ERR_COUL_OVERFLOW = 1 };
 
 struct DevAccum {
-  ecr_tallies t;        // steps field unused on the device
-  uint32_t err;         // ERR_* bits
+  ecr_tallies t;           // steps field unused on the device
+  uint32_t err;            // ERR_* bits
   uint32_t pad[63];
 };
+
+// one Coulomb work item of a chunk: chunk-relative slots a, b (and c for an
+// odd pool's triplet), the pool size m and the id of a; a chunk owns
+// kCoulItems items
+struct CoulItem {
+  uint16_t a, b, c, m;
+  uint32_t id;
+};
+constexpr int kCoulItems = kCoulMaxE / 2;
 
 template <typename R>
 void launch_init(const KParams &P, Soa<R> S, hipStream_t st);
 
+// push + wall/aperture + MCC; also deposits when dens != nullptr
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
-                 DevAccum *acc, uint32_t step, hipStream_t st);
+                 DevAccum *acc, double *dens, uint32_t step, hipStream_t st);
 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st);
 
+// Coulomb chunk table: chunk b covers slots [chunk_lo[b], chunk_lo[b+1]),
+// nchunks+1 entries, rebuilt after every sort
+int64_t coul_nchunks(int64_t n);
+void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_t n, uint32_t *chunk_lo,
+                        hipStream_t st);
+
+// pairing (k_coul_order) then collisions (k_coul_pairs); items holds
+// kCoulItems entries per chunk, counts one (pairs, triplets) per chunk
+// moments: coul_moment_slots(n) x 5 doubles of per-wavefront momentum /
+// energy sums, reduced into the tallies by launch_sum_moments
 template <typename R>
 void launch_coulomb(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid,
-                    const uint32_t *cell_off, int64_t ncell, DevAccum *acc, uint32_t step, hipStream_t st);
+                    const uint32_t *chunk_lo, DevAccum *acc, CoulItem *items, uint2 *counts, double *moments,
+                    uint32_t step, hipStream_t st);
+int64_t coul_moment_slots(int64_t n);
+void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hipStream_t st);
 
 // sort by cell: keys either from positions or (given != nullptr) from given[pid]
 template <typename R>

@@ -9,28 +9,33 @@
 // dt/2 each, in that order, then (3,4),...  Each pair draws its two uniforms
 // from the COUL stream of its first member.
 //
-// GPU mapping: workgroup b owns the cells whose first slot lies in
-// [b*kCoulCap, (b+1)*kCoulCap) (found by binary search on cell_off, so no
-// chunk table is needed).  It sorts the composite keys
-// (cell, not-in-pool, random key, id) of its slots in LDS with a bitonic
-// network, which groups each pool in pairing order; pools are then found by
-// binary search in the sorted keys, and one lane per pair (or per triplet)
-// applies the collision to the velocities in HBM.  Pairs are disjoint, so no
-// two lanes touch the same particle.
+// Two kernels per step:
+//  * k_coul_order: workgroup b owns the cells whose first slot lies in
+//    [b*kCoulCap, (b+1)*kCoulCap) (slot ranges tabulated once per sort by
+//    k_coul_chunks).  The chunk's slots are already grouped by cell, so the
+//    pool order is found per cell without a general sort: a cell of m slots
+//    gets B = 2^ceil(log2 m) buckets on the top bits of the uniform keys
+//    (about one member per bucket); an LDS histogram and scan place the
+//    members bucket by bucket, and a member's exact position is its bucket
+//    offset plus the number of bucket mates with a smaller (key, id).  Each
+//    pair leader writes (slot a, slot b, pool size) into the chunk's own
+//    region of the work list (pairs first, then the odd pools' triplets), and
+//    the chunk's counts go to a per-chunk array: no global atomics.
+//  * k_coul_pairs: one lane per work item (wavefront (b, y) takes items
+//    64y..64y+63 of chunk b), one collision or one triplet's three in
+//    sequence, with no LDS and no barriers, so the long dependent FP64 chains
+//    and scattered loads of the collisions are all in flight at once.  Pairs
+//    are disjoint, so no two lanes touch one particle, and the item order
+//    (set by LDS atomics) does not change results.
 #include "ecr_kernels.hpp"
 
 namespace ecr {
 
+// one binary collision of slots ia, ib with time step dtp and pool density
+// nc; acc gathers the momentum / energy change and the energy of the pool
+// before (count_e0_*: count this member's energy)
 template <typename R>
-struct PairAcc {
-  double dp[3];
-  double de;
-  double e0;
-};
-
-// one binary collision of slots ia, ib with time step dtp and pool density nc
-template <typename R>
-__device__ __forceinline__ void collide(const KParams &P, const Tables *__restrict__ T, Soa<R> S, uint32_t ia,
+__device__ __forceinline__ void collide(const KParams &P, const double *__restrict__ lnA, Soa<R> S, uint32_t ia,
                                         uint32_t ib, uint32_t id_a, double nc, double dtp, uint32_t step,
                                         double acc[5], bool count_e0_a, bool count_e0_b) {
   const uint4 W = draw(P, id_a, step, S_COUL, 0);
@@ -52,7 +57,7 @@ __device__ __forceinline__ void collide(const KParams &P, const Tables *__restri
   const double num = ((P.Cs * (qq * qq)) * nc) * dtp;
   const double den = (mu * mu) * ((double)g2 * (double)g);
   const double sv = num / den;
-  const R omc = (R)nanbu_omc(T->lnA, sv, u);
+  const R omc = (R)nanbu_omc(lnA, sv, u);
   const R sinchi = sqrt(omc * ((R)2 - omc));
   R sp, cp;
   sincos_r((R)(2.0 * kPi * u2), &sp, &cp);
@@ -85,159 +90,323 @@ __device__ __forceinline__ void collide(const KParams &P, const Tables *__restri
   acc[3] += (ea1 - ea) + (eb1 - eb);
 }
 
-__device__ __forceinline__ bool key_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
-  return ka < kb || (ka == kb && ia < ib);
+constexpr int kCB = 256;               // lanes per ordering workgroup
+constexpr int kEPT = kCoulMaxE / kCB;  // slots per lane at most
+
+struct CoulShared {
+  uint64_t skey[kCoulMaxE];         // (key << 32) | id, in slot order
+  uint32_t r1[2 * kCoulMaxE + 2];   // cell flags and scan scratch, then the bucket histogram
+  uint32_t cellv[kCoulMaxE];        // collision cell of each slot
+  uint16_t hd[kCoulMaxE];           // cell (head) index of each slot of the chunk
+  uint16_t hstart[kCoulMaxE + 1];   // first slot of each cell
+  uint16_t hbase[kCoulMaxE + 1];    // first bucket of each cell
+  uint8_t hlog[kCoulMaxE];          // log2 of the cell's bucket count
+  uint16_t ord[kCoulMaxE];          // members bucket by bucket
+  uint32_t npair, ntri;
+  uint32_t wsum[kCB / 64];
+};
+
+// in-place exclusive scan of a[0..L) by the workgroup; returns the total
+__device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum) {
+  const int tid = threadIdx.x;
+  const int per = (L + kCB - 1) / kCB;
+  const int b = tid * per, e = min(b + per, L);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += a[i];
+  const int lane = tid & 63, w = tid >> 6;
+  uint32_t x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t woff = 0, tot = 0;
+  for (int q = 0; q < kCB / 64; ++q) {
+    if (q < w) woff += wsum[q];
+    tot += wsum[q];
+  }
+  uint32_t run = woff + x - s;
+  for (int i = b; i < e; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// slot range of every chunk: the first slot of the first cell starting at or
+// after b*kCoulCap (the cell holding that slot if it starts there, else the
+// next one)
+__global__ void k_coul_chunks(const uint32_t *__restrict__ cellid, const uint32_t *__restrict__ cell_off, int64_t n,
+                              int64_t nchunks, uint32_t *__restrict__ chunk_lo) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nchunks) return;
+  const int64_t t = b * kCoulCap;
+  if (t >= n) {
+    chunk_lo[b] = (uint32_t)n;
+    return;
+  }
+  const uint32_t c = cellid[t];
+  const uint32_t st = cell_off[c];
+  chunk_lo[b] = st == (uint32_t)t ? (uint32_t)t : cell_off[c + 1];
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_coulomb(KParams P, const Tables *__restrict__ T, Soa<R> S,
-                                                 const uint32_t *__restrict__ cellid,
-                                                 const uint32_t *__restrict__ cell_off, int64_t ncell,
-                                                 DevAccum *__restrict__ accum, uint32_t step) {
-  __shared__ uint64_t skey[kCoulMaxE];
-  __shared__ uint32_t sid[kCoulMaxE];
-  __shared__ uint32_t sslot[kCoulMaxE];
-  __shared__ int64_t srange[2];
-  __shared__ double sred[5][4];
-  const int tid = threadIdx.x, bs = blockDim.x;
-  const int64_t n = P.n;
-  if (tid == 0) {
-    const int64_t b = blockIdx.x;
-    const int64_t t_lo = b * kCoulCap;
-    const int64_t t_hi = t_lo + kCoulCap < n ? t_lo + kCoulCap : n;
-    // first cell whose start offset is >= target (cell_off has ncell+1 entries)
-    int64_t lo = 0, hi = ncell + 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if ((int64_t)cell_off[mid] < t_lo) lo = mid + 1; else hi = mid;
-    }
-    const int64_t c_lo = lo;
-    lo = c_lo;
-    hi = ncell + 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if ((int64_t)cell_off[mid] < t_hi) lo = mid + 1; else hi = mid;
-    }
-    const int64_t c_hi = lo;
-    srange[0] = c_lo <= ncell ? cell_off[c_lo] : n;
-    srange[1] = c_hi <= ncell ? cell_off[c_hi] : n;
-    if (t_hi >= n) srange[1] = n;
-  }
-  __syncthreads();
-  const int64_t s_lo = srange[0];
-  const int64_t ns = srange[1] - s_lo;
+__global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const uint32_t *__restrict__ cellid,
+                                                    const uint32_t *__restrict__ chunk_lo,
+                                                    DevAccum *__restrict__ accum, CoulItem *__restrict__ items,
+                                                    uint2 *__restrict__ counts, uint32_t step) {
+  __shared__ CoulShared sh;
+  const int tid = threadIdx.x;
+  const int64_t s_lo = chunk_lo[blockIdx.x];
+  const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
   if (ns <= 1) return;
   if (ns > kCoulMaxE) {
     if (tid == 0) atomicOr(&accum->err, ERR_COUL_OVERFLOW);
     return;
   }
-  int p2 = 2;
-  while (p2 < ns) p2 <<= 1;
-  for (int i = tid; i < p2; i += bs) {
+  uint32_t *flags = sh.r1;
+  if (tid == 0) {
+    sh.npair = 0u;
+    sh.ntri = 0u;
+  }
+  // 1. coalesced loads: cell, pool flag, pairing key
+  bool pool[kEPT];
+  uint32_t key[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    pool[k] = false;
+    key[k] = 0;
     if (i < ns) {
       const int64_t j = s_lo + i;
       const uint32_t id = S.pid[j];
-      const bool pool = q_of(S.qs[j]) >= 1;
-      const uint4 W = draw(P, id, step, S_STEP, 0);
-      skey[i] = ((uint64_t)cellid[j] << 33) | ((uint64_t)(pool ? 0u : 1u) << 32) | (uint64_t)W.z;
-      sid[i] = id;
-      sslot[i] = (uint32_t)j;
-    } else {
-      skey[i] = ~0ull;
-      sid[i] = 0xFFFFFFFFu;
-      sslot[i] = 0;
+      pool[k] = q_of(S.qs[j]) >= 1;
+      if (pool[k]) key[k] = draw(P, id, step, S_STEP, 0).z;
+      sh.skey[i] = ((uint64_t)key[k] << 32) | id;
+      sh.cellv[i] = cellid[j];
     }
   }
   __syncthreads();
-  // bitonic sort ascending on (key, id)
-  for (int k = 2; k <= p2; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int i = tid; i < p2; i += bs) {
-        const int l = i ^ jj;
-        if (l > i) {
-          const uint64_t ka = skey[i], kb = skey[l];
-          const uint32_t ia = sid[i], ib = sid[l];
-          const bool up = (i & k) == 0;
-          const bool swap = up ? key_less(kb, ib, ka, ia) : key_less(ka, ia, kb, ib);
-          if (swap) {
-            skey[i] = kb;
-            skey[l] = ka;
-            sid[i] = ib;
-            sid[l] = ia;
-            const uint32_t t = sslot[i];
-            sslot[i] = sslot[l];
-            sslot[l] = t;
-          }
-        }
-      }
-      __syncthreads();
+  // 2. cells of the chunk: heads, cell index of every slot, first slot of every cell
+  uint32_t fl[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    fl[k] = (i < ns && (i == 0 || sh.cellv[i] != sh.cellv[i - 1])) ? 1u : 0u;
+    if (i < ns) flags[i] = fl[k];
+  }
+  __syncthreads();
+  const int nheads = (int)wg_exscan(flags, ns, sh.wsum);
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    if (i < ns) {
+      const int h = (int)(flags[i] + fl[k]) - 1;
+      sh.hd[i] = (uint16_t)h;
+      if (fl[k]) sh.hstart[h] = (uint16_t)i;
     }
   }
+  if (tid == 0) sh.hstart[nheads] = (uint16_t)ns;
+  __syncthreads();
+  // 3. buckets per cell: B = 2^ceil(log2(slots of the cell))
+  for (int h = tid; h < nheads; h += kCB) {
+    const int m = sh.hstart[h + 1] - sh.hstart[h];
+    const int lg = m <= 1 ? 0 : 32 - __clz(m - 1);
+    sh.hlog[h] = (uint8_t)lg;
+    sh.r1[h] = 1u << lg;
+  }
+  __syncthreads();
+  const int nbuckets = (int)wg_exscan(sh.r1, nheads, sh.wsum);
+  for (int h = tid; h < nheads; h += kCB) sh.hbase[h] = (uint16_t)sh.r1[h];
+  if (tid == 0) sh.hbase[nheads] = (uint16_t)nbuckets;
+  __syncthreads();
+  // 4-5. histogram of the pool members over their cell's buckets
+  uint32_t *hist = sh.r1;
+  for (int i = tid; i <= nbuckets; i += kCB) hist[i] = 0u;
+  __syncthreads();
+  int bk[kEPT], arr[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    bk[k] = 0;
+    arr[k] = 0;
+    if (i < ns && pool[k]) {
+      const int h = sh.hd[i];
+      const int lg = sh.hlog[h];
+      bk[k] = sh.hbase[h] + (lg ? (int)(key[k] >> (32 - lg)) : 0);
+      arr[k] = (int)atomicAdd(&hist[bk[k]], 1u);
+    }
+  }
+  __syncthreads();
+  // 6-7. bucket offsets, members listed bucket by bucket
+  const int npool = (int)wg_exscan(hist, nbuckets, sh.wsum);
+  if (tid == 0) hist[nbuckets] = (uint32_t)npool;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    if (i < ns && pool[k]) sh.ord[hist[bk[k]] + arr[k]] = (uint16_t)i;
+  }
+  __syncthreads();
+  // 8. exact pool position: bucket offset + bucket mates with a smaller (key, id)
+  int pos[kEPT], rr[kEPT], mm[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    pos[k] = rr[k] = mm[k] = 0;
+    if (i < ns && pool[k]) {
+      const uint64_t me = sh.skey[i];
+      const int b0 = (int)hist[bk[k]], b1 = (int)hist[bk[k] + 1];
+      int rib = 0;
+      for (int t = b0; t < b1; ++t) rib += sh.skey[sh.ord[t]] < me ? 1 : 0;
+      pos[k] = b0 + rib;
+      const int h = sh.hd[i];
+      const int pstart = (int)hist[sh.hbase[h]];
+      const int pend = (int)hist[sh.hbase[h] + (1 << sh.hlog[h])];
+      mm[k] = pend - pstart;
+      rr[k] = pos[k] - pstart;
+    }
+  }
+  __syncthreads();
+  // 9. pool order (element of every pool position)
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    if (i < ns && pool[k]) sh.ord[pos[k]] = (uint16_t)i;
+  }
+  __syncthreads();
+  // 10. pair leaders write their work items into the chunk's own list region:
+  //     pairs first, then the odd pools' triplets (order within each part is
+  //     that of LDS atomics; the items are disjoint, so it does not matter)
+  int lt[kEPT], li[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    lt[k] = 0;
+    li[k] = 0;
+    if (i < ns && pool[k]) {
+      const int m = mm[k], r = rr[k];
+      if (m >= 2) {
+        if ((m & 1) && r == 0) lt[k] = 2;                              // triplet
+        else if ((m & 1) ? (r >= 3 && (r & 1)) : !(r & 1)) lt[k] = 1;  // pair
+      }
+      if (lt[k] == 1) li[k] = (int)atomicAdd(&sh.npair, 1u);
+      if (lt[k] == 2) li[k] = (int)atomicAdd(&sh.ntri, 1u);
+    }
+  }
+  __syncthreads();
+  const int np = (int)sh.npair;
+  CoulItem *out = items + (int64_t)blockIdx.x * kCoulItems;
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    if (lt[k]) {
+      const int p = pos[k];
+      CoulItem e;
+      e.a = sh.ord[p];
+      e.b = sh.ord[p + 1];
+      e.c = lt[k] == 2 ? sh.ord[p + 2] : (uint16_t)0;
+      e.m = (uint16_t)mm[k];
+      e.id = (uint32_t)sh.skey[e.a];
+      out[lt[k] == 1 ? li[k] : np + li[k]] = e;
+    }
+  }
+  if (tid == 0) counts[blockIdx.x] = make_uint2((uint32_t)np, sh.ntri);
+}
+
+// collisions: wavefront (b, y) takes items y*64 .. y*64+63 of chunk b, one
+// per lane, so that every collision of the step is in flight at once
+template <typename R>
+__global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
+                                                   const uint32_t *__restrict__ chunk_lo,
+                                                   const CoulItem *__restrict__ items,
+                                                   const uint2 *__restrict__ counts, double *__restrict__ moments,
+                                                   uint32_t step) {
+  const int64_t b = blockIdx.x;
+  const int64_t s_lo = chunk_lo[b];
+  const int ns = (int)((int64_t)chunk_lo[b + 1] - s_lo);
+  if (ns <= 1 || ns > kCoulMaxE) return;  // no pool, or skipped by the ordering (overflow flagged there)
+  const uint2 cnt = counts[b];
+  const int np = (int)cnt.x, total = (int)(cnt.x + cnt.y);
+  if ((int)blockIdx.y * 64 >= total) return;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = tid; i < ns; i += bs) {
-    const uint64_t key = skey[i];
-    if ((key >> 32) & 1ull) continue;  // atom: not in any pool
-    const uint64_t cbase = (key >> 33) << 33;
-    // pool start: first entry with key >= cbase; pool end: first with key >= cbase | 1<<32
-    int lo = 0, hi = i;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (skey[mid] < cbase) lo = mid + 1; else hi = mid;
-    }
-    const int start = lo;
-    const uint64_t cend = cbase | (1ull << 32);
-    lo = i + 1;
-    hi = (int)ns;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (skey[mid] < cend) lo = mid + 1; else hi = mid;
-    }
-    const int m = lo - start;
-    const int r = i - start;
-    if (m < 2) continue;
-    const double nc = (double)m * P.nfac;
-    if (m & 1) {
-      if (r == 0) {
-        const double h = 0.5 * P.dt;
-        const uint32_t s0 = sslot[i], s1 = sslot[i + 1], s2 = sslot[i + 2];
-        collide<R>(P, T, S, s0, s1, sid[i], nc, h, step, acc, true, true);
-        collide<R>(P, T, S, s1, s2, sid[i + 1], nc, h, step, acc, false, true);
-        collide<R>(P, T, S, s2, s0, sid[i + 2], nc, h, step, acc, false, false);
-      } else if (r >= 3 && (r & 1)) {
-        collide<R>(P, T, S, sslot[i], sslot[i + 1], sid[i], nc, P.dt, step, acc, true, true);
-      }
-    } else if (!(r & 1)) {
-      collide<R>(P, T, S, sslot[i], sslot[i + 1], sid[i], nc, P.dt, step, acc, true, true);
+  const int q = (int)blockIdx.y * 64 + (int)threadIdx.x;
+  if (q < total) {
+    // a pair is one collision; an odd pool's triplet is (a,b), (b,c), (c,a)
+    // with dt/2 each, in sequence (one call site keeps the register count down)
+    const bool tri = q >= np;
+    const CoulItem e = items[b * kCoulItems + q];
+    const double nc = (double)e.m * P.nfac, dtp = tri ? 0.5 * P.dt : P.dt;
+    for (int c = 0; c < (tri ? 3 : 1); ++c) {
+      const uint32_t ia = (uint32_t)s_lo + (c == 0 ? e.a : (c == 1 ? e.b : e.c));
+      const uint32_t ib = (uint32_t)s_lo + (c == 0 ? e.b : (c == 1 ? e.c : e.a));
+      collide<R>(P, T->lnA, S, ia, ib, c == 0 ? e.id : S.pid[ia], nc, dtp, step, acc, c == 0, c < 2);
     }
   }
-  // workgroup reduction of the moment changes, then one atomic per quantity
-  for (int q = 0; q < 5; ++q) {
-    double v = acc[q];
+  // each wavefront owns one slot of the moment buffer: plain read-add-write,
+  // no contended atomics (summed in a fixed order when tallies are read)
+  double *slot = moments + (b * (kCoulItems / 64) + blockIdx.y) * 5;
+  for (int k = 0; k < 5; ++k) {
+    double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((tid & 63) == 0) sred[q][tid >> 6] = v;
+    if (threadIdx.x == 0 && v != 0.0) slot[k] += v;
   }
+}
+
+// fixed-order sum of the per-wavefront moment slots into the tallies
+__global__ void __launch_bounds__(256) k_sum_moments(const double *__restrict__ moments, int64_t nslots,
+                                                     DevAccum *__restrict__ accum) {
+  __shared__ double red[5][256];
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < nslots; i += 256)
+    for (int k = 0; k < 5; ++k) s[k] += moments[i * 5 + k];
+  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = s[k];
   __syncthreads();
-  if (tid < 5) {
-    double v = 0.0;
-    for (int w = 0; w < (bs + 63) / 64; ++w) v += sred[tid][w];
-    if (v != 0.0) {
-      double *dst = tid < 3 ? &accum->t.coul_dp[tid] : (tid == 3 ? &accum->t.coul_de : &accum->t.coul_e);
-      atomicAdd(dst, v);
-    }
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    accum->t.coul_dp[0] = red[0][0];
+    accum->t.coul_dp[1] = red[1][0];
+    accum->t.coul_dp[2] = red[2][0];
+    accum->t.coul_de = red[3][0];
+    accum->t.coul_e = red[4][0];
+  }
+}
+
+int64_t coul_moment_slots(int64_t n) { return ((n + kCoulCap - 1) / kCoulCap) * (kCoulItems / 64); }
+
+void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_moments, dim3(1), dim3(256), 0, st, moments, nslots, acc);
+}
+
+int64_t coul_nchunks(int64_t n) { return (n + kCoulCap - 1) / kCoulCap; }
+
+void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_t n, uint32_t *chunk_lo,
+                        hipStream_t st) {
+  const int64_t nc = coul_nchunks(n);
+  hipLaunchKernelGGL(k_coul_chunks, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, cellid, cell_off, n, nc,
+                     chunk_lo);
 }
 
 template <typename R>
-void launch_coulomb(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *cell_off,
-                    int64_t ncell, DevAccum *acc, uint32_t step, hipStream_t st) {
+void launch_coulomb(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
+                    DevAccum *acc, CoulItem *items, uint2 *counts, double *moments, uint32_t step,
+                    hipStream_t st) {
   if (P.n <= 1) return;
-  const unsigned nb = (unsigned)((P.n + kCoulCap - 1) / kCoulCap);
-  hipLaunchKernelGGL(k_coulomb<R>, dim3(nb), dim3(256), 0, st, P, T, S, cellid, cell_off, ncell, acc, step);
+  const unsigned nc = (unsigned)coul_nchunks(P.n);
+  hipLaunchKernelGGL(k_coul_order<R>, dim3(nc), dim3(kCB), 0, st, P, S, cellid, chunk_lo, acc, items, counts, step);
+  hipLaunchKernelGGL(k_coul_pairs<R>, dim3(nc, kCoulItems / 64), dim3(64), 0, st, P, T, S, chunk_lo, items, counts,
+                     moments, step);
 }
 
-template void launch_coulomb<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *,
-                                     const uint32_t *, int64_t, DevAccum *, uint32_t, hipStream_t);
+template void launch_coulomb<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *, const uint32_t *,
+                                     DevAccum *, CoulItem *, uint2 *, double *, uint32_t, hipStream_t);
 template void launch_coulomb<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const uint32_t *,
-                                    int64_t, DevAccum *, uint32_t, hipStream_t);
+                                    DevAccum *, CoulItem *, uint2 *, double *, uint32_t, hipStream_t);
 
 }  // namespace ecr

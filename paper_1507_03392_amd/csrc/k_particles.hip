@@ -1,14 +1,21 @@
 // k_particles.hip -- per-particle kernels of the ion step (Mironov et al.,
-// Sec. II): initial ions, the push / wall-aperture / Monte-Carlo-collision
-// kernel, and the cloud-in-cell deposit.
+// Sec. II): initial ions, and the kernel that pushes each particle, applies
+// the wall / aperture loss, draws ionisation or charge exchange, and
+// deposits it on the density mesh.
 //
-// Layout: structure of arrays in HBM, one lane per particle slot, so every
-// load and store of x, y, z, vx, vy, vz, qs and pid is a fully coalesced
-// 64-lane access.  Slots are in cell order (sorted every sort_every steps),
-// which keeps the deposit's atomics and the field-table reads local.
+// Layout: structure of arrays in HBM, one lane per slot, so every load and
+// store of a wavefront is 64 consecutive elements.  A workgroup covers a tile
+// of kP x 256 slots.  Slots are in cell order (sorted every sort_every steps),
+// which the deposit exploits (see deposit_staged): it takes the deposit from
+// 16 contended global atomics per particle to a few per workgroup.
 #include "ecr_kernels.hpp"
 
 namespace ecr {
+
+constexpr int kP = 4;                // consecutive slots per lane
+constexpr int kBlock = 256;          // lanes per workgroup
+constexpr int kTile = kBlock * kP;   // slots per workgroup
+constexpr int kBrickNodes = 1536;    // LDS brick capacity in nodes (x 3 fields)
 
 // ---------------------------------------------------------------------------
 // Initial ions: uniform in the ECR-zone ellipsoid by rejection sampling in
@@ -56,22 +63,14 @@ __global__ void __launch_bounds__(256) k_init(KParams P, Soa<R> S) {
 }
 
 // ---------------------------------------------------------------------------
-// Push -> wall/aperture -> ionisation / charge exchange, one particle per
-// lane.  Tallies are rare events (~1e-4 per particle-step) and go straight
-// to 64-bit global atomics.
+// One particle: push -> wall/aperture -> ionisation / charge exchange.
+// Tallies are rare events (~1e-4 per particle-step) and go straight to
+// 64-bit global atomics.  Returns the event code.
 // ---------------------------------------------------------------------------
 template <typename R, bool HAS_E>
-__global__ void __launch_bounds__(256) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
-                                              const double *__restrict__ ef, uint8_t *__restrict__ evlog,
-                                              DevAccum *__restrict__ acc, uint32_t step) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P.n) return;
-  R x = S.x[j], y = S.y[j], z = S.z[j];
-  R vx = S.vx[j], vy = S.vy[j], vz = S.vz[j];
-  const uint8_t qs0 = S.qs[j];
-  const uint32_t id = S.pid[j];
-  int Q = q_of(qs0);
-  const int s = sp_of(qs0);
+__device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
+                                           const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
+                                           uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz) {
   uint8_t ev = EV_NONE;
   if (P.pmask & P_PUSH) {
     const R x0 = x, y0 = y, z0 = z;
@@ -120,49 +119,257 @@ __global__ void __launch_bounds__(256) k_push(KParams P, const Tables *__restric
   }
   if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) && isfinite(vz)))
     atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
-  S.x[j] = x;
-  S.y[j] = y;
-  S.z[j] = z;
-  S.vx[j] = vx;
-  S.vy[j] = vy;
-  S.vz[j] = vz;
-  S.qs[j] = make_qs(Q, s);
-  if (evlog) evlog[j] = ev;
+  return ev;
 }
 
 // ---------------------------------------------------------------------------
-// Cloud-in-cell deposit of ion number, ion charge and atom number onto the
-// (nx+1)(ny+1)(nz+1) node grid, FP64 global atomics.
+// Cloud-in-cell deposit of a tile onto the (nx+1)(ny+1)(nz+1) node grid:
+// fields ion number (Q >= 1), ion charge (Q x weight) and atom number
+// (Q = 0), as enabled by the deposit mask.
+//
+// The push works on coalesced slots (lane = slot, kP rounds of 256).  Its
+// deposit inputs (lower node, fractional offsets, charge) are staged in LDS
+// and read back transposed, so that lane l owns the kP consecutive slots
+// kP*l .. kP*l+kP-1.  Consecutive slots share a cell almost always, so the
+// lane sums their weights in registers and flushes a run only when the cell
+// changes, into an LDS brick spanning the tile's nodes; the brick goes to HBM
+// with one FP64 atomic per touched node.  A tile whose nodes do not fit the
+// brick flushes its runs to HBM directly.
 // ---------------------------------------------------------------------------
+constexpr int kPad(int i) { return i + (i >> 2); }  // one pad slot every 4: fewer LDS bank conflicts
+constexpr int kStage = kPad(kTile);
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_deposit(KParams P, Soa<R> S, double *__restrict__ dens) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P.n) return;
-  const int Q = q_of(S.qs[j]);
-  const bool ion = Q >= 1;
-  const uint32_t dm = P.dmask;
-  if (!((ion && (dm & 3u)) || (!ion && (dm & 4u)))) return;
+struct DepStage {
+  R t[3][kStage];
+  uint16_t c[3][kStage];
+  uint8_t q[kStage];  // charge, or 0xFF: nothing to deposit
+};
+
+template <typename R>
+union DepShared {
+  DepStage<R> st;
+  double brick[3 * kBrickNodes];
+};
+
+template <typename R>
+struct DepIn {
+  int ix[kP], iy[kP], iz[kP], q[kP];
+  R tx[kP], ty[kP], tz[kP];
+  bool on[kP];
+};
+
+// sum the runs of equal base node held by this lane; flush(node, field, corner, value)
+template <typename R, typename NodeOf, typename Flush>
+__device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, NodeOf nodeof, Flush flush) {
+  double a[8], b[8], c[8];
+  int64_t cur = -1;
+  bool has_ion = false, has_atom = false;
+  auto emit = [&]() {
+    if (cur < 0) return;
+    for (int k = 0; k < 8; ++k) {
+      if (has_ion && (dm & 1u)) flush(cur, 0, k, a[k]);
+      if (has_ion && (dm & 2u)) flush(cur, 1, k, b[k]);
+      if (has_atom && (dm & 4u)) flush(cur, 2, k, c[k]);
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    if (!D.on[p]) continue;
+    const int64_t node = nodeof(D.ix[p], D.iy[p], D.iz[p]);
+    if (node != cur) {
+      emit();
+      cur = node;
+      has_ion = has_atom = false;
+      for (int k = 0; k < 8; ++k) a[k] = b[k] = c[k] = 0.0;
+    }
+    const R wx[2] = {(R)1 - D.tx[p], D.tx[p]}, wy[2] = {(R)1 - D.ty[p], D.ty[p]};
+    const R wz[2] = {(R)1 - D.tz[p], D.tz[p]};
+    const bool ion = D.q[p] >= 1;
+    const double qd = (double)D.q[p];
+    int k = 0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx, ++k) {
+          const double w = (double)((wx[dx] * wy[dy]) * wz[dz]);
+          if (ion) {
+            a[k] += w;
+            b[k] += qd * w;
+          } else {
+            c[k] += w;
+          }
+        }
+    has_ion |= ion;
+    has_atom |= !ion;
+  }
+  emit();
+}
+
+// stage the deposit input of tile slot i (lane = slot layout)
+template <typename R>
+__device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int i, R x, R y, R z, int q, int mn[3],
+                                          int mx[3]) {
   int ix, iy, iz;
   R tx, ty, tz;
-  cic_axis<R>(S.x[j], (R)P.R0, (R)P.idx, P.nx, ix, tx);
-  cic_axis<R>(S.y[j], (R)P.R0, (R)P.idy, P.ny, iy, ty);
-  cic_axis<R>(S.z[j], (R)P.hL, (R)P.idz, P.nz, iz, tz);
-  const R wx[2] = {(R)1 - tx, tx}, wy[2] = {(R)1 - ty, ty}, wz[2] = {(R)1 - tz, tz};
-  for (int dz = 0; dz < 2; ++dz)
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx) {
-        const int64_t node = (int64_t)(ix + dx) + (int64_t)P.nx1 * ((iy + dy) + (int64_t)P.ny1 * (iz + dz));
-        const double w = (double)((wx[dx] * wy[dy]) * wz[dz]);
-        if (ion) {
-          if (dm & 1u) atomicAdd(&dens[node], w);
-          if (dm & 2u) atomicAdd(&dens[P.nnode + node], (double)Q * w);
-        } else {
-          atomicAdd(&dens[2 * P.nnode + node], w);
-        }
-      }
+  cic_axis<R>(x, (R)P.R0, (R)P.idx, P.nx, ix, tx);
+  cic_axis<R>(y, (R)P.R0, (R)P.idy, P.ny, iy, ty);
+  cic_axis<R>(z, (R)P.hL, (R)P.idz, P.nz, iz, tz);
+  const uint32_t dm = P.dmask;
+  const bool on = (q >= 1) ? (dm & 3u) != 0 : (dm & 4u) != 0;
+  const int k = kPad(i);
+  st.t[0][k] = tx;
+  st.t[1][k] = ty;
+  st.t[2][k] = tz;
+  st.c[0][k] = (uint16_t)ix;
+  st.c[1][k] = (uint16_t)iy;
+  st.c[2][k] = (uint16_t)iz;
+  st.q[k] = on ? (uint8_t)q : (uint8_t)0xFF;
+  if (on) {
+    mn[0] = min(mn[0], ix);
+    mn[1] = min(mn[1], iy);
+    mn[2] = min(mn[2], iz);
+    mx[0] = max(mx[0], ix);
+    mx[1] = max(mx[1], iy);
+    mx[2] = max(mx[2], iz);
+  }
 }
 
-static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// deposit a staged tile; every lane of the workgroup must call it
+template <typename R>
+__device__ __forceinline__ void deposit_staged(const KParams &P, double *__restrict__ dens, DepShared<R> &sh,
+                                               int *box, int mn[3], int mx[3]) {
+  const int tid = threadIdx.x;
+  const uint32_t dm = P.dmask;
+  for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
+      mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
+    }
+  if ((tid & 63) == 0)
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&box[d], mn[d]);
+      atomicMax(&box[3 + d], mx[d]);
+    }
+  __syncthreads();  // staging and box complete
+  DepIn<R> D;
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    const int k = kPad(tid * kP + p);
+    const uint8_t q = sh.st.q[k];
+    D.on[p] = q != 0xFF;
+    D.q[p] = q;
+    D.tx[p] = sh.st.t[0][k];
+    D.ty[p] = sh.st.t[1][k];
+    D.tz[p] = sh.st.t[2][k];
+    D.ix[p] = sh.st.c[0][k];
+    D.iy[p] = sh.st.c[1][k];
+    D.iz[p] = sh.st.c[2][k];
+  }
+  const int x0 = box[0], y0 = box[1], z0 = box[2];
+  const bool any = box[3] >= 0;
+  const int bx = box[3] - x0 + 2, by = box[4] - y0 + 2, bz = box[5] - z0 + 2;
+  __syncthreads();  // staging read: the brick may now reuse it
+  if (!any) return;
+  const int64_t nodes = (int64_t)bx * by * bz;
+  if (nodes <= kBrickNodes) {
+    const int nb = (int)nodes;
+    for (int i = tid; i < 3 * nb; i += kBlock) sh.brick[i] = 0.0;
+    __syncthreads();
+    double *br = sh.brick;
+    run_accumulate<R>(
+        D, dm,
+        [&](int ix, int iy, int iz) -> int64_t { return (int64_t)((ix - x0) + bx * ((iy - y0) + by * (iz - z0))); },
+        [&](int64_t base, int f, int k, double v) {
+          const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+          atomicAdd(&br[f * nb + (int)base + dx + bx * (dy + by * dz)], v);
+        });
+    __syncthreads();
+    for (int i = tid; i < 3 * nb; i += kBlock) {
+      const double v = sh.brick[i];
+      if (v != 0.0) {
+        const int f = i / nb, li = i - f * nb;
+        const int lx = li % bx, ly = (li / bx) % by, lz = li / (bx * by);
+        const int64_t node = (int64_t)(x0 + lx) + (int64_t)P.nx1 * ((y0 + ly) + (int64_t)P.ny1 * (z0 + lz));
+        unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + node], v);
+      }
+    }
+  } else {
+    const int nx1 = P.nx1, ny1 = P.ny1;
+    run_accumulate<R>(
+        D, dm,
+        [&](int ix, int iy, int iz) -> int64_t { return (int64_t)ix + (int64_t)nx1 * (iy + (int64_t)ny1 * iz); },
+        [&](int64_t base, int f, int k, double v) {
+          const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+          unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + base + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz)], v);
+        });
+  }
+}
+
+__device__ __forceinline__ void box_init(int *box) {
+  if (threadIdx.x < 6) box[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -1;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Push + wall/aperture + MCC (+ deposit): slot j = tile + tid + 256 p.
+// ---------------------------------------------------------------------------
+template <typename R, bool HAS_E, bool DEP>
+__global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
+                                                 const double *__restrict__ ef, uint8_t *__restrict__ evlog,
+                                                 DevAccum *__restrict__ acc, double *__restrict__ dens,
+                                                 uint32_t step) {
+  __shared__ DepShared<R> sh;
+  __shared__ int box[6];
+  if (DEP) box_init(box);
+  int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    const int i = threadIdx.x + p * kBlock;
+    const int64_t j = base + i;
+    if (j >= P.n) {
+      if (DEP) sh.st.q[kPad(i)] = 0xFF;
+      continue;
+    }
+    R x = S.x[j], y = S.y[j], z = S.z[j];
+    R vx = S.vx[j], vy = S.vy[j], vz = S.vz[j];
+    const uint8_t qs0 = S.qs[j];
+    const uint32_t id = S.pid[j];
+    int Q = q_of(qs0);
+    const int s = sp_of(qs0);
+    const uint8_t ev = advance<R, HAS_E>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz);
+    S.x[j] = x;
+    S.y[j] = y;
+    S.z[j] = z;
+    S.vx[j] = vx;
+    S.vy[j] = vy;
+    S.vz[j] = vz;
+    S.qs[j] = make_qs(Q, s);
+    if (evlog) evlog[j] = ev;
+    if (DEP) stage_cic<R>(P, sh.st, i, x, y, z, Q, mn, mx);
+  }
+  if (DEP) deposit_staged<R>(P, dens, sh, box, mn, mx);
+}
+
+// standalone deposit (same tile code), for per-kernel timing
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double *__restrict__ dens) {
+  __shared__ DepShared<R> sh;
+  __shared__ int box[6];
+  box_init(box);
+  int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    const int i = threadIdx.x + p * kBlock;
+    const int64_t j = base + i;
+    if (j < P.n) stage_cic<R>(P, sh.st, i, S.x[j], S.y[j], S.z[j], q_of(S.qs[j]), mn, mx);
+    else sh.st.q[kPad(i)] = 0xFF;
+  }
+  deposit_staged<R>(P, dens, sh, box, mn, mx);
+}
+
+static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 template <typename R>
 void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
@@ -172,27 +379,30 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
 
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog, DevAccum *acc,
-                 uint32_t step, hipStream_t st) {
+                 double *dens, uint32_t step, hipStream_t st) {
   if (P.n <= 0) return;
-  if (ef)
-    hipLaunchKernelGGL((k_push<R, true>), dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, T, S, ef, evlog, acc, step);
-  else
-    hipLaunchKernelGGL((k_push<R, false>), dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, T, S, ef, evlog, acc,
-                       step);
+  const dim3 g(grid_for(P.n, kTile)), b(kBlock);
+  if (ef) {
+    if (dens) hipLaunchKernelGGL((k_push<R, true, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
+    else hipLaunchKernelGGL((k_push<R, true, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
+  } else {
+    if (dens) hipLaunchKernelGGL((k_push<R, false, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
+    else hipLaunchKernelGGL((k_push<R, false, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
+  }
 }
 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {
   if (P.n <= 0) return;
-  hipLaunchKernelGGL(k_deposit<R>, dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, S, dens);
+  hipLaunchKernelGGL(k_deposit<R>, dim3(grid_for(P.n, kTile)), dim3(kBlock), 0, st, P, S, dens);
 }
 
 template void launch_init<double>(const KParams &, Soa<double>, hipStream_t);
 template void launch_init<float>(const KParams &, Soa<float>, hipStream_t);
 template void launch_push<double>(const KParams &, const Tables *, Soa<double>, const double *, uint8_t *, DevAccum *,
-                                  uint32_t, hipStream_t);
+                                  double *, uint32_t, hipStream_t);
 template void launch_push<float>(const KParams &, const Tables *, Soa<float>, const double *, uint8_t *, DevAccum *,
-                                 uint32_t, hipStream_t);
+                                 double *, uint32_t, hipStream_t);
 template void launch_deposit<double>(const KParams &, Soa<double>, double *, hipStream_t);
 template void launch_deposit<float>(const KParams &, Soa<float>, double *, hipStream_t);
 

@@ -29,7 +29,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t soa[2][8];  // offsets of x y z vx vy vz qs pid in buffer A and B
-  size_t key, rank, cellid, count, cell_off, bsum, dens, acc, tables, efield, evlog;
+  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, efield, evlog;
   size_t total;
 };
 
@@ -57,6 +57,14 @@ Layout make_layout(const ecr_params *p) {
   o = align_up(o + 4 * N);
   L.cellid = o;
   o = align_up(o + 4 * N);
+  L.chunks = o;
+  o = align_up(o + 4 * (size_t)(coul_nchunks((int64_t)N) + 2));
+  L.pairs = o;
+  o = align_up(o + sizeof(CoulItem) * kCoulItems * (size_t)coul_nchunks((int64_t)N));
+  L.tris = o;  // per-chunk (pairs, triplets) counts
+  o = align_up(o + 8 * (size_t)coul_nchunks((int64_t)N));
+  L.moments = o;
+  o = align_up(o + 8 * 5 * (size_t)coul_moment_slots((int64_t)N));
   L.count = o;
   o = align_up(o + 4 * (size_t)(ncells(p) + 1));
   L.cell_off = o;
@@ -405,6 +413,9 @@ void do_sort(ecr_run *r, const uint32_t *given) {
   launch_sort<R>(r->kp, soa<R>(r, a), soa<R>(r, b), given, at<uint32_t>(r, r->L.key), at<uint32_t>(r, r->L.rank),
                  at<uint32_t>(r, r->L.count), at<uint32_t>(r, r->L.cell_off), at<uint32_t>(r, r->L.bsum),
                  at<uint32_t>(r, r->L.cellid), r->ncell, r->stream);
+  if (r->kp.n > 0)
+    launch_coul_chunks(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off), r->kp.n,
+                       at<uint32_t>(r, r->L.chunks), r->stream);
   r->cur = b;
 }
 
@@ -420,19 +431,23 @@ void do_step(ecr_run *r) {
   const Tables *T = at<Tables>(r, r->L.tables);
   if (pm & ECR_P_COULOMB) {
     ProfScope ps(r, ECR_K_COULOMB);
-    launch_coulomb<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off),
-                      r->ncell, acc, stepw, r->stream);
+    launch_coulomb<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.chunks), acc,
+                      at<CoulItem>(r, r->L.pairs), at<uint2>(r, r->L.tris), at<double>(r, r->L.moments), stepw,
+                      r->stream);
   }
+  const bool dep = (pm & ECR_P_DEPOSIT) != 0;
+  const bool split = (r->p.flags & ECR_FLAG_SPLIT) != 0;
   {
-    ProfScope ps(r, ECR_K_PUSH);
+    ProfScope ps(r, (dep && !split) ? ECR_K_FUSED : ECR_K_PUSH);
     launch_push<R>(r->kp, T, soa<R>(r, r->cur), r->p.efield_nodes ? at<double>(r, r->L.efield) : nullptr,
-                   (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc, stepw, r->stream);
+                   (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc,
+                   (dep && !split) ? at<double>(r, r->L.dens) : nullptr, stepw, r->stream);
   }
-  if (pm & ECR_P_DEPOSIT) {
+  if (dep && split) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
-    r->dens_steps++;
   }
+  if (dep) r->dens_steps++;
   r->step++;
   r->steps++;
 }
@@ -440,6 +455,7 @@ void do_step(ecr_run *r) {
 void zero_accumulators(ecr_run *r) {
   launch_fill_f64(at<double>(r, r->L.dens), 0.0, (int64_t)ECR_N_FIELDS * r->nnode, r->stream);
   launch_fill_u32(at<uint32_t>(r, r->L.acc), 0u, (int64_t)(sizeof(DevAccum) / 4), r->stream);
+  launch_fill_f64(at<double>(r, r->L.moments), 0.0, 5 * coul_moment_slots(r->kp.n > 0 ? r->kp.n : 1), r->stream);
   r->steps = 0;
   r->dens_steps = 0;
 }
@@ -620,6 +636,8 @@ ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps,
 ecr_status ecr_read_tallies(ecr_run *r, ecr_tallies *out) {
   if (!r || !out) return fail(r, ECR_EINVAL, "NULL argument");
   DevAccum h;
+  launch_sum_moments(at<double>(r, r->L.moments), coul_moment_slots(r->kp.n > 0 ? r->kp.n : 1), at<DevAccum>(r, r->L.acc),
+                     r->stream);
   hipError_t e = hipMemcpyAsync(&h, at<DevAccum>(r, r->L.acc), sizeof(DevAccum), hipMemcpyDeviceToHost, r->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
   if (e != hipSuccess) return check_hip(r, e, "read_tallies");
