@@ -30,8 +30,10 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES_FP64 = {
     # read x, v, qs, pid; write x, v, qs
     "push": 48 + 1 + 4 + 48 + 1,
-    # read qs, pid, cell; read and write v (every slot counted)
-    "coulomb": 1 + 4 + 4 + 48 + 48,
+    # read qs, pid, cell; write one 12-byte work item per pair (half a particle)
+    "coul_order": 1 + 4 + 4 + 6,
+    # per particle (half a pair): read the item, both velocities and charges, write both velocities
+    "coul_pairs": 6 + 24 + 1 + 24,
     # read x, qs
     "deposit": 24 + 1,
     # count pass (read x; write key, rank) + scatter (read record, key, rank; write record, cell)
@@ -41,7 +43,8 @@ ALG_BYTES_FP64 = {
 }
 ALG_BYTES_FP32 = {
     "push": 24 + 1 + 4 + 24 + 1,
-    "coulomb": 1 + 4 + 4 + 24 + 24,
+    "coul_order": 1 + 4 + 4 + 6,
+    "coul_pairs": 6 + 12 + 1 + 12,
     "deposit": 12 + 1,
     "sort": (12 + 8) + (29 + 8) + (29 + 4),
     "push_deposit": 24 + 1 + 4 + 24 + 1,

@@ -191,12 +191,13 @@ ecr_status ecr_weight(const ecr_run *run, double *weight);
  * the run's stream; ecr_kernel_times returns, per kernel kind (ECR_K_*), the
  * summed milliseconds and the launch count since the last reset. */
 enum {
-  ECR_K_SORT = 0,    /* the sort by cell (count, scan, scatter) */
-  ECR_K_COULOMB = 1, /* Coulomb pairing and scattering */
-  ECR_K_PUSH = 2,    /* push + wall/aperture + ionisation/charge exchange */
-  ECR_K_DEPOSIT = 3, /* deposit alone (ECR_FLAG_SPLIT) */
-  ECR_K_FUSED = 4,   /* push + wall/aperture + ionisation/charge exchange + deposit in one kernel */
-  ECR_N_KERNELS = 5
+  ECR_K_SORT = 0,       /* the sort by cell (count, scan, scatter, chunk table) */
+  ECR_K_COULOMB = 1,    /* Coulomb pairing: pool order and pair lists */
+  ECR_K_PUSH = 2,       /* push + wall/aperture + ionisation/charge exchange */
+  ECR_K_DEPOSIT = 3,    /* deposit alone (ECR_FLAG_SPLIT) */
+  ECR_K_FUSED = 4,      /* push + wall/aperture + ionisation/charge exchange + deposit in one kernel */
+  ECR_K_COUL_PAIRS = 5, /* Coulomb scattering of the listed pairs */
+  ECR_N_KERNELS = 6
 };
 ecr_status ecr_profile(ecr_run *run, int32_t enable);
 ecr_status ecr_kernel_times(ecr_run *run, double *ms_out, int64_t *launches_out);

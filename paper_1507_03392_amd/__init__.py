@@ -21,8 +21,8 @@ FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL = 1, 2, 4, 8, 16, 31
 F_ION_N, F_ION_Q, F_ATOM_N, N_FIELDS = 0, 1, 2, 3
 FLAG_EVENTS, FLAG_SPLIT = 1, 2
-K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, N_KERNELS = 0, 1, 2, 3, 4, 5
-KERNEL_NAMES = ["sort", "coulomb", "push", "deposit", "push_deposit"]
+K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, N_KERNELS = 0, 1, 2, 3, 4, 5, 6
+KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_pairs"]
 
 STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4: "ECR_ESTATE",
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}

@@ -54,9 +54,11 @@ void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_
 // moments: coul_moment_slots(n) x 5 doubles of per-wavefront momentum /
 // energy sums, reduced into the tallies by launch_sum_moments
 template <typename R>
-void launch_coulomb(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid,
-                    const uint32_t *chunk_lo, DevAccum *acc, CoulItem *items, uint2 *counts, double *moments,
-                    uint32_t step, hipStream_t st);
+void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo, DevAccum *acc,
+                       CoulItem *items, uint2 *counts, uint32_t step, hipStream_t st);
+template <typename R>
+void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *chunk_lo, const CoulItem *items,
+                       const uint2 *counts, double *moments, uint32_t step, hipStream_t st);
 int64_t coul_moment_slots(int64_t n);
 void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hipStream_t st);
 

@@ -394,19 +394,28 @@ void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_
 }
 
 template <typename R>
-void launch_coulomb(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
-                    DevAccum *acc, CoulItem *items, uint2 *counts, double *moments, uint32_t step,
-                    hipStream_t st) {
+void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo, DevAccum *acc,
+                       CoulItem *items, uint2 *counts, uint32_t step, hipStream_t st) {
   if (P.n <= 1) return;
-  const unsigned nc = (unsigned)coul_nchunks(P.n);
-  hipLaunchKernelGGL(k_coul_order<R>, dim3(nc), dim3(kCB), 0, st, P, S, cellid, chunk_lo, acc, items, counts, step);
-  hipLaunchKernelGGL(k_coul_pairs<R>, dim3(nc, kCoulItems / 64), dim3(64), 0, st, P, T, S, chunk_lo, items, counts,
-                     moments, step);
+  hipLaunchKernelGGL(k_coul_order<R>, dim3((unsigned)coul_nchunks(P.n)), dim3(kCB), 0, st, P, S, cellid, chunk_lo, acc,
+                     items, counts, step);
 }
 
-template void launch_coulomb<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *, const uint32_t *,
-                                     DevAccum *, CoulItem *, uint2 *, double *, uint32_t, hipStream_t);
-template void launch_coulomb<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const uint32_t *,
-                                    DevAccum *, CoulItem *, uint2 *, double *, uint32_t, hipStream_t);
+template <typename R>
+void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *chunk_lo, const CoulItem *items,
+                       const uint2 *counts, double *moments, uint32_t step, hipStream_t st) {
+  if (P.n <= 1) return;
+  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)coul_nchunks(P.n), kCoulItems / 64), dim3(64), 0, st, P, T, S,
+                     chunk_lo, items, counts, moments, step);
+}
+
+template void launch_coul_order<double>(const KParams &, Soa<double>, const uint32_t *, const uint32_t *, DevAccum *,
+                                        CoulItem *, uint2 *, uint32_t, hipStream_t);
+template void launch_coul_order<float>(const KParams &, Soa<float>, const uint32_t *, const uint32_t *, DevAccum *,
+                                       CoulItem *, uint2 *, uint32_t, hipStream_t);
+template void launch_coul_pairs<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *,
+                                        const CoulItem *, const uint2 *, double *, uint32_t, hipStream_t);
+template void launch_coul_pairs<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const CoulItem *,
+                                       const uint2 *, double *, uint32_t, hipStream_t);
 
 }  // namespace ecr

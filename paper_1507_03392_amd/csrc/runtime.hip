@@ -430,10 +430,14 @@ void do_step(ecr_run *r) {
   DevAccum *acc = at<DevAccum>(r, r->L.acc);
   const Tables *T = at<Tables>(r, r->L.tables);
   if (pm & ECR_P_COULOMB) {
-    ProfScope ps(r, ECR_K_COULOMB);
-    launch_coulomb<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.chunks), acc,
-                      at<CoulItem>(r, r->L.pairs), at<uint2>(r, r->L.tris), at<double>(r, r->L.moments), stepw,
-                      r->stream);
+    {
+      ProfScope ps(r, ECR_K_COULOMB);
+      launch_coul_order<R>(r->kp, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.chunks), acc,
+                           at<CoulItem>(r, r->L.pairs), at<uint2>(r, r->L.tris), stepw, r->stream);
+    }
+    ProfScope ps(r, ECR_K_COUL_PAIRS);
+    launch_coul_pairs<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.chunks), at<CoulItem>(r, r->L.pairs),
+                         at<uint2>(r, r->L.tris), at<double>(r, r->L.moments), stepw, r->stream);
   }
   const bool dep = (pm & ECR_P_DEPOSIT) != 0;
   const bool split = (r->p.flags & ECR_FLAG_SPLIT) != 0;
