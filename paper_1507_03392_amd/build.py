@@ -29,10 +29,17 @@ CFLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
+# per-file additions.  k_coulomb: machine LICM hoists the FP64 constants of
+# the collision's log/exp/sincos out of the triplet loop into ~70 VGPRs,
+# doubling the pair kernel's register count and halving its occupancy.
+EXTRA_FLAGS = {
+    "k_coulomb.hip": ["-mllvm", "-disable-machine-licm"],
+}
+
 
 def _compile(src, verbose):
     obj = os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -45,6 +45,8 @@ struct KParams {
   double B0, c1, c2, c3, c4;
   double dt, nfac, Cs;
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
+  // per species pair (a, b): reduced mass mu = ma mb / (ma + mb), mu / ma, mu / mb
+  double mu[kMaxS][kMaxS], mra[kMaxS][kMaxS], mrb[kMaxS][kMaxS];
   uint32_t cxok[kMaxS];  // bit Q: charge exchange allowed from Q
   int64_t sp_end[kMaxS]; // ids [sp_end[s-1], sp_end[s]) are species s
   int64_t n, nnode;
@@ -110,6 +112,9 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
 
 __device__ __forceinline__ void sincos_r(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ void sincos_r(float x, float *s, float *c) { sincosf(x, s, c); }
+// sin(pi x), cos(pi x): exact argument reduction, for angles 2 pi u with u in [0,1)
+__device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
+__device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
 
 // two standard normals from two uniforms
 __device__ __forceinline__ void box_muller(double ua, double ub, double &n1, double &n2) {

@@ -21,12 +21,13 @@
 //    pair leader writes (slot a, slot b, pool size) into the chunk's own
 //    region of the work list (pairs first, then the odd pools' triplets), and
 //    the chunk's counts go to a per-chunk array: no global atomics.
-//  * k_coul_pairs: one lane per work item (wavefront (b, y) takes items
-//    64y..64y+63 of chunk b), one collision or one triplet's three in
-//    sequence, with no LDS and no barriers, so the long dependent FP64 chains
-//    and scattered loads of the collisions are all in flight at once.  Pairs
-//    are disjoint, so no two lanes touch one particle, and the item order
-//    (set by LDS atomics) does not change results.
+//  * k_coul_pairs: one lane per pair (wavefront (b, y) takes pairs
+//    64y..64y+63 of chunk b) and one lane per odd-pool triplet (a wavefront
+//    gathers the triplets of kTriChunks chunks), with no LDS and no
+//    barriers, so the long dependent FP64 chains and scattered loads of the
+//    collisions are all in flight at once.  Pairs are disjoint, so no two
+//    lanes touch one particle, and the item order (set by LDS atomics) does
+//    not change results.
 #include "ecr_kernels.hpp"
 
 namespace ecr {
@@ -43,7 +44,8 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
   const R vax = S.vx[ia], vay = S.vy[ia], vaz = S.vz[ia];
   const R vbx = S.vx[ib], vby = S.vy[ib], vbz = S.vz[ib];
   const uint8_t qa = S.qs[ia], qb = S.qs[ib];
-  const double ma = P.mass[sp_of(qa)], mb = P.mass[sp_of(qb)];
+  const int sa = sp_of(qa), sb = sp_of(qb);
+  const double ma = P.mass[sa], mb = P.mass[sb];
   const double ea = 0.5 * ma * (double)((vax * vax + vay * vay) + vaz * vaz);
   const double eb = 0.5 * mb * (double)((vbx * vbx + vby * vby) + vbz * vbz);
   if (count_e0_a) acc[4] += ea;
@@ -52,7 +54,7 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
   const R g2 = (ux * ux + uy * uy) + uz * uz;
   if (g2 == (R)0) return;
   const R g = sqrt(g2);
-  const double mu = (ma * mb) / (ma + mb);
+  const double mu = P.mu[sa][sb];  // (ma mb) / (ma + mb), tabulated on the host
   const double qq = (double)q_of(qa) * (double)q_of(qb);
   const double num = ((P.Cs * (qq * qq)) * nc) * dtp;
   const double den = (mu * mu) * ((double)g2 * (double)g);
@@ -60,7 +62,7 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
   const R omc = (R)nanbu_omc(lnA, sv, u);
   const R sinchi = sqrt(omc * ((R)2 - omc));
   R sp, cp;
-  sincos_r((R)(2.0 * kPi * u2), &sp, &cp);
+  sincospi_r((R)(2.0 * u2), &sp, &cp);  // phi = 2 pi u2
   const R ca = sinchi * cp, cb = sinchi * sp;
   const R uperp = sqrt(ux * ux + uy * uy);
   R dux, duy, duz;
@@ -73,7 +75,7 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
     duy = g * cb;
     duz = -(g * omc);
   }
-  const R ra = (R)(mu / ma), rb = (R)(mu / mb);
+  const R ra = (R)P.mra[sa][sb], rb = (R)P.mrb[sa][sb];  // mu / ma, mu / mb
   const R nax = vax + ra * dux, nay = vay + ra * duy, naz = vaz + ra * duz;
   const R nbx = vbx - rb * dux, nby = vby - rb * duy, nbz = vbz - rb * duz;
   S.vx[ia] = nax;
@@ -89,6 +91,12 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
   const double eb1 = 0.5 * mb * (double)((nbx * nbx + nby * nby) + nbz * nbz);
   acc[3] += (ea1 - ea) + (eb1 - eb);
 }
+
+// moment slots of a chunk: one per pair wavefront, one for triplets
+constexpr int kMomentSlotsPerChunk = kCoulItems / 64 + 1;
+// chunks whose triplets one wavefront runs (about one odd pool per chunk
+// where cells are populous, so typically one round of 64 lanes)
+constexpr int kTriChunks = 32;
 
 constexpr int kCB = 256;               // lanes per ordering workgroup
 constexpr int kEPT = kCoulMaxE / kCB;  // slots per lane at most
@@ -318,40 +326,91 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 
 // collisions: wavefront (b, y) takes items y*64 .. y*64+63 of chunk b, one
 // per lane, so that every collision of the step is in flight at once
+// Grid (nchunks, 1 + kCoulItems/64), one wavefront per workgroup.  Row 0
+// holds the triplet waves: wave w runs every odd-pool triplet of chunks
+// kTriChunks*w .. kTriChunks*w + kTriChunks-1, one triplet per lane and
+// round, three dependent collisions each ((a,b), (b,c), (c,a) with dt/2).
+// Dispatched first (the grid goes row by row), these longer chains start
+// early and overlap the pair waves; row 1 + y, column b takes pairs
+// 64y..64y+63 of chunk b, so the mostly empty rows come last.  Triplets and
+// pairs touch disjoint particles.
 template <typename R>
 __global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                    const uint32_t *__restrict__ chunk_lo,
                                                    const CoulItem *__restrict__ items,
                                                    const uint2 *__restrict__ counts, double *__restrict__ moments,
-                                                   uint32_t step) {
+                                                   uint32_t step, int64_t nchunks) {
+  const int lane = (int)threadIdx.x;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (blockIdx.y == 0) {
+    // triplet wave: lane j < kTriChunks holds chunk b + j's first slot, pair
+    // count and inclusive triplet prefix
+    const int64_t b = (int64_t)blockIdx.x * kTriChunks;
+    if (b >= nchunks) return;
+    uint32_t my_lo = 0, my_np = 0, nt = 0;
+    if (lane < kTriChunks && b + lane < nchunks) {
+      my_lo = chunk_lo[b + lane];
+      const int ns = (int)(chunk_lo[b + lane + 1] - my_lo);
+      if (ns > 1 && ns <= kCoulMaxE) {  // else no pool, or skipped by the ordering (overflow flagged there)
+        const uint2 c = counts[b + lane];
+        my_np = c.x;
+        nt = c.y;
+      }
+    }
+    uint32_t my_incl = nt;
+    for (int off = 1; off < kTriChunks; off <<= 1) {
+      const uint32_t t = __shfl_up(my_incl, off, 64);
+      if (lane >= off) my_incl += t;
+    }
+    const int total = (int)__shfl(my_incl, kTriChunks - 1, 64);
+    if (total == 0) return;
+    const double h = 0.5 * P.dt;
+    for (int q0 = 0; q0 < total; q0 += 64) {
+      const int q = q0 + lane;
+      int c = 0;  // the lane's triplet is number q - incl[c-1] of chunk b + c
+      for (int j = 0; j < kTriChunks; ++j) c += (int)__shfl(my_incl, j, 64) <= q ? 1 : 0;
+      const int cc = c < kTriChunks ? c : kTriChunks - 1;  // c < kTriChunks when q < total
+      const uint32_t prev = __shfl(my_incl, cc > 0 ? cc - 1 : 0, 64);
+      const uint32_t lo = __shfl(my_lo, cc, 64), np = __shfl(my_np, cc, 64);
+      if (q < total) {
+        const CoulItem e = items[(b + c) * kCoulItems + np + ((uint32_t)q - (cc > 0 ? prev : 0u))];
+        const double nc = (double)e.m * P.nfac;
+        const uint32_t ia = lo + e.a, ib = lo + e.b, ic = lo + e.c;
+        collide<R>(P, T->lnA, S, ia, ib, e.id, nc, h, step, acc, true, true);
+        collide<R>(P, T->lnA, S, ib, ic, S.pid[ib], nc, h, step, acc, false, true);
+        collide<R>(P, T->lnA, S, ic, ia, S.pid[ic], nc, h, step, acc, false, false);
+      }
+    }
+    // the wave's moments go to its first chunk's triplet slot
+    double *slot = moments + (b * kMomentSlotsPerChunk + kMomentSlotsPerChunk - 1) * 5;
+    for (int k = 0; k < 5; ++k) {
+      double v = acc[k];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0 && v != 0.0) slot[k] += v;
+    }
+    return;
+  }
   const int64_t b = blockIdx.x;
+  const int y = (int)blockIdx.y - 1;
   const int64_t s_lo = chunk_lo[b];
   const int ns = (int)((int64_t)chunk_lo[b + 1] - s_lo);
-  if (ns <= 1 || ns > kCoulMaxE) return;  // no pool, or skipped by the ordering (overflow flagged there)
-  const uint2 cnt = counts[b];
-  const int np = (int)cnt.x, total = (int)(cnt.x + cnt.y);
-  if ((int)blockIdx.y * 64 >= total) return;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int q = (int)blockIdx.y * 64 + (int)threadIdx.x;
-  if (q < total) {
-    // a pair is one collision; an odd pool's triplet is (a,b), (b,c), (c,a)
-    // with dt/2 each, in sequence (one call site keeps the register count down)
-    const bool tri = q >= np;
+  if (ns <= 1 || ns > kCoulMaxE) return;
+  const int np = (int)counts[b].x;
+  if (y * 64 >= np) return;
+  const int q = y * 64 + lane;
+  if (q < np) {
     const CoulItem e = items[b * kCoulItems + q];
-    const double nc = (double)e.m * P.nfac, dtp = tri ? 0.5 * P.dt : P.dt;
-    for (int c = 0; c < (tri ? 3 : 1); ++c) {
-      const uint32_t ia = (uint32_t)s_lo + (c == 0 ? e.a : (c == 1 ? e.b : e.c));
-      const uint32_t ib = (uint32_t)s_lo + (c == 0 ? e.b : (c == 1 ? e.c : e.a));
-      collide<R>(P, T->lnA, S, ia, ib, c == 0 ? e.id : S.pid[ia], nc, dtp, step, acc, c == 0, c < 2);
-    }
+    collide<R>(P, T->lnA, S, (uint32_t)s_lo + e.a, (uint32_t)s_lo + e.b, e.id, (double)e.m * P.nfac, P.dt, step, acc,
+               true, true);
   }
-  // each wavefront owns one slot of the moment buffer: plain read-add-write,
-  // no contended atomics (summed in a fixed order when tallies are read)
-  double *slot = moments + (b * (kCoulItems / 64) + blockIdx.y) * 5;
+  // each pair wavefront owns one slot of the moment buffer: plain
+  // read-add-write, no contended atomics (summed in a fixed order when
+  // tallies are read)
+  double *slot = moments + (b * kMomentSlotsPerChunk + y) * 5;
   for (int k = 0; k < 5; ++k) {
     double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (threadIdx.x == 0 && v != 0.0) slot[k] += v;
+    if (lane == 0 && v != 0.0) slot[k] += v;
   }
 }
 
@@ -378,7 +437,7 @@ __global__ void __launch_bounds__(256) k_sum_moments(const double *__restrict__ 
   }
 }
 
-int64_t coul_moment_slots(int64_t n) { return ((n + kCoulCap - 1) / kCoulCap) * (kCoulItems / 64); }
+int64_t coul_moment_slots(int64_t n) { return ((n + kCoulCap - 1) / kCoulCap) * kMomentSlotsPerChunk; }
 
 void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_moments, dim3(1), dim3(256), 0, st, moments, nslots, acc);
@@ -405,8 +464,9 @@ template <typename R>
 void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *chunk_lo, const CoulItem *items,
                        const uint2 *counts, double *moments, uint32_t step, hipStream_t st) {
   if (P.n <= 1) return;
-  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)coul_nchunks(P.n), kCoulItems / 64), dim3(64), 0, st, P, T, S,
-                     chunk_lo, items, counts, moments, step);
+  const int64_t nc = coul_nchunks(P.n);
+  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)nc, 1 + kCoulItems / 64), dim3(64), 0, st, P, T, S, chunk_lo,
+                     items, counts, moments, step, nc);
 }
 
 template void launch_coul_order<double>(const KParams &, Soa<double>, const uint32_t *, const uint32_t *, DevAccum *,

@@ -160,11 +160,20 @@ struct DepIn {
 };
 
 // sum the runs of equal base node held by this lane; flush(node, field, corner, value)
-template <typename R, typename NodeOf, typename Flush>
-__device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, NodeOf nodeof, Flush flush) {
+// the last run of a lane, handed to the wavefront reduction (node -1: none)
+struct DepRun {
+  int64_t node;
+  double a[8], b[8], c[8];
+};
+
+// CARRY: the lane's last run is returned in `last` instead of flushed
+template <typename R, bool CARRY, typename NodeOf, typename Flush>
+__device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, NodeOf nodeof, Flush flush,
+                                               DepRun &last) {
   double a[8], b[8], c[8];
   int64_t cur = -1;
   bool has_ion = false, has_atom = false;
+  for (int k = 0; k < 8; ++k) a[k] = b[k] = c[k] = 0.0;
   auto emit = [&]() {
     if (cur < 0) return;
     for (int k = 0; k < 8; ++k) {
@@ -202,7 +211,31 @@ __device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, N
     has_ion |= ion;
     has_atom |= !ion;
   }
-  emit();
+  if (CARRY) {
+    last.node = cur;
+    for (int k = 0; k < 8; ++k) {
+      last.a[k] = a[k];
+      last.b[k] = b[k];
+      last.c[k] = c[k];
+    }
+  } else {
+    emit();
+  }
+}
+
+// segmented sum over the lanes of a wavefront: lanes are in slot order, so
+// equal run nodes form contiguous lane segments (a lane's earlier runs were
+// flushed already); afterwards the first lane of every segment holds its total
+__device__ __forceinline__ void wave_segment_sum(int seg, double *v) {
+  const int lane = threadIdx.x & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int sn = __shfl_down(seg, off, 64);
+    const bool take = lane + off < 64 && sn == seg;
+    for (int k = 0; k < 8; ++k) {
+      const double o = __shfl_down(v[k], off, 64);
+      v[k] += take ? o : 0.0;
+    }
+  }
 }
 
 // stage the deposit input of tile slot i (lane = slot layout)
@@ -276,13 +309,31 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
     for (int i = tid; i < 3 * nb; i += kBlock) sh.brick[i] = 0.0;
     __syncthreads();
     double *br = sh.brick;
-    run_accumulate<R>(
+    auto to_brick = [&](int64_t base, int f, int k, double v) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+      atomicAdd(&br[f * nb + (int)base + dx + bx * (dy + by * dz)], v);
+    };
+    DepRun L;
+    run_accumulate<R, true>(
         D, dm,
         [&](int ix, int iy, int iz) -> int64_t { return (int64_t)((ix - x0) + bx * ((iy - y0) + by * (iz - z0))); },
-        [&](int64_t base, int f, int k, double v) {
-          const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-          atomicAdd(&br[f * nb + (int)base + dx + bx * (dy + by * dz)], v);
-        });
+        to_brick, L);
+    // the lanes' last runs: one segmented sum per wavefront, then only the
+    // first lane of each segment (usually 2-3 per wavefront) touches the brick
+    const int lane = tid & 63;
+    const int key = (int)L.node;
+    const int kprev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || kprev != key;
+    const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+    if (dm & 1u) wave_segment_sum(seg, L.a);
+    if (dm & 2u) wave_segment_sum(seg, L.b);
+    if (dm & 4u) wave_segment_sum(seg, L.c);
+    if (head && key >= 0)
+      for (int k = 0; k < 8; ++k) {
+        if ((dm & 1u) && L.a[k] != 0.0) to_brick(key, 0, k, L.a[k]);
+        if ((dm & 2u) && L.b[k] != 0.0) to_brick(key, 1, k, L.b[k]);
+        if ((dm & 4u) && L.c[k] != 0.0) to_brick(key, 2, k, L.c[k]);
+      }
     __syncthreads();
     for (int i = tid; i < 3 * nb; i += kBlock) {
       const double v = sh.brick[i];
@@ -295,13 +346,15 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
     }
   } else {
     const int nx1 = P.nx1, ny1 = P.ny1;
-    run_accumulate<R>(
+    DepRun unused;
+    run_accumulate<R, false>(
         D, dm,
         [&](int ix, int iy, int iz) -> int64_t { return (int64_t)ix + (int64_t)nx1 * (iy + (int64_t)ny1 * iz); },
         [&](int64_t base, int f, int k, double v) {
           const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
           unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + base + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz)], v);
-        });
+        },
+        unused);
   }
 }
 

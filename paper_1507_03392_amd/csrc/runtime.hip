@@ -324,6 +324,13 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
     if (end > p->n_particles) end = p->n_particles;
     K.sp_end[s] = end;
   }
+  for (int a = 0; a < p->n_species; ++a)
+    for (int b = 0; b < p->n_species; ++b) {
+      const double ma = K.mass[a], mb = K.mass[b];
+      K.mu[a][b] = (ma * mb) / (ma + mb);
+      K.mra[a][b] = K.mu[a][b] / ma;
+      K.mrb[a][b] = K.mu[a][b] / mb;
+    }
   for (int e = kAeLo; e <= kAeHi; ++e)
     for (int j = 0; j < kAK; ++j) T.lnA[(e - kAeLo) * kAK + j] = nanbu_lnA_lib(ldexp(1.0 + (double)j / kAK, e));
   T.lnA[kANodes - 1] = nanbu_lnA_lib(kSHi);
