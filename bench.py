@@ -24,6 +24,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "ion particle-steps/s (push+MCC+deposit) at 2M ions; p50/p99 scan latency"
+
+
+def describe(name, p):
+    prec = "FP32-mixed (binary32 state, binary64 accumulators)" if p.get("precision", 0) else "FP64"
+    mix = " + ".join(f"{round(100 * s['fraction'])}% {'O' if s['z_max'] == 8 else 'Ar'} (Q<={s['z_max']})"
+                     for s in p["species"])
+    return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, "
+            f"mesh {p['nx']}x{p['ny']}x{p['nz']}, dt {p['dt']:g} s, sort every {p['sort_every']}, "
+            f"all processes on")
 
 # algorithmic HBM bytes per particle per launch (FP64 structure of arrays:
 # x y z vx vy vz 8 B each, qs 1 B, pid 4 B, collision cell 4 B)
@@ -77,6 +87,8 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=500)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--split", action="store_true",
+                    help="run push and deposit as two kernels (per-kernel timing; the default fuses them)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -103,7 +115,7 @@ def main():
     n = params["n"]
     fp32 = params.get("precision", 0) == ecr.FP32_MIXED
     log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")
-    run = ecr.Run(params)
+    run = ecr.Run(params, split=args.split)
     run.init_ions()
     run.step(args.warmup)
     torch.cuda.synchronize()
@@ -138,7 +150,7 @@ def main():
         cpu = cpu_baseline(params, args.cpu_steps)
 
     out = {
-        "metric": "ion particle-steps/s (push+MCC+deposit) at 2M ions",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -150,9 +162,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {n} Ar ions born Q=1 in the ECR-zone ellipsoid, "
-                               f"{'FP32-mixed' if fp32 else 'FP64'}, mesh {params['nx']}x{params['ny']}x{params['nz']}, "
-                               f"dt 1e-9 s, sort every {params['sort_every']}, all processes on",
+        "config": {"workload": describe(args.workload, params),
                    "n_particles": n, "mesh": [params["nx"], params["ny"], params["nz"]],
                    "sort_every": params["sort_every"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -94,8 +94,8 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
 
 // moment slots of a chunk: one per pair wavefront, one for triplets
 constexpr int kMomentSlotsPerChunk = kCoulItems / 64 + 1;
-// chunks whose triplets one wavefront runs (about one odd pool per chunk
-// where cells are populous, so typically one round of 64 lanes)
+// chunks whose triplets are numbered together (about one odd pool per chunk
+// where cells are populous, so one wavefront of 64 lanes takes them all)
 constexpr int kTriChunks = 32;
 
 constexpr int kCB = 256;               // lanes per ordering workgroup
@@ -327,13 +327,15 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 // collisions: wavefront (b, y) takes items y*64 .. y*64+63 of chunk b, one
 // per lane, so that every collision of the step is in flight at once
 // Grid (nchunks, 1 + kCoulItems/64), one wavefront per workgroup.  Row 0
-// holds the triplet waves: wave w runs every odd-pool triplet of chunks
-// kTriChunks*w .. kTriChunks*w + kTriChunks-1, one triplet per lane and
-// round, three dependent collisions each ((a,b), (b,c), (c,a) with dt/2).
-// Dispatched first (the grid goes row by row), these longer chains start
-// early and overlap the pair waves; row 1 + y, column b takes pairs
-// 64y..64y+63 of chunk b, so the mostly empty rows come last.  Triplets and
-// pairs touch disjoint particles.
+// holds the triplet waves: the triplets of a group of kTriChunks chunks are
+// numbered in chunk order, and wave k of the group (column k * ngroups + g
+// for group g) runs numbers 64k..64k+63 (then 64(k + nw).. if the group has
+// more), one triplet per lane, three dependent collisions each ((a,b),
+// (b,c), (c,a) with dt/2).  The k = 0 waves, usually the only busy ones, thus
+// sit side by side at the front, spread over the XCDs (consecutive
+// workgroups go to different XCDs), and start before the pair waves;
+// row 1 + y, column b takes pairs 64y..64y+63 of chunk b, so the mostly empty
+// rows come last.  Triplets and pairs touch disjoint particles.
 template <typename R>
 __global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                    const uint32_t *__restrict__ chunk_lo,
@@ -343,10 +345,13 @@ __global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__re
   const int lane = (int)threadIdx.x;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (blockIdx.y == 0) {
-    // triplet wave: lane j < kTriChunks holds chunk b + j's first slot, pair
-    // count and inclusive triplet prefix
-    const int64_t b = (int64_t)blockIdx.x * kTriChunks;
-    if (b >= nchunks) return;
+    // triplet wave kw of the group starting at chunk b: lane j < kTriChunks
+    // holds chunk b + j's first slot, pair count and inclusive triplet prefix
+    const int64_t ngroups = (nchunks + kTriChunks - 1) / kTriChunks;
+    const int64_t g = (int64_t)blockIdx.x % ngroups;
+    const int kw = (int)((int64_t)blockIdx.x / ngroups);
+    const int nw = (int)((nchunks - 1 - g) / ngroups) + 1;  // waves serving group g
+    const int64_t b = g * kTriChunks;
     uint32_t my_lo = 0, my_np = 0, nt = 0;
     if (lane < kTriChunks && b + lane < nchunks) {
       my_lo = chunk_lo[b + lane];
@@ -363,9 +368,9 @@ __global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__re
       if (lane >= off) my_incl += t;
     }
     const int total = (int)__shfl(my_incl, kTriChunks - 1, 64);
-    if (total == 0) return;
+    if (kw * 64 >= total) return;
     const double h = 0.5 * P.dt;
-    for (int q0 = 0; q0 < total; q0 += 64) {
+    for (int q0 = kw * 64; q0 < total; q0 += 64 * nw) {
       const int q = q0 + lane;
       int c = 0;  // the lane's triplet is number q - incl[c-1] of chunk b + c
       for (int j = 0; j < kTriChunks; ++j) c += (int)__shfl(my_incl, j, 64) <= q ? 1 : 0;
@@ -381,8 +386,8 @@ __global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__re
         collide<R>(P, T->lnA, S, ic, ia, S.pid[ic], nc, h, step, acc, false, false);
       }
     }
-    // the wave's moments go to its first chunk's triplet slot
-    double *slot = moments + (b * kMomentSlotsPerChunk + kMomentSlotsPerChunk - 1) * 5;
+    // each triplet wave owns the triplet slot of the chunk its column names
+    double *slot = moments + ((int64_t)blockIdx.x * kMomentSlotsPerChunk + kMomentSlotsPerChunk - 1) * 5;
     for (int k = 0; k < 5; ++k) {
       double v = acc[k];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
