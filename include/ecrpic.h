@@ -161,6 +161,15 @@ ecr_status ecr_init_ions(ecr_run *run);
  * wall/aperture, ionisation/charge exchange, deposit).  Asynchronous. */
 ecr_status ecr_step(ecr_run *run, int64_t n_steps);
 
+/* Same as ecr_step(run, n_steps), with the same results, but every whole
+ * sort period (sort_every steps starting at a step that is a multiple of
+ * sort_every, the period's sort first) is replayed from a HIP graph that
+ * the run captures on first use: one launch instead of ~3 per step.  Steps
+ * outside whole periods, runs on the null stream and runs being profiled
+ * are launched step by step as ecr_step does.  The run keeps at most two
+ * graphs (one per sort buffer) until ecr_destroy.  Asynchronous. */
+ecr_status ecr_step_graph(ecr_run *run, int64_t n_steps);
+
 /* Advance several independent runs that share one stream by n_steps each. */
 ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps, void *hip_stream);
 

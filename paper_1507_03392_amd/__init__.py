@@ -27,7 +27,7 @@ KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_p
 STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4: "ECR_ESTATE",
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}
 
-EXPORTS = ["ecr_footprint", "ecr_create", "ecr_init_ions", "ecr_step", "ecr_step_batch", "ecr_read_tallies",
+EXPORTS = ["ecr_footprint", "ecr_create", "ecr_init_ions", "ecr_step", "ecr_step_graph", "ecr_step_batch", "ecr_read_tallies",
            "ecr_read_density", "ecr_get_state", "ecr_set_state", "ecr_event_log", "ecr_weight", "ecr_profile",
            "ecr_kernel_times", "ecr_last_error", "ecr_destroy", "ecr_selftest_philox", "ecr_selftest_divsqrt"]
 
@@ -92,7 +92,7 @@ def lib():
         sig = {
             "ecr_footprint": [C.POINTER(Params), C.POINTER(C.c_size_t)],
             "ecr_create": [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)],
-            "ecr_init_ions": [vp], "ecr_step": [vp, i64], "ecr_step_batch": [C.POINTER(vp), i32, i64, vp],
+            "ecr_init_ions": [vp], "ecr_step": [vp, i64], "ecr_step_graph": [vp, i64], "ecr_step_batch": [C.POINTER(vp), i32, i64, vp],
             "ecr_read_tallies": [vp, C.POINTER(Tallies)],
             "ecr_read_density": [vp, u32, vp, C.POINTER(i64)],
             "ecr_get_state": [vp, C.POINTER(StateView)], "ecr_set_state": [vp, C.POINTER(StateView)],
@@ -214,6 +214,10 @@ class Run:
 
     def step(self, n=1):
         _check(lib().ecr_step(self.h, int(n)), self.h)
+
+    def step_graph(self, n):
+        """n steps; whole sort periods replay a captured HIP graph."""
+        _check(lib().ecr_step_graph(self.h, int(n)), self.h)
 
     def tallies(self, allow_anomalies=True):
         t = Tallies()

@@ -55,6 +55,14 @@ struct KParams {
 };
 
 // Device-resident tables.
+// the step number of a launch: off alone, or *base + off when the launch
+// sits in a replayed graph and reads its first step from device memory
+struct StepArg {
+  const uint32_t *base;
+  uint32_t off;
+  __device__ __forceinline__ uint32_t get() const { return base ? *base + off : off; }
+};
+
 struct Tables {
   double qmh[kMaxS][kMaxQ];      // (Q e / M) dt / 2
   double pion[kMaxS][2][kMaxQ];  // ionisation probability per step [outside, inside]

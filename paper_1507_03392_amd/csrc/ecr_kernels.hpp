@@ -38,7 +38,7 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st);
 // push + wall/aperture + MCC; also deposits when dens != nullptr
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
-                 DevAccum *acc, double *dens, uint32_t step, hipStream_t st);
+                 DevAccum *acc, double *dens, StepArg step, hipStream_t st);
 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st);
@@ -55,10 +55,10 @@ void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_
 // energy sums, reduced into the tallies by launch_sum_moments
 template <typename R>
 void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo, DevAccum *acc,
-                       CoulItem *items, uint2 *counts, uint32_t step, hipStream_t st);
+                       CoulItem *items, uint2 *counts, StepArg step, hipStream_t st);
 template <typename R>
 void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *chunk_lo, const CoulItem *items,
-                       const uint2 *counts, double *moments, uint32_t step, hipStream_t st);
+                       const uint2 *counts, double *moments, StepArg step, hipStream_t st);
 int64_t coul_moment_slots(int64_t n);
 void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hipStream_t st);
 

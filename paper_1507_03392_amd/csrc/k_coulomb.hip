@@ -165,8 +165,9 @@ template <typename R>
 __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const uint32_t *__restrict__ cellid,
                                                     const uint32_t *__restrict__ chunk_lo,
                                                     DevAccum *__restrict__ accum, CoulItem *__restrict__ items,
-                                                    uint2 *__restrict__ counts, uint32_t step) {
+                                                    uint2 *__restrict__ counts, StepArg sa) {
   __shared__ CoulShared sh;
+  const uint32_t step = sa.get();
   const int tid = threadIdx.x;
   const int64_t s_lo = chunk_lo[blockIdx.x];
   const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
@@ -341,7 +342,8 @@ __global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__re
                                                    const uint32_t *__restrict__ chunk_lo,
                                                    const CoulItem *__restrict__ items,
                                                    const uint2 *__restrict__ counts, double *__restrict__ moments,
-                                                   uint32_t step, int64_t nchunks) {
+                                                   StepArg sa, int64_t nchunks) {
+  const uint32_t step = sa.get();
   const int lane = (int)threadIdx.x;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (blockIdx.y == 0) {
@@ -459,7 +461,7 @@ void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_
 
 template <typename R>
 void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo, DevAccum *acc,
-                       CoulItem *items, uint2 *counts, uint32_t step, hipStream_t st) {
+                       CoulItem *items, uint2 *counts, StepArg step, hipStream_t st) {
   if (P.n <= 1) return;
   hipLaunchKernelGGL(k_coul_order<R>, dim3((unsigned)coul_nchunks(P.n)), dim3(kCB), 0, st, P, S, cellid, chunk_lo, acc,
                      items, counts, step);
@@ -467,7 +469,7 @@ void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const
 
 template <typename R>
 void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *chunk_lo, const CoulItem *items,
-                       const uint2 *counts, double *moments, uint32_t step, hipStream_t st) {
+                       const uint2 *counts, double *moments, StepArg step, hipStream_t st) {
   if (P.n <= 1) return;
   const int64_t nc = coul_nchunks(P.n);
   hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)nc, 1 + kCoulItems / 64), dim3(64), 0, st, P, T, S, chunk_lo,
@@ -475,12 +477,12 @@ void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32
 }
 
 template void launch_coul_order<double>(const KParams &, Soa<double>, const uint32_t *, const uint32_t *, DevAccum *,
-                                        CoulItem *, uint2 *, uint32_t, hipStream_t);
+                                        CoulItem *, uint2 *, StepArg, hipStream_t);
 template void launch_coul_order<float>(const KParams &, Soa<float>, const uint32_t *, const uint32_t *, DevAccum *,
-                                       CoulItem *, uint2 *, uint32_t, hipStream_t);
+                                       CoulItem *, uint2 *, StepArg, hipStream_t);
 template void launch_coul_pairs<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *,
-                                        const CoulItem *, const uint2 *, double *, uint32_t, hipStream_t);
+                                        const CoulItem *, const uint2 *, double *, StepArg, hipStream_t);
 template void launch_coul_pairs<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const CoulItem *,
-                                       const uint2 *, double *, uint32_t, hipStream_t);
+                                       const uint2 *, double *, StepArg, hipStream_t);
 
 }  // namespace ecr

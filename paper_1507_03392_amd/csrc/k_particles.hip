@@ -370,8 +370,9 @@ template <typename R, bool HAS_E, bool DEP>
 __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                  const double *__restrict__ ef, uint8_t *__restrict__ evlog,
                                                  DevAccum *__restrict__ acc, double *__restrict__ dens,
-                                                 uint32_t step) {
+                                                 StepArg sa) {
   __shared__ DepShared<R> sh;
+  const uint32_t step = sa.get();
   __shared__ int box[6];
   if (DEP) box_init(box);
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
@@ -432,7 +433,7 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
 
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog, DevAccum *acc,
-                 double *dens, uint32_t step, hipStream_t st) {
+                 double *dens, StepArg step, hipStream_t st) {
   if (P.n <= 0) return;
   const dim3 g(grid_for(P.n, kTile)), b(kBlock);
   if (ef) {
@@ -453,9 +454,9 @@ void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {
 template void launch_init<double>(const KParams &, Soa<double>, hipStream_t);
 template void launch_init<float>(const KParams &, Soa<float>, hipStream_t);
 template void launch_push<double>(const KParams &, const Tables *, Soa<double>, const double *, uint8_t *, DevAccum *,
-                                  double *, uint32_t, hipStream_t);
+                                  double *, StepArg, hipStream_t);
 template void launch_push<float>(const KParams &, const Tables *, Soa<float>, const double *, uint8_t *, DevAccum *,
-                                 double *, uint32_t, hipStream_t);
+                                 double *, StepArg, hipStream_t);
 template void launch_deposit<double>(const KParams &, Soa<double>, double *, hipStream_t);
 template void launch_deposit<float>(const KParams &, Soa<float>, double *, hipStream_t);
 

@@ -6,8 +6,9 @@
 //   qs (u8), pid (u32); key, rank, cellid (u32 per slot); count and cell_off
 //   (u32 per cell, +1); scan block sums; density grids (3 fields of FP64 per
 //   node); accumulators (tallies, FP64 Coulomb moments, error bits); tables
-//   (Boris factors, ionisation probabilities, Nanbu ln A); the optional node
-//   E field; the optional per-slot event log.
+//   (Boris factors, ionisation probabilities, Nanbu ln A); the first step of
+//   a replayed graph (u32); the optional node E field; the optional per-slot
+//   event log.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -29,7 +30,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t soa[2][8];  // offsets of x y z vx vy vz qs pid in buffer A and B
-  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, efield, evlog;
+  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, evlog;
   size_t total;
 };
 
@@ -77,6 +78,8 @@ Layout make_layout(const ecr_params *p) {
   o = align_up(o + sizeof(DevAccum));
   L.tables = o;
   o = align_up(o + sizeof(Tables));
+  L.stepc = o;
+  o = align_up(o + 4);
   L.efield = o;
   if (p->efield_nodes) o = align_up(o + 8 * 3 * (size_t)nnodes(p));
   L.evlog = o;
@@ -201,6 +204,9 @@ struct ecr_run {
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
+  // one sort period (sort_every steps, starting with its sort) captured as a
+  // HIP graph, one per SoA buffer the period starts from
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -426,14 +432,15 @@ void do_sort(ecr_run *r, const uint32_t *given) {
   r->cur = b;
 }
 
+// one step; sa gives the step number the kernels use (the host's counter in
+// eager launches, a device word plus an offset inside a captured graph)
 template <typename R>
-void do_step(ecr_run *r) {
+void do_step(ecr_run *r, StepArg stepw) {
   const uint32_t pm = r->p.process_mask;
   if (r->need_sort || r->step % r->p.sort_every == 0) {
     do_sort<R>(r, nullptr);
     r->need_sort = false;
   }
-  const uint32_t stepw = (uint32_t)r->step;
   DevAccum *acc = at<DevAccum>(r, r->L.acc);
   const Tables *T = at<Tables>(r, r->L.tables);
   if (pm & ECR_P_COULOMB) {
@@ -620,10 +627,77 @@ ecr_status ecr_step(ecr_run *r, int64_t n_steps) {
   if (r->failed) return fail(r, ECR_ESTATE, "run failed earlier");
   if (!r->initialized) return fail(r, ECR_ESTATE, "call ecr_init_ions or ecr_set_state first");
   for (int64_t i = 0; i < n_steps; ++i) {
-    if (r->fp32) do_step<float>(r);
-    else do_step<double>(r);
+    if (r->fp32) do_step<float>(r, StepArg{nullptr, (uint32_t)r->step});
+    else do_step<double>(r, StepArg{nullptr, (uint32_t)r->step});
   }
   return check_hip(r, hipGetLastError(), "step launch");
+}
+
+namespace {
+
+// capture one sort period starting from buffer r->cur; host counters are
+// restored afterwards (capturing runs nothing)
+hipError_t capture_period(ecr_run *r, hipGraphExec_t *out) {
+  const int64_t K = r->p.sort_every;
+  const int64_t step0 = r->step, steps0 = r->steps, dens0 = r->dens_steps;
+  const int cur0 = r->cur;
+  const bool need0 = r->need_sort;
+  const uint32_t *base = at<uint32_t>(r, r->L.stepc);
+  hipError_t e = hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  for (int64_t i = 0; i < K; ++i) {
+    if (r->fp32) do_step<float>(r, StepArg{base, (uint32_t)i});
+    else do_step<double>(r, StepArg{base, (uint32_t)i});
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(r->stream, &g);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  r->step = step0;
+  r->steps = steps0;
+  r->dens_steps = dens0;
+  r->cur = cur0;
+  r->need_sort = need0;
+  return e;
+}
+
+}  // namespace
+
+ecr_status ecr_step_graph(ecr_run *r, int64_t n_steps) {
+  if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
+  if (n_steps < 0) return fail(r, ECR_EINVAL, "n_steps < 0");
+  if (r->failed) return fail(r, ECR_ESTATE, "run failed earlier");
+  if (!r->initialized) return fail(r, ECR_ESTATE, "call ecr_init_ions or ecr_set_state first");
+  const int64_t K = r->p.sort_every;
+  const bool dep = (r->p.process_mask & ECR_P_DEPOSIT) != 0;
+  while (n_steps > 0) {
+    if (r->stream == nullptr || r->prof || r->step % K != 0 || n_steps < K || r->step + K > 0xffffffffLL) {
+      // not at the start of a whole period (or nothing to capture on): one eager step
+      const ecr_status st = ecr_step(r, 1);
+      if (st != ECR_OK) return st;
+      --n_steps;
+      continue;
+    }
+    hipGraphExec_t &ge = r->gexec[r->cur];
+    if (!ge) {
+      const hipError_t e = capture_period(r, &ge);
+      if (e != hipSuccess) {
+        ge = nullptr;
+        return check_hip(r, e, "graph capture");
+      }
+    }
+    launch_fill_u32(at<uint32_t>(r, r->L.stepc), (uint32_t)r->step, 1, r->stream);
+    const hipError_t e = hipGraphLaunch(ge, r->stream);
+    if (e != hipSuccess) return check_hip(r, e, "graph launch");
+    r->step += K;
+    r->steps += K;
+    if (dep) r->dens_steps += K;
+    r->cur = 1 - r->cur;  // the period's sort moved the state to the other buffer
+    r->need_sort = false;
+    n_steps -= K;
+  }
+  return check_hip(r, hipGetLastError(), "graph step");
 }
 
 ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps, void *hip_stream) {
@@ -634,8 +708,8 @@ ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps,
   for (int64_t i = 0; i < n_steps; ++i)
     for (int32_t k = 0; k < n_runs; ++k) {
       ecr_run *r = runs[k];
-      if (r->fp32) do_step<float>(r);
-      else do_step<double>(r);
+      if (r->fp32) do_step<float>(r, StepArg{nullptr, (uint32_t)r->step});
+      else do_step<double>(r, StepArg{nullptr, (uint32_t)r->step});
     }
   for (int32_t k = 0; k < n_runs; ++k) {
     const ecr_status st = check_hip(runs[k], hipGetLastError(), "batch step launch");
@@ -753,6 +827,8 @@ ecr_status ecr_destroy(ecr_run *r) {
   if (!r) return ECR_OK;
   harvest(r);
   for (auto e : r->free_events) (void)hipEventDestroy(e);
+  for (auto &g : r->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
   delete r;
   return ECR_OK;
 }

@@ -1,0 +1,198 @@
+"""Continuous-batching server for scan runs of the ion step on one GPU.
+
+A request is one independent run (its own parameters, particle count and
+seed) of a fixed number of steps.  The server keeps every admitted run's
+state on the device from admission to retirement and works like this:
+
+* arrivals enter a FIFO queue at their scheduled time;
+* the head of the queue is admitted as soon as a run slot is free and its
+  device footprint (ecr_footprint) fits the HBM budget next to the runs
+  already resident; a request that can never fit, or whose parameters the
+  library rejects, is answered at once with its error;
+* each slot owns a HIP stream (default priority); an admitted run is
+  created and initialised on its slot's stream and then advanced one sort
+  period at a time with ecr_step_graph, i.e. one graph launch per period;
+* the host loop polls one event per run: a run whose period has finished
+  gets its next period queued, or, when done, its tallies and density read
+  back and its slot and memory released, after which the queue head may be
+  admitted.
+
+Runs on different slots overlap on the device (their streams map to
+separate hardware queues); a run's result depends only on its own
+parameters, so it is the same alone and in any mix (tallies and state bit
+for bit, density within FP64 atomic rounding).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from . import EcrError, Run, footprint
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float      # seconds after the start of the serving loop
+    params: dict
+    steps: int
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    n: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    nbytes: int = 0
+    tallies: dict | None = None
+    density: dict | None = None
+    error: str | None = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+@dataclasses.dataclass
+class _Active:
+    req: Request
+    res: Result
+    run: Run
+    slot: int
+    done: int = 0
+    event: object = None
+
+
+class Server:
+    """Admission by HBM footprint into at most max_active slots.
+
+    hbm_budget: device bytes the resident runs may hold together.
+    period: steps per launch (None: each run's sort_every, the unit that
+    ecr_step_graph replays as one graph).
+    density_fields: density grids to read back at retirement.
+    """
+
+    def __init__(self, hbm_budget, max_active=8, period=None, density_fields=(), device="cuda"):
+        import torch
+        if max_active < 1:
+            raise ValueError("max_active must be >= 1")
+        self.budget = int(hbm_budget)
+        self.max_active = max_active
+        self.period = period
+        self.fields = tuple(density_fields)
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_active)]
+        self.log = []  # (t, event, rid, active runs, resident bytes)
+
+    def serve(self, requests, poll_s=0.0002):
+        import torch
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting = collections.deque()
+        active = {}
+        free = list(range(self.max_active))[::-1]
+        used = 0
+        results = {}
+        t0 = time.monotonic()
+
+        def now():
+            return time.monotonic() - t0
+
+        def note(ev, rid):
+            self.log.append((now(), ev, rid, len(active), used))
+
+        while pending or waiting or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.popleft())
+            # admission, in arrival order
+            while waiting and free:
+                req = waiting[0]
+                res = Result(rid=req.rid, n=int(req.params["n"]), arrival=req.arrival)
+                try:
+                    nb = footprint(req.params)
+                except EcrError as e:
+                    waiting.popleft()
+                    res.error, res.finished = str(e), now()
+                    results[req.rid] = res
+                    note("reject", req.rid)
+                    continue
+                if nb > self.budget:
+                    waiting.popleft()
+                    res.error, res.finished = f"footprint {nb} B exceeds the HBM budget {self.budget} B", now()
+                    results[req.rid] = res
+                    note("reject", req.rid)
+                    continue
+                if used + nb > self.budget:
+                    break
+                waiting.popleft()
+                slot = free.pop()
+                try:
+                    run = Run(req.params, stream=self.streams[slot], device=self.device)
+                    run.init_ions()
+                except EcrError as e:
+                    free.append(slot)
+                    res.error, res.finished = str(e), now()
+                    results[req.rid] = res
+                    note("reject", req.rid)
+                    continue
+                used += nb
+                res.admitted, res.nbytes = now(), nb
+                active[slot] = _Active(req, res, run, slot)
+                note("admit", req.rid)
+            # progress
+            moved = False
+            for slot in list(active):
+                a = active[slot]
+                if a.event is not None and not a.event.query():
+                    continue
+                moved = True
+                if a.done >= a.req.steps:
+                    try:
+                        a.res.tallies = a.run.tallies()
+                        a.res.density = {f: a.run.density(f)[0] for f in self.fields}
+                    except EcrError as e:
+                        a.res.error = str(e)
+                    a.res.finished = now()
+                    results[a.req.rid] = a.res
+                    a.run.close()
+                    del active[slot]
+                    free.append(slot)
+                    used -= a.res.nbytes
+                    note("finish", a.req.rid)
+                    continue
+                k = self.period or int(a.req.params["sort_every"])
+                n = min(k, a.req.steps - a.done)
+                try:
+                    a.run.step_graph(n)
+                except EcrError as e:
+                    a.res.error, a.res.finished = str(e), now()
+                    results[a.req.rid] = a.res
+                    a.run.close()
+                    del active[slot]
+                    free.append(slot)
+                    used -= a.res.nbytes
+                    note("evict", a.req.rid)
+                    continue
+                a.done += n
+                a.event = torch.cuda.Event()
+                a.event.record(self.streams[slot])
+            if not moved:
+                time.sleep(poll_s)
+        return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+
+def summary(results, steps_key="steps"):
+    """p50/p99 latency (s) and throughput (particle-steps/s) of served results."""
+    ok = [r for r in results if r.error is None]
+    lat = np.array([r.latency for r in ok])
+    work = sum(r.n * (r.tallies or {}).get(steps_key, 0) for r in ok)
+    span = max(r.finished for r in ok) - min(r.arrival for r in ok) if ok else float("nan")
+    return dict(requests=len(results), completed=len(ok),
+                p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
+                p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
+                throughput=work / span if ok else None, span_s=span, particle_steps=work)

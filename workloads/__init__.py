@@ -61,15 +61,29 @@ def synthetic_rates(ip_ev, k0_cm3s=K0_CM3S, exponent=1.5):
 SIGMA_CX1_M2 = 5.0e-19  # synthetic Ar+ + Ar charge-exchange cross-section (5e-15 cm^2)
 
 
-def argon(fraction=1.0, n0_m3=1.0e17, sigma_cx1_m2=SIGMA_CX1_M2, outside_rates=False):
-    k = synthetic_rates(AR_IP_EV)
+def te_scaled(k, ip_ev, te_ev, te_ref_ev=1000.0):
+    """The synthetic rate table k (given at te_ref_ev) moved to electron
+    temperature te_ev with the temperature shape of a Maxwellian-averaged
+    Lotz-type cross-section, k_Q ~ T^-1/2 E1(I_Q / T).  A stated synthetic
+    input; the identity at te_ev == te_ref_ev."""
+    if te_ev == te_ref_ev:
+        return list(k)
+    from scipy.special import exp1
+    out = list(k)
+    for q, ip in enumerate(ip_ev):
+        out[q] = k[q] * math.sqrt(te_ref_ev / te_ev) * float(exp1(ip / te_ev) / exp1(ip / te_ref_ev))
+    return out
+
+
+def argon(fraction=1.0, n0_m3=1.0e17, sigma_cx1_m2=SIGMA_CX1_M2, outside_rates=False, te_ev=1000.0):
+    k = te_scaled(synthetic_rates(AR_IP_EV), AR_IP_EV, te_ev)
     return dict(mass_amu=39.948, z_max=18, cx_forbidden_mask=1 << 2, fraction=fraction,
                 k_in=k, k_out=(list(k) if outside_rates else [0.0] * 32),
                 sigma_cx1=sigma_cx1_m2, n0=n0_m3)
 
 
-def oxygen(fraction=1.0, n0_m3=1.0e17, sigma_cx1_m2=SIGMA_CX1_M2, outside_rates=False):
-    k = synthetic_rates(O_IP_EV, k0_cm3s=K0_CM3S * (O_IP_EV[0] / AR_IP_EV[0]) ** -1.5)
+def oxygen(fraction=1.0, n0_m3=1.0e17, sigma_cx1_m2=SIGMA_CX1_M2, outside_rates=False, te_ev=1000.0):
+    k = te_scaled(synthetic_rates(O_IP_EV, k0_cm3s=K0_CM3S * (O_IP_EV[0] / AR_IP_EV[0]) ** -1.5), O_IP_EV, te_ev)
     return dict(mass_amu=15.999, z_max=8, cx_forbidden_mask=0, fraction=fraction,
                 k_in=k, k_out=(list(k) if outside_rates else [0.0] * 32),
                 sigma_cx1=sigma_cx1_m2, n0=n0_m3)
@@ -102,6 +116,34 @@ def config(name):
         p["species"] = [oxygen(0.7, n0_m3=0.7 * 3e17), argon(0.3, n0_m3=0.3 * 3e17)]
         return p, 5000
     raise KeyError(name)
+
+
+def c5_trace(n_requests=256, rate_hz=20.0, seed=0, precision=PREC_FP32, steps=2000, n_lo=10_000, n_hi=2_000_000):
+    """The serving workload: a parameter scan of n_requests argon runs.
+
+    Drawn in this order from numpy.default_rng(seed), all arrays of length
+    n_requests: exponential inter-arrival gaps of mean 1/rate_hz (arrival =
+    running sum); particle count log-uniform in [n_lo, n_hi] (gas load);
+    neutral density uniform in 3e10..3e11 cm^-3 (gas flow); one power draw u
+    uniform in [0, 1) giving T_e = 0.3 + 2.7u keV and n_e = (0.3 + 2.2u)e12
+    cm^-3 in the zone (microwave power).  Each run: grid 64x64x128, sort every
+    50 steps, seed = request index, weight n_e V_zone / N.
+    Returns a list of (arrival_s, params, steps).
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, n_requests)
+    counts = np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), n_requests)).astype(np.int64)
+    n0_cm3 = rng.uniform(3e10, 3e11, n_requests)
+    u = rng.uniform(0.0, 1.0, n_requests)
+    arrival = np.cumsum(gaps)
+    out = []
+    for i in range(n_requests):
+        te_ev = (0.3 + 2.7 * u[i]) * 1e3
+        p = base_params(int(counts[i]), 64, 64, 128, seed=i, precision=precision)
+        p.update(ne_in=(0.3 + 2.2 * u[i]) * 1e18, Te_in_eV=te_ev)
+        p["species"] = [argon(n0_m3=n0_cm3[i] * 1e6, te_ev=te_ev)]
+        out.append((float(arrival[i]), p, steps))
+    return out
 
 
 def with_(params, **kw):
