@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -144,6 +146,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=500)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
     ap.add_argument("--slots", type=int, default=8, help="c5: run slots (one HIP stream each)")
     ap.add_argument("--split", action="store_true",
@@ -207,6 +210,33 @@ def main():
                    "share": round(tot[k] / max(1e-12, sum(tot.values())), 3)} for k in tot if per[k][1]}
     log(f"bench: kernels {json.dumps(kernels)}")
 
+    drift = None
+    if fp32 and not args.no_drift:
+        # the FP32-mixed run against the same workload in FP64 on the same
+        # GPU (the FP64 path matches the oracle to 1e-12), same steps from init
+        done = args.warmup + args.steps + args.prof_steps
+        ref = ecr.Run(W.with_(params, precision=0))
+        ref.init_ions()
+        ref.step(done)
+        tr = ref.tallies()
+        t32 = run.tallies()
+        a32, a64 = run.get_state(), ref.get_state()
+        d32, d64 = run.density(W.F_ION_N)[0], ref.density(W.F_ION_N)[0]
+        ion32, ion64 = t32["ionized"].sum(axis=0), tr["ionized"].sum(axis=0)
+        q = [int(i) for i in np.nonzero(ion64 >= 100)[0]]
+        e32 = float(np.mean(a32["vx"] ** 2 + a32["vy"] ** 2 + a32["vz"] ** 2))
+        e64 = float(np.mean(a64["vx"] ** 2 + a64["vy"] ** 2 + a64["vz"] ** 2))
+        drift = {"reference": "same workload in FP64 on this GPU", "steps": done,
+                 "ionized_rel_err_by_q": {str(i): float(ion32[i] / ion64[i] - 1) for i in q},
+                 "ionized_total": [int(ion32.sum()), int(ion64.sum())],
+                 "extracted_total": [int(t32["extracted"].sum()), int(tr["extracted"].sum())],
+                 "wall_total": [int(t32["wall"].sum()), int(tr["wall"].sum())],
+                 "cx_total": [int(t32["cx"].sum()), int(tr["cx"].sum())],
+                 "mean_v2_rel_diff": e32 / e64 - 1,
+                 "ion_density_rel_l1": float(np.abs(d32 - d64).sum() / np.abs(d64).sum())}
+        log(f"bench: FP32-mixed drift vs FP64 {json.dumps(drift)}")
+        del ref
+
     cpu = None
     if not args.no_cpu:
         log(f"bench: CPU oracle sample, {args.cpu_steps} steps of the same workload")
@@ -237,6 +267,8 @@ def main():
                     "anomalies": tal["anomalies"]},
         "cpu_baseline": cpu,
     }
+    if drift is not None:
+        out["drift_vs_fp64"] = drift
     print(json.dumps(out), flush=True)
 
 

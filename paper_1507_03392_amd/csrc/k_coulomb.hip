@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 // row 1 + y, column b takes pairs 64y..64y+63 of chunk b, so the mostly empty
 // rows come last.  Triplets and pairs touch disjoint particles.
 template <typename R>
-__global__ void __launch_bounds__(64) k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                    const uint32_t *__restrict__ chunk_lo,
                                                    const CoulItem *__restrict__ items,
                                                    const uint2 *__restrict__ counts, double *__restrict__ moments,

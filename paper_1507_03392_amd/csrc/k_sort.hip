@@ -2,7 +2,8 @@
 // self-test kernels.
 //
 // Counting sort in three passes: (1) each slot computes its cell and claims
-// a rank inside the cell with an atomic increment of the cell's counter;
+// a rank inside the cell from the cell's counter (one atomic per run of
+// equal cells within a wavefront);
 // (2) an exclusive scan of the counters gives cell_off (reduce per block of
 // 1024 counters, scan of the block sums in one workgroup, scan within each
 // block); (3) each slot scatters its record to cell_off[cell] + rank and
@@ -20,10 +21,27 @@ __global__ void __launch_bounds__(256) k_sort_count(KParams P, Soa<R> A, const u
                                                     uint32_t *__restrict__ key, uint32_t *__restrict__ rank,
                                                     uint32_t *__restrict__ count) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P.n) return;
-  const uint32_t c = given ? given[A.pid[j]] : cell_of<R>(P, A.x[j], A.y[j], A.z[j]);
-  key[j] = c;
-  rank[j] = atomicAdd(&count[c], 1u);
+  const bool valid = j < P.n;
+  const int lane = (int)(threadIdx.x & 63);
+  uint32_t c = 0xffffffffu;
+  if (valid) {
+    c = given ? given[A.pid[j]] : cell_of<R>(P, A.x[j], A.y[j], A.z[j]);
+    key[j] = c;
+  }
+  // slots are mostly in cell order already (the previous sort), so runs of
+  // lanes share a cell: the first lane of each run claims the whole run with
+  // one atomic and the others take consecutive ranks after it
+  const uint32_t prev = __shfl_up(c, 1, 64);
+  const bool head = lane == 0 || prev != c;
+  const uint64_t hm = __ballot(head);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  const int h = 63 - __clzll(hm & upto);  // first lane of my run
+  const uint64_t after = hm & ~upto;
+  const int next = after ? __builtin_ctzll(after) : 64;  // first lane of the next run
+  uint32_t base = 0;
+  if (head && valid) base = atomicAdd(&count[c], (uint32_t)(next - lane));
+  base = __shfl(base, h, 64);
+  if (valid) rank[j] = base + (uint32_t)(lane - h);
 }
 
 __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *__restrict__ count, int64_t ncell,

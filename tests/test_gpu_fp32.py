@@ -168,6 +168,19 @@ def test_fp32_collisionless_energy_drift():
     d64 = np.abs((s2["vx"] ** 2 + s2["vy"] ** 2 + s2["vz"] ** 2) / v0 - 1)[alive]
     assert np.median(d64) < 1e-12
     assert np.median(d32) < 2e-5 and d32.max() < 2e-4, (np.median(d32), d32.max())
+    # magnetic moment v_perp^2 / |B| at the end: FP32 run against the FP64
+    # oracle run from the same start (an adiabatic invariant, so both drift
+    # a little; their difference is the precision effect)
+    def mu(st, i):
+        b = o.field(st["x"][i], st["y"][i], st["z"][i])
+        v = np.array([st["vx"][i], st["vy"][i], st["vz"][i]])
+        bb = float(b @ b)
+        return float(v @ v - (v @ b) ** 2 / bb) / np.sqrt(bb)
+    idx = np.nonzero(alive)[0][:300]
+    dmu = np.array([abs(mu(s1, i) / mu(s2, i) - 1) for i in idx])
+    print(f"FP32 energy drift median {np.median(d32):.3e} max {d32.max():.3e}; FP64 oracle {np.median(d64):.3e}; "
+          f"mu FP32 vs FP64 median {np.median(dmu):.3e} max {dmu.max():.3e}")
+    assert np.median(dmu) < 1e-3
 
 
 def test_fp32_two_species_c4_full_size_sampled_cells():
