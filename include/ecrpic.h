@@ -196,9 +196,12 @@ ecr_status ecr_event_log(ecr_run *run, uint8_t *host_out);
 /* Macro-particle weight in use (real ions per macro-particle). */
 ecr_status ecr_weight(const ecr_run *run, double *weight);
 
-/* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
- * the run's stream; ecr_kernel_times returns, per kernel kind (ECR_K_*), the
- * summed milliseconds and the launch count since the last reset. */
+/* Per-kernel timing.  ecr_profile(run, mask): bit k of mask (1 << ECR_K_*)
+ * brackets every launch of kernel kind k with HIP events on the run's
+ * stream (-1: every kind; 0: off) and resets the counters;
+ * ecr_kernel_times returns, per kind, the summed milliseconds and the launch
+ * count since then.  Timed runs are stepped launch by launch (ecr_step_graph
+ * does not replay graphs while any bit is set). */
 enum {
   ECR_K_SORT = 0,       /* the sort by cell (count, scan, scatter, chunk table) */
   ECR_K_COULOMB = 1,    /* Coulomb pairing: pool order and pair lists */

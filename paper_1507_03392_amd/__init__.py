@@ -27,8 +27,8 @@ KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_p
 STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4: "ECR_ESTATE",
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}
 
-EXPORTS = ["ecr_footprint", "ecr_create", "ecr_init_ions", "ecr_step", "ecr_step_graph", "ecr_step_batch", "ecr_read_tallies",
-           "ecr_read_density", "ecr_get_state", "ecr_set_state", "ecr_event_log", "ecr_weight", "ecr_profile",
+EXPORTS = ["ecr_footprint", "ecr_create", "ecr_init_ions", "ecr_step", "ecr_step_graph", "ecr_step_batch",
+           "ecr_read_tallies", "ecr_read_density", "ecr_get_state", "ecr_set_state", "ecr_event_log", "ecr_weight", "ecr_profile",
            "ecr_kernel_times", "ecr_last_error", "ecr_destroy", "ecr_selftest_philox", "ecr_selftest_divsqrt"]
 
 
@@ -262,8 +262,13 @@ class Run:
         _check(lib().ecr_weight(self.h, C.byref(w)), self.h)
         return w.value
 
-    def profile(self, enable=True):
-        _check(lib().ecr_profile(self.h, 1 if enable else 0), self.h)
+    def profile(self, enable=True, kinds=None):
+        """Time launches with HIP events: every kernel kind, or only `kinds`
+        (names from KERNEL_NAMES); enable=False turns timing off."""
+        mask = 0
+        if enable:
+            mask = -1 if kinds is None else sum(1 << KERNEL_NAMES.index(k) for k in kinds)
+        _check(lib().ecr_profile(self.h, mask), self.h)
 
     def kernel_times(self):
         ms = np.zeros(N_KERNELS)

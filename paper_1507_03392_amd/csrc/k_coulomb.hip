@@ -14,8 +14,8 @@
 //    [b*kCoulCap, (b+1)*kCoulCap) (slot ranges tabulated once per sort by
 //    k_coul_chunks).  The chunk's slots are already grouped by cell, so the
 //    pool order is found per cell without a general sort: a cell of m slots
-//    gets B = 2^ceil(log2 m) buckets on the top bits of the uniform keys
-//    (about one member per bucket); an LDS histogram and scan place the
+//    gets B = 2^floor(log2 m) buckets on the top bits of the uniform keys
+//    (one or two members per bucket); an LDS histogram and scan place the
 //    members bucket by bucket, and a member's exact position is its bucket
 //    offset plus the number of bucket mates with a smaller (key, id).  Each
 //    pair leader writes (slot a, slot b, pool size) into the chunk's own
@@ -103,8 +103,7 @@ constexpr int kEPT = kCoulMaxE / kCB;  // slots per lane at most
 
 struct CoulShared {
   uint64_t skey[kCoulMaxE];         // (key << 32) | id, in slot order
-  uint32_t r1[2 * kCoulMaxE + 2];   // cell flags and scan scratch, then the bucket histogram
-  uint32_t cellv[kCoulMaxE];        // collision cell of each slot
+  uint32_t r1[kCoulMaxE + 2];       // cell flags and scan scratch, then the bucket histogram
   uint16_t hd[kCoulMaxE];           // cell (head) index of each slot of the chunk
   uint16_t hstart[kCoulMaxE + 1];   // first slot of each cell
   uint16_t hbase[kCoulMaxE + 1];    // first bucket of each cell
@@ -195,7 +194,6 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
       pool[k] = q_of(S.qs[j]) >= 1;
       if (pool[k]) key[k] = draw(P, id, step, S_STEP, 0).z;
       sh.skey[i] = ((uint64_t)key[k] << 32) | id;
-      sh.cellv[i] = cellid[j];
     }
   }
   __syncthreads();
@@ -204,7 +202,7 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int i = tid + k * kCB;
-    fl[k] = (i < ns && (i == 0 || sh.cellv[i] != sh.cellv[i - 1])) ? 1u : 0u;
+    fl[k] = (i < ns && (i == 0 || cellid[s_lo + i] != cellid[s_lo + i - 1])) ? 1u : 0u;
     if (i < ns) flags[i] = fl[k];
   }
   __syncthreads();
@@ -220,10 +218,11 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
   }
   if (tid == 0) sh.hstart[nheads] = (uint16_t)ns;
   __syncthreads();
-  // 3. buckets per cell: B = 2^ceil(log2(slots of the cell))
+  // 3. buckets per cell: B = 2^floor(log2(slots of the cell)), so at most
+  //    one bucket per slot of the chunk
   for (int h = tid; h < nheads; h += kCB) {
     const int m = sh.hstart[h + 1] - sh.hstart[h];
-    const int lg = m <= 1 ? 0 : 32 - __clz(m - 1);
+    const int lg = m <= 1 ? 0 : 31 - __clz(m);
     sh.hlog[h] = (uint8_t)lg;
     sh.r1[h] = 1u << lg;
   }

@@ -194,8 +194,8 @@ struct ecr_run {
   bool failed;
   int cur;  // which SoA buffer is current
   std::string err;
-  // profiling
-  bool prof;
+  // profiling: bit k set = launches of kernel kind k are bracketed by events
+  uint32_t prof;
   double ms[ECR_N_KERNELS];
   int64_t launches[ECR_N_KERNELS];
   std::vector<hipEvent_t> free_events;
@@ -404,14 +404,14 @@ struct ProfScope {
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(ecr_run *r_, int k) : r(r_), kind(k) {
-    if (r->prof) {
+    if ((r->prof >> kind) & 1u) {
       a = get_event(r);
       b = get_event(r);
       (void)hipEventRecord(a, r->stream);
     }
   }
   ~ProfScope() {
-    if (r->prof) {
+    if ((r->prof >> kind) & 1u) {
       (void)hipEventRecord(b, r->stream);
       r->pending.push_back({kind, a, b});
       if (r->pending.size() >= 4096) harvest(r);
@@ -586,7 +586,7 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   r->nnode = nnodes(params);
   r->cur = 0;
   r->need_sort = true;
-  r->prof = false;
+  r->prof = 0u;
   for (int k = 0; k < ECR_N_KERNELS; ++k) {
     r->ms[k] = 0.0;
     r->launches[k] = 0;
@@ -803,7 +803,7 @@ ecr_status ecr_weight(const ecr_run *r, double *w) {
 ecr_status ecr_profile(ecr_run *r, int32_t enable) {
   if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
   harvest(r);
-  r->prof = enable != 0;
+  r->prof = (uint32_t)enable & ((1u << ECR_N_KERNELS) - 1u);
   for (int k = 0; k < ECR_N_KERNELS; ++k) {
     r->ms[k] = 0.0;
     r->launches[k] = 0;
