@@ -94,6 +94,8 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
 
 // moment slots of a chunk: one per pair wavefront, one for triplets
 constexpr int kMomentSlotsPerChunk = kCoulItems / 64 + 1;
+// pair wavefronts per chunk (a chunk of 256 slots holds about 128 pairs)
+constexpr int kPairRows = 2;
 // chunks whose triplets are numbered together (about one odd pool per chunk
 // where cells are populous, so one wavefront of 64 lanes takes them all)
 constexpr int kTriChunks = 32;
@@ -324,9 +326,9 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
   if (tid == 0) counts[blockIdx.x] = make_uint2((uint32_t)np, sh.ntri);
 }
 
-// collisions: wavefront (b, y) takes items y*64 .. y*64+63 of chunk b, one
-// per lane, so that every collision of the step is in flight at once
-// Grid (nchunks, 1 + kCoulItems/64), one wavefront per workgroup.  Row 0
+// collisions, one per lane, so that every collision of the step is in
+// flight at once.  Grid (nchunks, 1 + kPairRows), one wavefront per
+// workgroup.  Row 0
 // holds the triplet waves: the triplets of a group of kTriChunks chunks are
 // numbered in chunk order, and wave k of the group (column k * ngroups + g
 // for group g) runs numbers 64k..64k+63 (then 64(k + nw).. if the group has
@@ -334,10 +336,13 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 // (b,c), (c,a) with dt/2).  The k = 0 waves, usually the only busy ones, thus
 // sit side by side at the front, spread over the XCDs (consecutive
 // workgroups go to different XCDs), and start before the pair waves;
-// row 1 + y, column b takes pairs 64y..64y+63 of chunk b, so the mostly empty
-// rows come last.  Triplets and pairs touch disjoint particles.
+// row 1 + y, column b takes pairs 64y..64y+63 of chunk b (then
+// 64(y + kPairRows).. if the chunk has more).  Triplets and pairs touch
+// disjoint particles.  At most 4 waves per SIMD: the triplet path alone
+// would need a few more registers than that allows, for nothing.
 template <typename R>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                    const uint32_t *__restrict__ chunk_lo,
                                                    const CoulItem *__restrict__ items,
                                                    const uint2 *__restrict__ counts, double *__restrict__ moments,
@@ -403,8 +408,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
   if (ns <= 1 || ns > kCoulMaxE) return;
   const int np = (int)counts[b].x;
   if (y * 64 >= np) return;
-  const int q = y * 64 + lane;
-  if (q < np) {
+  // rows beyond kPairRows are folded onto these (rare: > 64 kPairRows pairs)
+#pragma unroll 1
+  for (int q = y * 64 + lane; q < np; q += 64 * kPairRows) {
     const CoulItem e = items[b * kCoulItems + q];
     collide<R>(P, T->lnA, S, (uint32_t)s_lo + e.a, (uint32_t)s_lo + e.b, e.id, (double)e.m * P.nfac, P.dt, step, acc,
                true, true);
@@ -471,7 +477,7 @@ void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32
                        const uint2 *counts, double *moments, StepArg step, hipStream_t st) {
   if (P.n <= 1) return;
   const int64_t nc = coul_nchunks(P.n);
-  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)nc, 1 + kCoulItems / 64), dim3(64), 0, st, P, T, S, chunk_lo,
+  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)nc, 1 + kPairRows), dim3(64), 0, st, P, T, S, chunk_lo,
                      items, counts, moments, step, nc);
 }
 

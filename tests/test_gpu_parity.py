@@ -203,6 +203,26 @@ def test_multi_step_c1_from_init():
         assert np.abs(dg - do).max() <= 1e-12 * np.abs(do).max()
 
 
+def test_deposit_fused_and_split_agree():
+    # deposit inside the push kernel (default) or as its own kernel after it:
+    # the same run, densities within FP64 atomic rounding
+    params, _ = W.config("c1")
+    outs = []
+    for kw in (dict(), dict(split=True)):
+        g = gpu_run(params, **kw)
+        g.init_ions()
+        g.step(37)
+        g.step(83)
+        outs.append((g.get_state(), g.tallies(), [g.density(f) for f in (W.F_ION_N, W.F_ION_Q)]))
+    for st, t, d in outs[1:]:
+        for k in ("x", "vx", "q", "cell"):
+            assert np.array_equal(st[k], outs[0][0][k]), k
+        assert_tallies_equal(t, outs[0][1])
+        for (a, na), (b, nb) in zip(d, outs[0][2]):
+            assert na == nb == 120
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+
+
 def test_given_cells_and_resume_bitwise():
     params = boosted(W.base_params(30_000, 16, 16, 32, seed=4))
     params.update(dt=2e-9)
