@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
-    ap.add_argument("--slots", type=int, default=8, help="c5: run slots (one HIP stream each)")
+    ap.add_argument("--slots", type=int, default=16, help="c5: run slots (one HIP stream each)")
     ap.add_argument("--split", action="store_true",
                     help="run push and deposit as two kernels (per-kernel timing; the default fuses them)")
     ap.add_argument("--copy-mb", type=int, default=0,

@@ -386,7 +386,10 @@ __device__ __forceinline__ double nanbu_omc(const double *__restrict__ lnA, doub
     omc = 2.0 * u;
   } else {
     const double A = (sv < kSLo) ? 1.0 / sv : nanbu_A(lnA, sv);
-    omc = -log1p(u * expm1(-2.0 * A)) / A;
+    // for A > 20, exp(-2A) < 5e-18 is below half an ulp of 1, so expm1(-2A)
+    // rounds to -1 exactly: skip the call (most pairs of a cool plasma)
+    const double em = A > 20.0 ? -1.0 : expm1(-2.0 * A);
+    omc = -log1p(u * em) / A;
   }
   omc = omc < 0.0 ? 0.0 : omc;
   omc = omc > 2.0 ? 2.0 : omc;

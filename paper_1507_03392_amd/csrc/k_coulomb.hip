@@ -67,8 +67,10 @@ __device__ __forceinline__ void collide(const KParams &P, const double *__restri
   const R uperp = sqrt(ux * ux + uy * uy);
   R dux, duy, duz;
   if (uperp > (R)0) {
-    dux = (((ux / uperp) * uz) * ca - ((uy / uperp) * g) * cb) - ux * omc;
-    duy = (((uy / uperp) * uz) * ca + ((ux / uperp) * g) * cb) - uy * omc;
+    const R iu = (R)1 / uperp;
+    const R cx = ux * iu, cy = uy * iu;  // within an ulp of ux/uperp, uy/uperp
+    dux = ((cx * uz) * ca - (cy * g) * cb) - ux * omc;
+    duy = ((cy * uz) * ca + (cx * g) * cb) - uy * omc;
     duz = -(uperp * ca) - uz * omc;
   } else {
     dux = g * ca;

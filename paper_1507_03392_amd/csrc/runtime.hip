@@ -251,6 +251,7 @@ std::string validate(const ecr_params *p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "mesh dimensions must be >= 1";
   if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 31) - 1) return "mesh too large";
   if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 30)) return "mesh too large for 64-bit pairing keys";
+  if (nnodes(p) >= (1LL << 31)) return "mesh has too many nodes";
   if (p->n_species < 1 || p->n_species > ECR_MAX_SPECIES) return "n_species must be 1..4";
   if (!(p->R0_m > 0.0) || !(p->L_m > 0.0)) return "R0_m and L_m must be positive";
   if (!(p->zone_a_m > 0.0) || !(p->zone_c_m > 0.0)) return "zone semi-axes must be positive";
