@@ -135,6 +135,16 @@ def serve_bench(args):
     # time-weighted number of resident runs
     ev = srv.log
     occ = sum((ev[i + 1][0] - ev[i][0]) * ev[i][3] for i in range(len(ev) - 1)) / max(1e-9, ev[-1][0] - ev[0][0])
+    # resident runs over time: time-weighted mean per one-second bin
+    t_end = ev[-1][0]
+    bins = []
+    for b0 in range(int(t_end) + 1):
+        acc_t = 0.0
+        for i in range(len(ev) - 1):
+            lo, hi = max(ev[i][0], b0), min(ev[i + 1][0], b0 + 1)
+            if hi > lo:
+                acc_t += (hi - lo) * ev[i][3]
+        bins.append(round(acc_t / max(1e-9, min(1.0, t_end - b0)), 2))
     total_steps = sum(r.steps for r in reqs)
     offered = sum(r.params["n"] * r.steps for r in reqs) / max(r.arrival for r in reqs)
     log(f"bench: served {s['completed']}/{s['requests']} in {s['span_s']:.2f} s, p50 {s['p50_s']:.3f} s, "
@@ -161,6 +171,7 @@ def serve_bench(args):
                     "span_s": s["span_s"], "particle_steps": s["particle_steps"],
                     "offered_particle_steps_per_s": offered, "mean_resident_runs": occ,
                     "max_resident_runs": max(e[3] for e in ev),
+                    "resident_runs_per_second": bins,
                     "max_resident_bytes": max(e[4] for e in ev)},
         "cpu_baseline": None,
     }
