@@ -172,6 +172,7 @@ class Server:
                 except EcrError as e:
                     a.res.error, a.res.finished = str(e), now()
                     results[a.req.rid] = a.res
+                    self.streams[slot].synchronize()  # nothing may still use the arena
                     a.run.close()
                     del active[slot]
                     free.append(slot)
