@@ -38,9 +38,11 @@
 extern "C" {
 #endif
 
-#define ECR_ABI_VERSION 1u
+#define ECR_ABI_VERSION 2u
 #define ECR_MAX_SPECIES 4
-#define ECR_MAX_Q 32 /* charge-state slots per species: Q = 0..31 */
+#define ECR_MAX_Q 32          /* charge-state slots per species: Q = 0..31 */
+#define ECR_FPT_BINS 32       /* log2 bins of first-passage times */
+#define ECR_BIRTH_NONE 0xffffffffu /* birth step of an atom, or of an ion of unknown origin */
 
 typedef enum {
   ECR_OK = 0,
@@ -129,6 +131,18 @@ typedef struct {
   double coul_dp[3];                              /* total momentum change in Coulomb collisions, kg m/s */
   double coul_de;                                 /* total kinetic-energy change in Coulomb collisions, J */
   double coul_e;                                  /* kinetic energy of the collision pools before, J */
+  /* Diagnostics of the extracted ions and of the losses (Sec. III.B, III.D
+   * and the power balance of Sec. II).  An ion's birth is the step in which
+   * it was made from an atom (ionisation of Q = 0, or resonant Q = 1 charge
+   * exchange, which hands the charge to the neutral partner), or step 0 for
+   * the ions of ecr_init_ions; its first-passage time is (step of its
+   * extraction - birth) steps.  Ions of unknown birth (set_state without
+   * births) are counted in extracted but not here. */
+  uint64_t fpt_n[ECR_MAX_SPECIES][ECR_MAX_Q];       /* extracted ions of known birth, by charge at exit */
+  uint64_t fpt_sum[ECR_MAX_SPECIES][ECR_MAX_Q];     /* sum of their first-passage times, steps */
+  uint64_t fpt_hist[ECR_MAX_SPECIES][ECR_FPT_BINS]; /* all charges: bin k counts times t with floor(log2 t) = k (t <= 1 in bin 0) */
+  double extracted_r[ECR_MAX_SPECIES][ECR_MAX_Q];   /* sum of sqrt(x^2 + y^2) where the extracted ions cross the flange, m */
+  double lost_ke[ECR_MAX_SPECIES];                  /* kinetic energy of the ions (Q >= 1) lost to the walls and the aperture, J */
 } ecr_tallies;
 
 /* Host particle arrays indexed by particle id (length n). */
@@ -139,6 +153,7 @@ typedef struct {
   uint32_t *cell;    /* collision cell (cell of the last sort); set: may be NULL -> sorted at the next step */
   int64_t n;
   int64_t step;      /* step counter (Philox counter word 1) */
+  uint32_t *birth;   /* birth step (ECR_BIRTH_NONE: atom or unknown); may be NULL (set: all unknown) */
 } ecr_state_view;
 
 typedef struct ecr_run ecr_run;

@@ -10,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libecr_oracle.so")
 
 MAXS, MAXQ = 4, 32
+FPT_BINS = 32
+BIRTH_NONE = 0xFFFFFFFF
 
 
 class Species(C.Structure):
@@ -37,7 +39,9 @@ class Tallies(C.Structure):
                 ("ionized", (C.c_uint64 * MAXQ) * MAXS), ("cx", (C.c_uint64 * MAXQ) * MAXS),
                 ("cx_products", C.c_uint64 * MAXS), ("recycled", C.c_uint64), ("anomalies", C.c_uint64),
                 ("steps", C.c_int64), ("coul_dp", C.c_double * 3), ("coul_de", C.c_double),
-                ("coul_e", C.c_double)]
+                ("coul_e", C.c_double), ("fpt_n", (C.c_uint64 * MAXQ) * MAXS),
+                ("fpt_sum", (C.c_uint64 * MAXQ) * MAXS), ("fpt_hist", (C.c_uint64 * FPT_BINS) * MAXS),
+                ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS)]
 
 
 _lib = None
@@ -55,8 +59,8 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_init_ions.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
-        L.orc_set_state.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 8
-        L.orc_get_state.argtypes = [C.c_void_p, C.POINTER(C.c_int64)] + [C.c_void_p] * 9
+        L.orc_set_state.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 9
+        L.orc_get_state.argtypes = [C.c_void_p, C.POINTER(C.c_int64)] + [C.c_void_p] * 10
         L.orc_get_tallies.argtypes = [C.c_void_p, C.POINTER(Tallies)]
         L.orc_get_density.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_int64)]
         L.orc_get_events.argtypes = [C.c_void_p, C.c_void_p]
@@ -157,8 +161,9 @@ class OracleSim:
         a = {k: np.ascontiguousarray(st[k], dtype=np.float64) for k in ("x", "y", "z", "vx", "vy", "vz")}
         q = np.ascontiguousarray(st["q"], dtype=np.uint8)
         c = None if cell is None else np.ascontiguousarray(cell, dtype=np.uint32)
+        b = np.ascontiguousarray(st["birth"], dtype=np.uint32) if st.get("birth") is not None else None
         rc = lib().orc_set_state(self.h, step, _ptr(a["x"]), _ptr(a["y"]), _ptr(a["z"]), _ptr(a["vx"]),
-                                 _ptr(a["vy"]), _ptr(a["vz"]), _ptr(q), _ptr(c))
+                                 _ptr(a["vy"]), _ptr(a["vz"]), _ptr(q), _ptr(c), _ptr(b))
         if rc != 0:
             raise ValueError(f"orc_set_state failed ({rc})")
 
@@ -169,9 +174,10 @@ class OracleSim:
         out["species"] = np.empty(n, dtype=np.uint8)
         out["cell"] = np.empty(n, dtype=np.uint32)
         step = C.c_int64()
+        out["birth"] = np.empty(n, dtype=np.uint32)
         lib().orc_get_state(self.h, C.byref(step), _ptr(out["x"]), _ptr(out["y"]), _ptr(out["z"]),
                             _ptr(out["vx"]), _ptr(out["vy"]), _ptr(out["vz"]), _ptr(out["q"]),
-                            _ptr(out["species"]), _ptr(out["cell"]))
+                            _ptr(out["species"]), _ptr(out["cell"]), _ptr(out["birth"]))
         out["step"] = step.value
         return out
 
@@ -264,4 +270,9 @@ def tallies_to_dict(t):
         cx=np.array([[t.cx[s][q] for q in range(MAXQ)] for s in range(MAXS)], dtype=np.uint64),
         cx_products=np.array(t.cx_products[:], dtype=np.uint64),
         recycled=int(t.recycled), anomalies=int(t.anomalies), steps=int(t.steps),
-        coul_dp=np.array(t.coul_dp[:]), coul_de=float(t.coul_de), coul_e=float(t.coul_e))
+        coul_dp=np.array(t.coul_dp[:]), coul_de=float(t.coul_de), coul_e=float(t.coul_e),
+        fpt_n=np.array([t.fpt_n[s][:] for s in range(MAXS)], dtype=np.uint64),
+        fpt_sum=np.array([t.fpt_sum[s][:] for s in range(MAXS)], dtype=np.uint64),
+        fpt_hist=np.array([t.fpt_hist[s][:] for s in range(MAXS)], dtype=np.uint64),
+        extracted_r=np.array([t.extracted_r[s][:] for s in range(MAXS)], dtype=np.float64),
+        lost_ke=np.array(t.lost_ke[:], dtype=np.float64))

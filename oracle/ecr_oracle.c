@@ -64,6 +64,7 @@ struct orc_sim {
   double *x, *y, *z, *vx, *vy, *vz;
   uint8_t *q, *sp, *ev;
   uint32_t *cell;
+  uint32_t *birth;  /* step the ion was made from an atom, or ORC_BIRTH_NONE */
   /* cell order */
   uint32_t *order, *cell_off;
   int64_t step;
@@ -396,11 +397,11 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->vx = calloc(nd, 8); s->vy = calloc(nd, 8); s->vz = calloc(nd, 8);
   s->q = calloc(nd, 1); s->sp = calloc(nd, 1); s->ev = calloc(nd, 1);
   s->cell = calloc(nd, 4); s->order = calloc(nd, 4); s->id = calloc(nd, 4);
-  s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4);
+  s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4); s->birth = calloc(nd, 4);
   s->cell_off = calloc((size_t)s->ncell + 1, 4);
   for (int f = 0; f < 3; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
-      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->cell_off || !s->dens[0] ||
+      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->dens[0] ||
       !s->dens[1] || !s->dens[2]) {
     orc_destroy(s);
     return -2;
@@ -418,7 +419,7 @@ void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
   free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order); free(s->id);
-  free(s->pool); free(s->pkey); free(s->cell_off);
+  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off);
   for (int f = 0; f < 3; f++) free(s->dens[f]);
   free(s);
 }
@@ -461,6 +462,7 @@ int orc_init_ions(orc_sim *s) {
     s->x[i] = px; s->y[i] = py; s->z[i] = pz;
     s->vx[i] = sg * n0; s->vy[i] = sg * n1; s->vz[i] = sg * n2;
     s->q[i] = 1;
+    s->birth[i] = 0;
     s->ev[i] = ORC_EV_NONE;
   }
   s->step = 0;
@@ -654,6 +656,16 @@ static void reemit(orc_sim *s, int64_t i, const double n[3], const double t1[3],
   s->vz[i] = (vn * n[2] + sa * t1[2]) + sb * t2[2];
 }
 
+/* first-passage histogram bin: floor(log2 t), 0 for t <= 1 */
+static int fpt_bin_of(uint32_t t) {
+  int k = 0;
+  while (t >= 2u) {
+    t >>= 1;
+    k++;
+  }
+  return k;
+}
+
 static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
   double f;
   int kind = segment_exit(s, x0, y0, z0, s->x[i], s->y[i], s->z[i], &f);
@@ -662,9 +674,26 @@ static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
   double dx = s->x[i] - x0, dy = s->y[i] - y0, dz = s->z[i] - z0;
   double xc = x0 + f * dx, yc = y0 + f * dy, zc = z0 + f * dz;
   static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, pz[3] = {0, 0, 1}, mz[3] = {0, 0, -1};
+  /* an ion lost to a wall or the aperture carries its kinetic energy out of
+   * the plasma (power balance, Sec. II) and is an atom from now on */
+  if (Q >= 1) {
+    double v2 = (s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i];
+    s->t.lost_ke[sp] += 0.5 * s->M[sp] * v2;
+  }
+  uint32_t born = s->birth[i];
+  s->birth[i] = ORC_BIRTH_NONE;
   if (kind == X_EXT_FLANGE && xc * xc + yc * yc <= s->rap2) {
     s->t.extracted[sp][Q]++;
     s->t.recycled++;
+    /* radial size of the extracted beam (Sec. III.B) and first-passage time
+     * from the ion's birth (Sec. III.D) */
+    s->t.extracted_r[sp][Q] += sqrt(xc * xc + yc * yc);
+    if (Q >= 1 && born != ORC_BIRTH_NONE) {
+      uint32_t tp = (uint32_t)s->step - born;
+      s->t.fpt_n[sp][Q]++;
+      s->t.fpt_sum[sp][Q] += tp;
+      s->t.fpt_hist[sp][fpt_bin_of(tp)]++;
+    }
     s->q[i] = 0;
     s->x[i] = s->p.inlet_x;
     s->y[i] = s->p.inlet_y;
@@ -718,11 +747,14 @@ static int mcc(orc_sim *s, int64_t i) {
   if (pt > 0.1) s->t.anomalies++;
   if (u < pi) {
     s->t.ionized[sp][Q]++;
+    if (Q == 0) s->birth[i] = (uint32_t)s->step; /* an ion is made from an atom */
     s->q[i] = (uint8_t)(Q + 1);
     return ORC_EV_IONIZE;
   }
   if (u < pt) {
     s->t.cx[sp][Q]++;
+    /* resonant exchange hands the charge to the neutral: a new ion */
+    if (Q == 1) s->birth[i] = (uint32_t)s->step;
     uint32_t G[4], H[4];
     draw(s, s->id[i], (uint32_t)s->step, S_CX, 0, G);
     draw(s, s->id[i], (uint32_t)s->step, S_CX, 1, H);
@@ -826,15 +858,17 @@ int orc_step(orc_sim *s, int64_t n_steps) {
 /* ------------------------------------------------------------------------ */
 int orc_set_state(orc_sim *s, int64_t step, const double *x, const double *y, const double *z,
                   const double *vx, const double *vy, const double *vz, const uint8_t *q,
-                  const uint32_t *cell) {
+                  const uint32_t *cell, const uint32_t *birth) {
   for (int64_t i = 0; i < s->N; i++) {
     if (q[i] > s->p.sp[s->sp[i]].z_max) return -1;
     if (cell && cell[i] >= (uint32_t)s->ncell) return -1;
+    if (birth && q[i] >= 1 && birth[i] != ORC_BIRTH_NONE && (int64_t)birth[i] > step) return -1;
   }
   for (int64_t i = 0; i < s->N; i++) {
     s->x[i] = x[i]; s->y[i] = y[i]; s->z[i] = z[i];
     s->vx[i] = vx[i]; s->vy[i] = vy[i]; s->vz[i] = vz[i];
     s->q[i] = q[i];
+    s->birth[i] = (birth && q[i] >= 1) ? birth[i] : ORC_BIRTH_NONE;
     s->ev[i] = ORC_EV_NONE;
   }
   s->step = step;
@@ -850,7 +884,7 @@ int orc_set_state(orc_sim *s, int64_t step, const double *x, const double *y, co
 }
 
 int orc_get_state(const orc_sim *s, int64_t *step, double *x, double *y, double *z, double *vx,
-                  double *vy, double *vz, uint8_t *q, uint8_t *species, uint32_t *cell) {
+                  double *vy, double *vz, uint8_t *q, uint8_t *species, uint32_t *cell, uint32_t *birth) {
   size_t n8 = (size_t)s->N * 8;
   if (step) *step = s->step;
   if (x) memcpy(x, s->x, n8);
@@ -862,6 +896,7 @@ int orc_get_state(const orc_sim *s, int64_t *step, double *x, double *y, double 
   if (q) memcpy(q, s->q, (size_t)s->N);
   if (species) memcpy(species, s->sp, (size_t)s->N);
   if (cell) memcpy(cell, s->cell, (size_t)s->N * 4);
+  if (birth) memcpy(birth, s->birth, (size_t)s->N * 4);
   return 0;
 }
 

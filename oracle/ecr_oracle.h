@@ -21,6 +21,8 @@ extern "C" {
 
 #define ORC_MAXS 4   /* species */
 #define ORC_MAXQ 32  /* charge-state slots per species, Q = 0..31 */
+#define ORC_FPT_BINS 32            /* log2 bins of first-passage times */
+#define ORC_BIRTH_NONE 0xFFFFFFFFu /* birth of an atom or of an ion of unknown origin */
 
 /* process switches */
 #define ORC_P_PUSH 1u      /* Boris push + wall/aperture boundary */
@@ -81,6 +83,15 @@ typedef struct {
   double coul_dp[3];  /* total momentum change from Coulomb collisions, kg m/s */
   double coul_de;     /* total kinetic-energy change, J */
   double coul_e;      /* total kinetic energy of the collision pools before, J */
+  /* losses and extracted-ion diagnostics (Sec. II power balance, Sec. III.B
+   * radial size, Sec. III.D first-passage times); an ion's birth is the step
+   * in which it was made from an atom (ionisation of Q = 0, or resonant
+   * Q = 1 charge exchange), step 0 for the initial ions */
+  uint64_t fpt_n[ORC_MAXS][ORC_MAXQ];   /* extracted ions of known birth, by charge at exit */
+  uint64_t fpt_sum[ORC_MAXS][ORC_MAXQ]; /* sum of (extraction step - birth) */
+  uint64_t fpt_hist[ORC_MAXS][ORC_FPT_BINS]; /* bin floor(log2 t), t <= 1 in bin 0 */
+  double extracted_r[ORC_MAXS][ORC_MAXQ];    /* sum of the crossing radius of extracted particles, m */
+  double lost_ke[ORC_MAXS];             /* kinetic energy of ions (Q >= 1) lost to walls and aperture, J */
 } orc_tallies;
 
 typedef struct orc_sim orc_sim;
@@ -90,11 +101,12 @@ void orc_destroy(orc_sim *s);
 int orc_init_ions(orc_sim *s);
 int orc_step(orc_sim *s, int64_t n_steps);
 /* arrays indexed by particle id; cell may be NULL (then the next step sorts) */
+/* birth may be NULL: every ion of unknown birth (ORC_BIRTH_NONE) */
 int orc_set_state(orc_sim *s, int64_t step, const double *x, const double *y, const double *z,
                   const double *vx, const double *vy, const double *vz, const uint8_t *q,
-                  const uint32_t *cell);
+                  const uint32_t *cell, const uint32_t *birth);
 int orc_get_state(const orc_sim *s, int64_t *step, double *x, double *y, double *z, double *vx,
-                  double *vy, double *vz, uint8_t *q, uint8_t *species, uint32_t *cell);
+                  double *vy, double *vz, uint8_t *q, uint8_t *species, uint32_t *cell, uint32_t *birth);
 int orc_get_tallies(const orc_sim *s, orc_tallies *t);
 int orc_get_density(const orc_sim *s, int field, double *out, int64_t *steps);
 int orc_get_events(const orc_sim *s, uint8_t *out);

@@ -15,8 +15,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libecrpic.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAXS, MAXQ = 4, 32
+FPT_BINS = 32
+BIRTH_NONE = 0xFFFFFFFF
 FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL = 1, 2, 4, 8, 16, 31
 F_ION_N, F_ION_Q, F_ATOM_N, N_FIELDS = 0, 1, 2, 3
@@ -64,13 +66,15 @@ class Tallies(C.Structure):
                 ("ionized", (C.c_uint64 * MAXQ) * MAXS), ("cx", (C.c_uint64 * MAXQ) * MAXS),
                 ("cx_products", C.c_uint64 * MAXS), ("recycled", C.c_uint64), ("anomalies", C.c_uint64),
                 ("steps", C.c_int64), ("coul_dp", C.c_double * 3), ("coul_de", C.c_double),
-                ("coul_e", C.c_double)]
+                ("coul_e", C.c_double), ("fpt_n", (C.c_uint64 * MAXQ) * MAXS),
+                ("fpt_sum", (C.c_uint64 * MAXQ) * MAXS), ("fpt_hist", (C.c_uint64 * FPT_BINS) * MAXS),
+                ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS)]
 
 
 class StateView(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("vx", C.c_void_p),
                 ("vy", C.c_void_p), ("vz", C.c_void_p), ("q", C.c_void_p), ("species", C.c_void_p),
-                ("cell", C.c_void_p), ("n", C.c_int64), ("step", C.c_int64)]
+                ("cell", C.c_void_p), ("n", C.c_int64), ("step", C.c_int64), ("birth", C.c_void_p)]
 
 
 _lib = None
@@ -167,11 +171,13 @@ def _ptr(a):
 
 
 def tallies_to_dict(t):
-    g = lambda a: np.array([[a[s][q] for q in range(MAXQ)] for s in range(MAXS)], dtype=np.uint64)
+    g = lambda a: np.array([a[s][:] for s in range(MAXS)], dtype=np.uint64)
+    d = lambda a: np.array([a[s][:] for s in range(MAXS)], dtype=np.float64)
     return dict(extracted=g(t.extracted), wall=g(t.wall), ionized=g(t.ionized), cx=g(t.cx),
                 cx_products=np.array(t.cx_products[:], dtype=np.uint64), recycled=int(t.recycled),
                 anomalies=int(t.anomalies), steps=int(t.steps), coul_dp=np.array(t.coul_dp[:]),
-                coul_de=float(t.coul_de), coul_e=float(t.coul_e))
+                coul_de=float(t.coul_de), coul_e=float(t.coul_e), fpt_n=g(t.fpt_n), fpt_sum=g(t.fpt_sum),
+                fpt_hist=g(t.fpt_hist), extracted_r=d(t.extracted_r), lost_ke=np.array(t.lost_ke[:]))
 
 
 class Run:
@@ -238,7 +244,9 @@ class Run:
         out["q"] = np.empty(n, dtype=np.uint8)
         out["species"] = np.empty(n, dtype=np.uint8)
         out["cell"] = np.empty(n, dtype=np.uint32)
-        v = StateView(*(_ptr(out[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "q", "species", "cell")), n, 0)
+        out["birth"] = np.empty(n, dtype=np.uint32)
+        v = StateView(*(_ptr(out[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "q", "species", "cell")), n, 0,
+                      _ptr(out["birth"]))
         _check(lib().ecr_get_state(self.h, C.byref(v)), self.h)
         out["step"] = v.step
         return out
@@ -247,8 +255,9 @@ class Run:
         a = {k: np.ascontiguousarray(st[k], dtype=np.float64) for k in ("x", "y", "z", "vx", "vy", "vz")}
         q = np.ascontiguousarray(st["q"], dtype=np.uint8)
         c = None if cell is None else np.ascontiguousarray(cell, dtype=np.uint32)
+        b = np.ascontiguousarray(st["birth"], dtype=np.uint32) if st.get("birth") is not None else None
         v = StateView(*(_ptr(a[k]) for k in ("x", "y", "z", "vx", "vy", "vz")), _ptr(q), None, _ptr(c),
-                      self.n, int(step))
+                      self.n, int(step), _ptr(b))
         _check(lib().ecr_set_state(self.h, C.byref(v)), self.h)
 
     def events(self):

@@ -74,7 +74,13 @@ struct Soa {
   R *x, *y, *z, *vx, *vy, *vz;
   uint8_t *qs;   // charge state in bits 0-4, species in bits 5-7
   uint32_t *pid;
+  uint32_t *birth;  // step the ion was made from an atom (ECR_BIRTH_NONE: atom or unknown); touched on events only
 };
+
+constexpr uint32_t kBirthNone = 0xffffffffu;
+
+// first-passage histogram bin of a time of t steps: floor(log2 t), 0 for t <= 1
+__device__ __forceinline__ int fpt_bin(uint32_t t) { return t <= 1u ? 0 : 31 - __clz(t); }
 
 __device__ __forceinline__ int q_of(uint8_t qs) { return qs & 31; }
 __device__ __forceinline__ int sp_of(uint8_t qs) { return qs >> 5; }
@@ -291,14 +297,17 @@ __device__ __forceinline__ void reemit(const KParams &P, uint32_t id, uint32_t s
 
 // kind: from segment_exit; returns EV_WALL or EV_EXTRACT and sets q_new = 0
 template <typename R>
+// rc2: squared radius of the crossing point, set for an extraction
 __device__ __forceinline__ uint8_t wall_event(const KParams &P, uint32_t id, uint32_t step, int s, int kind,
-                                              R f, R x0, R y0, R z0, R &x, R &y, R &z, R &vx, R &vy, R &vz) {
+                                              R f, R x0, R y0, R z0, R &x, R &y, R &z, R &vx, R &vy, R &vz,
+                                              R &rc2) {
   const R dx = x - x0, dy = y - y0, dz = z - z0;
   const R xc = x0 + f * dx, yc = y0 + f * dy, zc = z0 + f * dz;
   const R ex[3] = {(R)1, (R)0, (R)0}, ey[3] = {(R)0, (R)1, (R)0};
   const R pz[3] = {(R)0, (R)0, (R)1}, mz[3] = {(R)0, (R)0, (R)-1};
   const R hL = (R)P.hL, eps = (R)kWallEps;
   if (kind == X_EXT && xc * xc + yc * yc <= (R)P.rap2) {
+    rc2 = xc * xc + yc * yc;
     x = (R)P.inlet_x;
     y = (R)P.inlet_y;
     z = -hL + eps;

@@ -14,6 +14,8 @@ namespace ecr {
 constexpr int kCoulCap = 256;
 constexpr int kCoulMaxE = 1024;
 
+static_assert(kBirthNone == ECR_BIRTH_NONE, "birth sentinel");
+
 // Error bits raised by kernels (read back with the tallies).
 enum : uint32_t { ERR_COUL_OVERFLOW = 1 };
 

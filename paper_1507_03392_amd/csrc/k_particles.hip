@@ -60,17 +60,21 @@ __global__ void __launch_bounds__(256) k_init(KParams P, Soa<R> S) {
   S.vz[i] = (R)(sg * n2);
   S.qs[i] = make_qs(1, s);
   S.pid[i] = id;
+  S.birth[i] = 0u;  // created at step 0
 }
 
 // ---------------------------------------------------------------------------
 // One particle: push -> wall/aperture -> ionisation / charge exchange.
 // Tallies are rare events (~1e-4 per particle-step) and go straight to
-// 64-bit global atomics.  Returns the event code.
+// 64-bit global atomics; so do the loss diagnostics (first-passage times,
+// crossing radius, lost kinetic energy), and the particle's birth step
+// (birth[j]) is read or written only on such events.  Returns the event code.
 // ---------------------------------------------------------------------------
 template <typename R, bool HAS_E>
 __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
                                            const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
-                                           uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz) {
+                                           uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz,
+                                           uint32_t *__restrict__ birth, int64_t j) {
   uint8_t ev = EV_NONE;
   if (P.pmask & P_PUSH) {
     const R x0 = x, y0 = y, z0 = z;
@@ -81,13 +85,27 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     R f;
     const int kind = segment_exit<R>(P, x0, y0, z0, x, y, z, f);
     if (kind != X_NONE) {
-      ev = wall_event<R>(P, id, step, s, kind, f, x0, y0, z0, x, y, z, vx, vy, vz);
+      if (Q >= 1) {
+        const double ke = 0.5 * P.mass[s] * (double)((vx * vx + vy * vy) + vz * vz);
+        unsafeAtomicAdd(&acc->t.lost_ke[s], ke);
+      }
+      R rc2 = (R)0;
+      ev = wall_event<R>(P, id, step, s, kind, f, x0, y0, z0, x, y, z, vx, vy, vz, rc2);
       if (ev == EV_EXTRACT) {
         atomicAdd((unsigned long long *)&acc->t.extracted[s][Q], 1ull);
         atomicAdd((unsigned long long *)&acc->t.recycled, 1ull);
+        unsafeAtomicAdd(&acc->t.extracted_r[s][Q], (double)sqrt(rc2));
+        const uint32_t b = birth[j];
+        if (Q >= 1 && b != kBirthNone) {
+          const uint32_t t = step - b;
+          atomicAdd((unsigned long long *)&acc->t.fpt_n[s][Q], 1ull);
+          atomicAdd((unsigned long long *)&acc->t.fpt_sum[s][Q], (unsigned long long)t);
+          atomicAdd((unsigned long long *)&acc->t.fpt_hist[s][fpt_bin(t)], 1ull);
+        }
       } else {
         atomicAdd((unsigned long long *)&acc->t.wall[s][Q], 1ull);
       }
+      if (Q >= 1) birth[j] = kBirthNone;  // now an atom
       Q = 0;
     }
   }
@@ -105,10 +123,12 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     if (pt > 0.1) atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
     if (u < pi) {
       atomicAdd((unsigned long long *)&acc->t.ionized[s][Q], 1ull);
+      if (Q == 0) birth[j] = step;  // an ion is made from an atom
       Q = Q + 1;
       ev = EV_IONIZE;
     } else if (u < pt) {
       atomicAdd((unsigned long long *)&acc->t.cx[s][Q], 1ull);
+      if (Q == 1) birth[j] = step;  // resonant exchange: the ion is the former neutral
       cx_outcome<R>(P, id, step, s, Q, vx, vy, vz);
       if (Q >= 2) {
         Q = Q - 1;
@@ -391,7 +411,7 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
     const uint32_t id = S.pid[j];
     int Q = q_of(qs0);
     const int s = sp_of(qs0);
-    const uint8_t ev = advance<R, HAS_E>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz);
+    const uint8_t ev = advance<R, HAS_E>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j);
     S.x[j] = x;
     S.y[j] = y;
     S.z[j] = z;

@@ -144,6 +144,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(KParams P, Soa<R> A, Soa<R
   B.vz[d] = A.vz[j];
   B.qs[d] = A.qs[j];
   B.pid[d] = A.pid[j];
+  B.birth[d] = A.birth[j];
   cellid[d] = c;
 }
 

@@ -29,7 +29,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t soa[2][8];  // offsets of x y z vx vy vz qs pid in buffer A and B
+  size_t soa[2][9];  // offsets of x y z vx vy vz qs pid birth in buffer A and B
   size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, evlog;
   size_t total;
 };
@@ -50,6 +50,8 @@ Layout make_layout(const ecr_params *p) {
     L.soa[b][6] = o;
     o = align_up(o + N);
     L.soa[b][7] = o;
+    o = align_up(o + 4 * N);
+    L.soa[b][8] = o;
     o = align_up(o + 4 * N);
   }
   L.key = o;
@@ -227,6 +229,7 @@ Soa<R> soa(ecr_run *r, int b) {
   s.vz = at<R>(r, r->L.soa[b][5]);
   s.qs = at<uint8_t>(r, r->L.soa[b][6]);
   s.pid = at<uint32_t>(r, r->L.soa[b][7]);
+  s.birth = at<uint32_t>(r, r->L.soa[b][8]);
   return s;
 }
 
@@ -487,7 +490,7 @@ ecr_status get_state_t(ecr_run *r, ecr_state_view *v) {
   const int64_t n = r->kp.n;
   std::vector<R> buf[6];
   std::vector<uint8_t> qs(n);
-  std::vector<uint32_t> pid(n), cell(n);
+  std::vector<uint32_t> pid(n), cell(n), birth(n);
   hipError_t e = hipSuccess;
   for (int k = 0; k < 6 && e == hipSuccess; ++k) {
     buf[k].resize(n);
@@ -498,6 +501,8 @@ ecr_status get_state_t(ecr_run *r, ecr_state_view *v) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(pid.data(), r->base + r->L.soa[r->cur][7], 4 * n, hipMemcpyDeviceToHost, r->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(cell.data(), r->base + r->L.cellid, 4 * n, hipMemcpyDeviceToHost, r->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(birth.data(), r->base + r->L.soa[r->cur][8], 4 * n, hipMemcpyDeviceToHost, r->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
   if (e != hipSuccess) return check_hip(r, e, "get_state");
   double *dst[6] = {v->x, v->y, v->z, v->vx, v->vy, v->vz};
@@ -509,6 +514,7 @@ ecr_status get_state_t(ecr_run *r, ecr_state_view *v) {
     if (v->q) v->q[i] = qs[j] & 31;
     if (v->species) v->species[i] = qs[j] >> 5;
     if (v->cell) v->cell[i] = cell[j];
+    if (v->birth) v->birth[i] = birth[j];
   }
   v->step = r->step;
   return ECR_OK;
@@ -520,7 +526,7 @@ ecr_status set_state_t(ecr_run *r, const ecr_state_view *v) {
   std::vector<R> buf[6];
   const double *src[6] = {v->x, v->y, v->z, v->vx, v->vy, v->vz};
   std::vector<uint8_t> qs(n);
-  std::vector<uint32_t> pid(n);
+  std::vector<uint32_t> pid(n), birth(n);
   for (int64_t i = 0; i < n; ++i) {
     int s = r->kp.nspecies - 1;
     for (int k = r->kp.nspecies - 1; k >= 0; --k)
@@ -529,6 +535,9 @@ ecr_status set_state_t(ecr_run *r, const ecr_state_view *v) {
     if (v->cell && v->cell[i] >= (uint32_t)r->ncell) return fail(r, ECR_EINVAL, "cell out of range");
     qs[i] = (uint8_t)(v->q[i] | (s << 5));
     pid[i] = (uint32_t)i;
+    birth[i] = v->birth && v->q[i] >= 1 ? v->birth[i] : ECR_BIRTH_NONE;
+    if (birth[i] != ECR_BIRTH_NONE && (int64_t)birth[i] > v->step)
+      return fail(r, ECR_EINVAL, "birth step after the state's step");
   }
   for (int k = 0; k < 6; ++k) {
     buf[k].resize(n);
@@ -540,6 +549,8 @@ ecr_status set_state_t(ecr_run *r, const ecr_state_view *v) {
     e = hipMemcpyAsync(r->base + r->L.soa[0][k], buf[k].data(), sizeof(R) * n, hipMemcpyHostToDevice, r->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(r->base + r->L.soa[0][6], qs.data(), n, hipMemcpyHostToDevice, r->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(r->base + r->L.soa[0][7], pid.data(), 4 * n, hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(r->base + r->L.soa[0][8], birth.data(), 4 * n, hipMemcpyHostToDevice, r->stream);
   // given collision cells (by id) are staged in buffer B's id array: the
   // sort's count pass reads them before its scatter overwrites buffer B
   if (e == hipSuccess && v->cell)

@@ -203,7 +203,7 @@ def test_fp32_two_species_c4_full_size_sampled_cells():
     sub = W.with_(params, n=len(ids), weight=g.weight, precision=W.PREC_FP64)
     o = OracleSim(sub)
     o.set_ids(ids, before["species"][ids])
-    o.set_state({k: before[k][ids] for k in ("x", "y", "z", "vx", "vy", "vz", "q")}, step=60,
+    o.set_state({k: before[k][ids] for k in ("x", "y", "z", "vx", "vy", "vz", "q", "birth")}, step=60,
                 cell=before["cell"][ids])
     o.step(1)
     assert_close32(after, o.get_state(), params, ids=ids, what="c4 sampled")

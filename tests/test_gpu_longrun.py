@@ -38,7 +38,7 @@ def oracle_tallies():
 
 
 def _within_sampling(tg, to, what):
-    for k in ("extracted", "wall", "ionized"):
+    for k in ("extracted", "wall", "ionized", "fpt_n"):
         g, o = tg[k].astype(np.float64), to[k].astype(np.float64)
         bad = np.abs(g - o) > 3 * np.sqrt(np.maximum(o, 1.0)) + 2
         assert not bad.any(), f"{what} {k}: {g[bad.nonzero()]} vs {o[bad.nonzero()]}"
@@ -58,5 +58,9 @@ def test_long_run_extracted_spectrum(oracle_tallies, prec):
     eg, eo = tg["extracted"][0][1:5], to["extracted"][0][1:5]
     print(f"precision {prec}: extracted Q=1..4 GPU {eg.tolist()} oracle {eo.tolist()}, "
           f"relative error {np.round(eg / eo - 1, 4).tolist()}")
+    n, t = tg["fpt_n"][0][1:5], tg["fpt_sum"][0][1:5] * _params()["dt"] * 1e6
+    no, to_ = to["fpt_n"][0][1:5], to["fpt_sum"][0][1:5] * _params()["dt"] * 1e6
+    print(f"  mean first-passage time Q=1..4 (us): GPU {np.round(t / np.maximum(n, 1), 3).tolist()} "
+          f"oracle {np.round(to_ / np.maximum(no, 1), 3).tolist()}")
     # the recycled count is the extracted total (every extracted ion re-enters at the inlet)
     assert tg["recycled"] == tg["extracted"].sum()

@@ -152,13 +152,15 @@ def with_(params, **kw):
     return q
 
 
-def random_state(params, seed, q_max=None, frac_atoms=0.1, v_ev=0.5, radius_frac=0.95, mass_amu=39.948):
+def random_state(params, seed, q_max=None, frac_atoms=0.1, v_ev=0.5, radius_frac=0.95, mass_amu=39.948,
+                 birth_max=None):
     """Seeded synthetic particle state, indexed by particle id.
 
     Positions uniform in the cylinder r < radius_frac R0, |z| < radius_frac L/2;
     velocities Maxwellian with sigma = sqrt(v_ev e / m) for a mass of mass_amu;
     charge states uniform in [1, q_max] (default: the smallest z_max of the
-    species), then a fraction frac_atoms set to Q = 0.
+    species), then a fraction frac_atoms set to Q = 0.  With birth_max, the
+    ions get birth steps uniform in [0, birth_max] (atoms 0xFFFFFFFF).
     """
     rng = np.random.default_rng(seed)
     n = params["n"]
@@ -175,4 +177,8 @@ def random_state(params, seed, q_max=None, frac_atoms=0.1, v_ev=0.5, radius_frac
     qm = min(s["z_max"] for s in params["species"]) if q_max is None else q_max
     q = (1 + np.floor(rng.random(n) * qm)).astype(np.uint8)
     q[rng.random(n) < frac_atoms] = 0
-    return dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, q=q)
+    out = dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, q=q)
+    if birth_max is not None:
+        b = rng.integers(0, birth_max + 1, n).astype(np.uint32)
+        out["birth"] = np.where(q >= 1, b, np.uint32(0xFFFFFFFF)).astype(np.uint32)
+    return out
