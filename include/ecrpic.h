@@ -68,7 +68,14 @@ enum {
 };
 
 /* density fields (bit f of deposit_mask enables field f) */
-enum { ECR_F_ION_N = 0, ECR_F_ION_Q = 1, ECR_F_ATOM_N = 2, ECR_N_FIELDS = 3 };
+enum {
+  ECR_F_ION_N = 0,  /* sum of CIC weights of ions (Q >= 1) */
+  ECR_F_ION_Q = 1,  /* sum of Q x CIC weight of ions */
+  ECR_F_ATOM_N = 2, /* sum of CIC weights of atoms (Q = 0) */
+  ECR_F_ION_P = 3,  /* sum of CIC weight x M |v|^2 / 3 of ions, J: with no mean flow, the ion pressure
+                       n k T (Sec. III.B) times the node volume; its own kernel, only when requested */
+  ECR_N_FIELDS = 4
+};
 
 /* run flags */
 enum {

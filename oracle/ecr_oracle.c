@@ -70,7 +70,7 @@ struct orc_sim {
   int64_t step;
   int need_sort;
   orc_tallies t;
-  double *dens[3];
+  double *dens[ORC_NFIELDS];
   int64_t dens_steps;
   /* scratch for the Coulomb pools */
   uint32_t *pool;
@@ -399,10 +399,10 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->cell = calloc(nd, 4); s->order = calloc(nd, 4); s->id = calloc(nd, 4);
   s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4); s->birth = calloc(nd, 4);
   s->cell_off = calloc((size_t)s->ncell + 1, 4);
-  for (int f = 0; f < 3; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
+  for (int f = 0; f < ORC_NFIELDS; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
       !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->dens[0] ||
-      !s->dens[1] || !s->dens[2]) {
+      !s->dens[1] || !s->dens[2] || !s->dens[3]) {
     orc_destroy(s);
     return -2;
   }
@@ -420,7 +420,7 @@ void orc_destroy(orc_sim *s) {
   free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
   free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order); free(s->id);
   free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off);
-  for (int f = 0; f < 3; f++) free(s->dens[f]);
+  for (int f = 0; f < ORC_NFIELDS; f++) free(s->dens[f]);
   free(s);
 }
 
@@ -428,7 +428,7 @@ double orc_weight(const orc_sim *s) { return s->w; }
 
 static void zero_accumulators(orc_sim *s) {
   memset(&s->t, 0, sizeof(s->t));
-  for (int f = 0; f < 3; f++) memset(s->dens[f], 0, (size_t)s->nnode * 8);
+  for (int f = 0; f < ORC_NFIELDS; f++) memset(s->dens[f], 0, (size_t)s->nnode * 8);
   s->dens_steps = 0;
 }
 
@@ -795,7 +795,14 @@ static void deposit(orc_sim *s) {
   for (int64_t i = 0; i < s->N; i++) {
     int Q = s->q[i];
     int ion = Q >= 1;
-    if (!((ion && (dm & 3u)) || (!ion && (dm & 4u)))) continue;
+    if (!((ion && (dm & 11u)) || (!ion && (dm & 4u)))) continue;
+    /* ion pressure moment (Sec. III.B): with no mean flow, an ion of speed v
+     * adds M v^2 / 3 = k T to n k T */
+    double e = 0.0;
+    if (ion && (dm & 8u)) {
+      double v2 = (s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i];
+      e = (s->M[s->sp[i]] * v2) / 3.0;
+    }
     int ix, iy, iz;
     double tx, ty, tz;
     cic_axis(s->x[i], s->p.R0, s->idx, s->p.nx, &ix, &tx);
@@ -810,6 +817,7 @@ static void deposit(orc_sim *s) {
           if (ion) {
             if (dm & 1u) s->dens[ORC_F_ION_N][node] += w;
             if (dm & 2u) s->dens[ORC_F_ION_Q][node] += (double)Q * w;
+            if (dm & 8u) s->dens[ORC_F_ION_P][node] += w * e;
           } else {
             s->dens[ORC_F_ATOM_N][node] += w;
           }
@@ -928,7 +936,7 @@ int orc_get_tallies(const orc_sim *s, orc_tallies *t) {
 }
 
 int orc_get_density(const orc_sim *s, int field, double *out, int64_t *steps) {
-  if (field < 0 || field > 2) return -1;
+  if (field < 0 || field >= ORC_NFIELDS) return -1;
   memcpy(out, s->dens[field], (size_t)s->nnode * 8);
   if (steps) *steps = s->dens_steps;
   return 0;

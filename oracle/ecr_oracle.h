@@ -35,6 +35,8 @@ extern "C" {
 #define ORC_F_ION_N 0  /* sum of CIC weights of ions (Q >= 1) */
 #define ORC_F_ION_Q 1  /* sum of Q * CIC weight of ions */
 #define ORC_F_ATOM_N 2 /* sum of CIC weights of atoms (Q = 0) */
+#define ORC_F_ION_P 3  /* sum of CIC weight * M |v|^2 / 3 of ions (J): ion pressure x cell volume */
+#define ORC_NFIELDS 4
 
 /* per-particle event codes of the last step */
 #define ORC_EV_NONE 0

@@ -21,7 +21,7 @@ FPT_BINS = 32
 BIRTH_NONE = 0xFFFFFFFF
 FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL = 1, 2, 4, 8, 16, 31
-F_ION_N, F_ION_Q, F_ATOM_N, N_FIELDS = 0, 1, 2, 3
+F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P, N_FIELDS = 0, 1, 2, 3, 4
 FLAG_EVENTS, FLAG_SPLIT = 1, 2
 K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, N_KERNELS = 0, 1, 2, 3, 4, 5, 6
 KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_pairs"]

@@ -45,6 +45,10 @@ void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st);
 
+// optional ion pressure moment (field ECR_F_ION_P)
+template <typename R>
+void launch_deposit_pressure(const KParams &P, Soa<R> S, double *dens, hipStream_t st);
+
 // Coulomb chunk table: chunk b covers slots [chunk_lo[b], chunk_lo[b+1]),
 // nchunks+1 entries, rebuilt after every sort
 int64_t coul_nchunks(int64_t n);

@@ -443,6 +443,152 @@ __global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double 
   deposit_staged<R>(P, dens, sh, box, mn, mx);
 }
 
+// ---------------------------------------------------------------------------
+// Ion pressure moment (optional field ECR_F_ION_P, Sec. III.B): every ion
+// adds its CIC weights times M |v|^2 / 3.  The tile scheme of the number and
+// charge deposit (lane = slot staging, transposed runs of 4 slots, wavefront
+// segmented sums, LDS brick) with one field and a weight per particle.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PStage {
+  R t[3][kStage];
+  uint16_t c[3][kStage];
+  double e[kStage];  // M |v|^2 / 3, or < 0: nothing to deposit
+};
+
+template <typename R>
+union PShared {
+  PStage<R> st;
+  double brick[3 * kBrickNodes];  // one field: three times the nodes of the number brick
+};
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_deposit_pressure(KParams P, Soa<R> S, double *__restrict__ dens) {
+  __shared__ PShared<R> sh;
+  __shared__ int box[6];
+  box_init(box);
+  const int tid = threadIdx.x;
+  int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    const int i = tid + p * kBlock;
+    const int64_t j = base + i;
+    const int k = kPad(i);
+    sh.st.e[k] = -1.0;
+    if (j < P.n) {
+      const uint8_t qs = S.qs[j];
+      if (q_of(qs) >= 1) {
+        const R vx = S.vx[j], vy = S.vy[j], vz = S.vz[j];
+        int ix, iy, iz;
+        R tx, ty, tz;
+        cic_axis<R>(S.x[j], (R)P.R0, (R)P.idx, P.nx, ix, tx);
+        cic_axis<R>(S.y[j], (R)P.R0, (R)P.idy, P.ny, iy, ty);
+        cic_axis<R>(S.z[j], (R)P.hL, (R)P.idz, P.nz, iz, tz);
+        sh.st.t[0][k] = tx;
+        sh.st.t[1][k] = ty;
+        sh.st.t[2][k] = tz;
+        sh.st.c[0][k] = (uint16_t)ix;
+        sh.st.c[1][k] = (uint16_t)iy;
+        sh.st.c[2][k] = (uint16_t)iz;
+        sh.st.e[k] = (P.mass[sp_of(qs)] * (double)((vx * vx + vy * vy) + vz * vz)) / 3.0;
+        mn[0] = min(mn[0], ix);
+        mn[1] = min(mn[1], iy);
+        mn[2] = min(mn[2], iz);
+        mx[0] = max(mx[0], ix);
+        mx[1] = max(mx[1], iy);
+        mx[2] = max(mx[2], iz);
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
+      mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
+    }
+  if ((tid & 63) == 0)
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&box[d], mn[d]);
+      atomicMax(&box[3 + d], mx[d]);
+    }
+  __syncthreads();  // staging and box complete
+  int ix[kP], iy[kP], iz[kP];
+  R tx[kP], ty[kP], tz[kP];
+  double e[kP];
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    const int k = kPad(tid * kP + p);
+    e[p] = sh.st.e[k];
+    tx[p] = sh.st.t[0][k];
+    ty[p] = sh.st.t[1][k];
+    tz[p] = sh.st.t[2][k];
+    ix[p] = sh.st.c[0][k];
+    iy[p] = sh.st.c[1][k];
+    iz[p] = sh.st.c[2][k];
+  }
+  const int x0 = box[0], y0 = box[1], z0 = box[2];
+  const bool any = box[3] >= 0;
+  const int bx = box[3] - x0 + 2, by = box[4] - y0 + 2, bz = box[5] - z0 + 2;
+  __syncthreads();  // staging read: the brick may now reuse it
+  if (!any) return;
+  const int64_t nodes = (int64_t)bx * by * bz;
+  const bool in_brick = nodes <= 3 * kBrickNodes;
+  const int nb = (int)(in_brick ? nodes : 0);
+  const int nx1 = P.nx1, ny1 = P.ny1;
+  double *f3 = dens + (int64_t)ECR_F_ION_P * P.nnode;
+  auto node_of = [&](int p) -> int64_t {
+    return in_brick ? (int64_t)((ix[p] - x0) + bx * ((iy[p] - y0) + by * (iz[p] - z0)))
+                    : (int64_t)ix[p] + (int64_t)nx1 * (iy[p] + (int64_t)ny1 * iz[p]);
+  };
+  auto flush = [&](int64_t nd, const double *a) {
+    for (int k = 0; k < 8; ++k) {
+      if (a[k] == 0.0) continue;
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+      if (in_brick) atomicAdd(&sh.brick[(int)nd + dx + bx * (dy + by * dz)], a[k]);
+      else unsafeAtomicAdd(&f3[nd + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz)], a[k]);
+    }
+  };
+  if (in_brick) {
+    for (int i = tid; i < nb; i += kBlock) sh.brick[i] = 0.0;
+    __syncthreads();
+  }
+  // this lane's runs of equal base node; the last one goes to the wavefront sum
+  double a[8];
+  int64_t cur = -1;
+  for (int k = 0; k < 8; ++k) a[k] = 0.0;
+#pragma unroll
+  for (int p = 0; p < kP; ++p) {
+    if (!(e[p] >= 0.0)) continue;
+    const int64_t nd = node_of(p);
+    if (nd != cur) {
+      if (cur >= 0) flush(cur, a);
+      cur = nd;
+      for (int k = 0; k < 8; ++k) a[k] = 0.0;
+    }
+    const R wx[2] = {(R)1 - tx[p], tx[p]}, wy[2] = {(R)1 - ty[p], ty[p]}, wz[2] = {(R)1 - tz[p], tz[p]};
+    int k = 0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx, ++k) a[k] += (double)((wx[dx] * wy[dy]) * wz[dz]) * e[p];
+  }
+  const int lane = tid & 63;
+  const int64_t key = cur;
+  const int64_t kprev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || kprev != key;
+  const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+  wave_segment_sum(seg, a);
+  if (head && key >= 0) flush(key, a);
+  if (!in_brick) return;
+  __syncthreads();
+  for (int li = tid; li < nb; li += kBlock) {
+    const double v = sh.brick[li];
+    if (v != 0.0) {
+      const int t = li / bx, lx = li - t * bx, lz = t / by, ly = t - lz * by;
+      unsafeAtomicAdd(&f3[(int64_t)(x0 + lx) + (int64_t)nx1 * ((y0 + ly) + (int64_t)ny1 * (z0 + lz))], v);
+    }
+  }
+}
+
 static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 template <typename R>
@@ -471,6 +617,14 @@ void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {
   hipLaunchKernelGGL(k_deposit<R>, dim3(grid_for(P.n, kTile)), dim3(kBlock), 0, st, P, S, dens);
 }
 
+template <typename R>
+void launch_deposit_pressure(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {
+  if (P.n <= 0) return;
+  hipLaunchKernelGGL(k_deposit_pressure<R>, dim3(grid_for(P.n, kTile)), dim3(kBlock), 0, st, P, S, dens);
+}
+
+template void launch_deposit_pressure<double>(const KParams &, Soa<double>, double *, hipStream_t);
+template void launch_deposit_pressure<float>(const KParams &, Soa<float>, double *, hipStream_t);
 template void launch_init<double>(const KParams &, Soa<double>, hipStream_t);
 template void launch_init<float>(const KParams &, Soa<float>, hipStream_t);
 template void launch_push<double>(const KParams &, const Tables *, Soa<double>, const double *, uint8_t *, DevAccum *,

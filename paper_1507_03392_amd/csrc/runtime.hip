@@ -251,6 +251,7 @@ std::string validate(const ecr_params *p) {
   if (p->n_particles < 0 || p->n_particles > 0x7fffffffLL) return "n_particles out of range";
   if (!(p->dt_s > 0.0) || !isfinite(p->dt_s)) return "dt_s must be positive";
   if (p->sort_every < 1) return "sort_every must be >= 1";
+  if (p->deposit_mask >= (1u << ECR_N_FIELDS)) return "deposit_mask has unknown bits";
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "mesh dimensions must be >= 1";
   if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 31) - 1) return "mesh too large";
   if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 30)) return "mesh too large for 64-bit pairing keys";
@@ -468,6 +469,10 @@ void do_step(ecr_run *r, StepArg stepw) {
   if (dep && split) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
+  }
+  if (dep && (r->p.deposit_mask & (1u << ECR_F_ION_P))) {
+    ProfScope ps(r, ECR_K_DEPOSIT);
+    launch_deposit_pressure<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
   }
   if (dep) r->dens_steps++;
   r->step++;

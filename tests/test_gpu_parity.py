@@ -124,7 +124,7 @@ CASES = {
 def test_single_step_parity(case, seed):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
-    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=7, weight=4e9)
+    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=15, weight=4e9)
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     st = W.random_state(params, seed=100 + seed, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95),
@@ -147,7 +147,7 @@ def test_single_step_parity(case, seed):
         assert abs(tg["coul_de"]) <= 1e-12 * tg["coul_e"]
         assert tg["coul_e"] == pytest.approx(to["coul_e"], rel=1e-12)
     if c["mask"] & W.P_DEPOSIT:
-        for f in (W.F_ION_N, W.F_ION_Q, W.F_ATOM_N):
+        for f in (W.F_ION_N, W.F_ION_Q, W.F_ATOM_N, W.F_ION_P):
             dg, sg = g.density(f)
             do, so = o.density(f)
             assert sg == so == 1

@@ -14,10 +14,14 @@
 * Lost kinetic energy (the power balance of Sec. II): the Boris rotation
   keeps |v| with no electric field, so each ion lost in a step carries
   1/2 M |v|^2 of its state before the step.
+* Ion pressure moment (Sec. III.B, P = sum_Q n_Q T_Q): the optional field
+  equals the brute-force tent sums of M |v|^2 / 3, and for the Maxwellian
+  initial ions its total over the ion number is k T_i0.
 """
 import math
 
 import numpy as np
+import pytest
 
 import workloads as W
 from oracle.binding import BIRTH_NONE, OracleSim
@@ -127,3 +131,37 @@ def test_lost_kinetic_energy_of_ions():
     v2 = st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2
     ke = 0.5 * p["species"][0]["mass_amu"] * AMU * v2[lost].sum()
     assert math.isclose(t["lost_ke"][0], ke, rel_tol=1e-12)
+
+
+def test_ion_pressure_field_brute_force_and_equipartition():
+    # field 3: sum over ions of CIC weight x M |v|^2 / 3; with a Maxwellian at
+    # T its total over the nodes is N k T (the CIC weights of a particle sum
+    # to 1), so total pressure moment / total ion number = k T
+    p = W.base_params(20_000, 8, 8, 16, seed=6)
+    p.update(process_mask=W.P_DEPOSIT, deposit_mask=(1 << W.F_ION_N) | (1 << W.F_ION_P))
+    o = OracleSim(p)
+    o.init_ions()
+    o.step(1)
+    st = o.get_state()
+    dp, steps = o.density(W.F_ION_P)
+    dn, _ = o.density(W.F_ION_N)
+    assert steps == 1
+    m = p["species"][0]["mass_amu"] * AMU
+    e = m * (st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2) / 3.0
+    # brute force: every node's tent-function sum
+    R0, hL, nx, ny, nz = p["R0"], p["L"] / 2, p["nx"], p["ny"], p["nz"]
+    gx = (st["x"] + R0) * nx / (2 * R0)
+    gy = (st["y"] + R0) * ny / (2 * R0)
+    gz = (st["z"] + hL) * nz / (2 * hL)
+    brute = np.zeros((nz + 1, ny + 1, nx + 1))
+    for i in range(len(e)):
+        ix, iy, iz = min(int(gx[i]), nx - 1), min(int(gy[i]), ny - 1), min(int(gz[i]), nz - 1)
+        tx, ty, tz = gx[i] - ix, gy[i] - iy, gz[i] - iz
+        for dz, wz in ((0, 1 - tz), (1, tz)):
+            for dy, wy in ((0, 1 - ty), (1, ty)):
+                for dx, wx in ((0, 1 - tx), (1, tx)):
+                    brute[iz + dz, iy + dy, ix + dx] += wx * wy * wz * e[i]
+    assert np.abs(dp - brute.ravel()).max() <= 1e-9 * np.abs(brute).max()
+    kT = p["Ti0_eV"] * 1.602176634e-19
+    assert dn.sum() == pytest.approx(20_000, rel=1e-12)
+    assert dp.sum() / dn.sum() == pytest.approx(kT, rel=0.02)

@@ -28,7 +28,7 @@ P_COULOMB = 8
 P_DEPOSIT = 16
 P_ALL = P_PUSH | P_IONIZE | P_CX | P_COULOMB | P_DEPOSIT
 
-F_ION_N, F_ION_Q, F_ATOM_N = 0, 1, 2
+F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P = 0, 1, 2, 3
 
 EV_NONE, EV_IONIZE, EV_CX, EV_WALL, EV_EXTRACT = 0, 1, 2, 3, 4
 
