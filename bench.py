@@ -36,7 +36,9 @@ def describe(name, p):
     prec = "FP32-mixed (binary32 state, binary64 accumulators)" if p.get("precision", 0) else "FP64"
     mix = " + ".join(f"{round(100 * s['fraction'])}% {'O' if s['z_max'] == 8 else 'Ar'} (Q<={s['z_max']})"
                      for s in p["species"])
-    return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, "
+    ne = "self-consistent electrons (n_e = ion charge density per cell)" if p.get("self_ne") else \
+        "fixed electron background"
+    return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, {ne}, "
             f"mesh {p['nx']}x{p['ny']}x{p['nz']}, dt {p['dt']:g} s, sort every {p['sort_every']}, "
             f"all processes on")
 
@@ -189,6 +191,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
+    ap.add_argument("--self-ne", action="store_true",
+                    help="electron density = ion charge density per cell (self-consistent electrons)")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
     ap.add_argument("--slots", type=int, default=16, help="c5: run slots (one HIP stream each)")
     ap.add_argument("--split", action="store_true",
@@ -220,6 +224,8 @@ def main():
         del a, b
 
     params, _ = W.config(args.workload)
+    if args.self_ne:
+        params["self_ne"] = True
     n = params["n"]
     fp32 = params.get("precision", 0) == ecr.FP32_MIXED
     log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")

@@ -31,7 +31,7 @@ class Params(C.Structure):
                 ("Ti0_eV", C.c_double), ("T_wall_eV", C.c_double), ("T_n_eV", C.c_double),
                 ("dE_cx_eV", C.c_double), ("lnL", C.c_double), ("weight", C.c_double),
                 ("efield", C.POINTER(C.c_double)), ("n_species", C.c_int32),
-                ("sp", Species * MAXS)]
+                ("sp", Species * MAXS), ("self_ne", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -122,6 +122,7 @@ def make_params(p):
             S.k_out[q] = s["k_out"][q]
         S.sigma_cx1 = s["sigma_cx1"]
         S.n0 = s["n0"]
+    P.self_ne = 1 if p.get("self_ne") else 0
     return P, keep
 
 

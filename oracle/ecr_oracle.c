@@ -49,6 +49,7 @@ struct orc_sim {
   double M[ORC_MAXS];                /* species mass, kg */
   double qmh[ORC_MAXS][ORC_MAXQ];    /* (Q e / M) dt / 2 */
   double pion[ORC_MAXS][2][ORC_MAXQ];/* ionisation probability per step [outside, inside] */
+  double kdt[ORC_MAXS][2][ORC_MAXQ]; /* rate x dt [outside, inside] (self-consistent electrons) */
   double ccx[ORC_MAXS];              /* n0 sigma1 dt */
   int cxok[ORC_MAXS][ORC_MAXQ];
   double sig_w[ORC_MAXS], sig_n[ORC_MAXS], sig_i[ORC_MAXS], decx[ORC_MAXS];
@@ -65,6 +66,7 @@ struct orc_sim {
   uint8_t *q, *sp, *ev;
   uint32_t *cell;
   uint32_t *birth;  /* step the ion was made from an atom, or ORC_BIRTH_NONE */
+  uint32_t *chg;    /* self-consistent electrons: ion charge per cell at the start of the step */
   /* cell order */
   uint32_t *order, *cell_off;
   int64_t step;
@@ -354,6 +356,8 @@ int orc_create(const orc_params *p, orc_sim **out) {
       /* probability of one ionisation in dt: 1 - exp(-n_e k dt) */
       s->pion[k][1][Q] = (Q < sp->z_max) ? -expm1(-(p->ne_in * sp->k_in[Q]) * dt) : 0.0;
       s->pion[k][0][Q] = (Q < sp->z_max) ? -expm1(-(p->ne_out * sp->k_out[Q]) * dt) : 0.0;
+      s->kdt[k][1][Q] = (Q < sp->z_max) ? sp->k_in[Q] * dt : 0.0;
+      s->kdt[k][0][Q] = (Q < sp->z_max) ? sp->k_out[Q] * dt : 0.0;
       s->cxok[k][Q] = (Q >= 1 && Q <= sp->z_max && !((sp->cx_forbidden_mask >> Q) & 1u));
     }
     s->ccx[k] = (sp->n0 * sp->sigma_cx1) * dt;
@@ -399,9 +403,10 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->cell = calloc(nd, 4); s->order = calloc(nd, 4); s->id = calloc(nd, 4);
   s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4); s->birth = calloc(nd, 4);
   s->cell_off = calloc((size_t)s->ncell + 1, 4);
+  s->chg = calloc((size_t)s->ncell, 4);
   for (int f = 0; f < ORC_NFIELDS; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
-      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->dens[0] ||
+      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->chg || !s->dens[0] ||
       !s->dens[1] || !s->dens[2] || !s->dens[3]) {
     orc_destroy(s);
     return -2;
@@ -419,7 +424,7 @@ void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
   free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order); free(s->id);
-  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off);
+  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off); free(s->chg);
   for (int f = 0; f < ORC_NFIELDS; f++) free(s->dens[f]);
   free(s);
 }
@@ -737,7 +742,18 @@ static int mcc(orc_sim *s, int64_t i) {
   int sp = s->sp[i], Q = s->q[i];
   double x = s->x[i], y = s->y[i], z = s->z[i];
   int zone = (((x * x) * s->ia2 + (y * y) * s->ia2) + (z * z) * s->ic2) < 1.0;
-  double pi = (s->p.process_mask & ORC_P_IONIZE) ? s->pion[sp][zone][Q] : 0.0;
+  /* ionisation probability: the fixed background's 1 - exp(-n_e k dt), or
+   * with self-consistent electrons n_e k dt, n_e = weight x (ion charge of
+   * the cell at the start of the step) / cell volume */
+  double pi = 0.0;
+  if (s->p.process_mask & ORC_P_IONIZE) {
+    if (s->p.self_ne) {
+      double ne = s->nfac * (double)s->chg[orc_cell_of(s, x, y, z)];
+      pi = ne * s->kdt[sp][zone][Q];
+    } else {
+      pi = s->pion[sp][zone][Q];
+    }
+  }
   double pc = 0.0;
   if ((s->p.process_mask & ORC_P_CX) && s->cxok[sp][Q]) {
     double sp2 = (s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i];
@@ -838,6 +854,12 @@ int orc_step(orc_sim *s, int64_t n_steps) {
       s->need_sort = 0;
     }
     if (pm & ORC_P_COULOMB) coulomb(s);
+    if (s->p.self_ne) {
+      /* electrons neutralise the ions cell by cell (Sec. II) */
+      memset(s->chg, 0, (size_t)s->ncell * 4);
+      for (int64_t i = 0; i < s->N; i++)
+        if (s->q[i] >= 1) s->chg[orc_cell_of(s, s->x[i], s->y[i], s->z[i])] += s->q[i];
+    }
     for (int64_t i = 0; i < s->N; i++) {
       int ev = ORC_EV_NONE;
       if (pm & ORC_P_PUSH) {

@@ -71,6 +71,7 @@ typedef struct {
   const double *efield;       /* [3][(nx+1)(ny+1)(nz+1)] node field, V/m, or NULL */
   int32_t n_species;
   orc_species sp[ORC_MAXS];
+  int32_t self_ne;            /* 1: electron density = ion charge density of the cell (Sec. II) */
 } orc_params;
 
 typedef struct {

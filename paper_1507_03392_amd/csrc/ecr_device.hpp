@@ -66,6 +66,7 @@ struct StepArg {
 struct Tables {
   double qmh[kMaxS][kMaxQ];      // (Q e / M) dt / 2
   double pion[kMaxS][2][kMaxQ];  // ionisation probability per step [outside, inside]
+  double kdt[kMaxS][2][kMaxQ];   // rate x dt [outside, inside], for a cell's own electron density
   double lnA[kANodes];           // ln A at the Nanbu table nodes
 };
 

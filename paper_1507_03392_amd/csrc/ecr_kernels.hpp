@@ -37,10 +37,17 @@ constexpr int kCoulItems = kCoulMaxE / 2;
 template <typename R>
 void launch_init(const KParams &P, Soa<R> S, hipStream_t st);
 
-// push + wall/aperture + MCC; also deposits when dens != nullptr
+// push + wall/aperture + MCC; also deposits when dens != nullptr; with
+// chg_cur, ionisation uses the cell's ion charge (self-consistent n_e) and
+// the updated charges are summed per cell into chg_next (zeroed before)
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
-                 DevAccum *acc, double *dens, StepArg step, hipStream_t st);
+                 DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
+                 hipStream_t st);
+
+// ion charge per cell of the current state, added into chg (zeroed before)
+template <typename R>
+void launch_charge_grid(const KParams &P, Soa<R> S, uint32_t *chg, hipStream_t st);
 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st);

@@ -74,7 +74,8 @@ template <typename R, bool HAS_E>
 __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
                                            const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
                                            uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz,
-                                           uint32_t *__restrict__ birth, int64_t j) {
+                                           uint32_t *__restrict__ birth, int64_t j,
+                                           const uint32_t *__restrict__ chg) {
   uint8_t ev = EV_NONE;
   if (P.pmask & P_PUSH) {
     const R x0 = x, y0 = y, z0 = z;
@@ -113,7 +114,12 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     const uint4 W = draw(P, id, step, S_STEP, 0);
     const double u = u53(W.x, W.y);
     const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
-    const double pi = (P.pmask & P_IONIZE) ? T->pion[s][zone][Q] : 0.0;
+    // ionisation: the fixed background's tabulated probability, or with
+    // ECR_FLAG_SELF_NE n_e k dt, n_e = weight x (ion charge of the cell at
+    // the start of the step) / cell volume
+    double pi = 0.0;
+    if (P.pmask & P_IONIZE)
+      pi = chg ? (P.nfac * (double)chg[cell_of<R>(P, x, y, z)]) * T->kdt[s][zone][Q] : T->pion[s][zone][Q];
     double pc = 0.0;
     if ((P.pmask & P_CX) && ((P.cxok[s] >> Q) & 1u)) {
       const R sp2 = (vx * vx + vy * vy) + vz * vz;
@@ -386,11 +392,28 @@ __device__ __forceinline__ void box_init(int *box) {
 // ---------------------------------------------------------------------------
 // Push + wall/aperture + MCC (+ deposit): slot j = tile + tid + 256 p.
 // ---------------------------------------------------------------------------
+// the ion charge Q of a lane's particle added to its cell (chg_next): lanes
+// hold consecutive slots, mostly of one cell, so the first lane of each run
+// of equal cells adds the run's sum with one atomic
+__device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t cell, uint32_t q) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t prev = __shfl_up(cell, 1, 64);
+  const bool head = lane == 0 || prev != cell;
+  const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+  for (int off = 1; off < 64; off <<= 1) {
+    const int sn = __shfl_down(seg, off, 64);
+    const uint32_t o = __shfl_down(q, off, 64);
+    q += (lane + off < 64 && sn == seg) ? o : 0u;
+  }
+  if (head && cell != 0xffffffffu && q != 0u) atomicAdd(&chg[cell], q);
+}
+
 template <typename R, bool HAS_E, bool DEP>
 __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                  const double *__restrict__ ef, uint8_t *__restrict__ evlog,
                                                  DevAccum *__restrict__ acc, double *__restrict__ dens,
-                                                 StepArg sa) {
+                                                 StepArg sa, const uint32_t *__restrict__ chg_cur,
+                                                 uint32_t *__restrict__ chg_next) {
   __shared__ DepShared<R> sh;
   const uint32_t step = sa.get();
   __shared__ int box[6];
@@ -401,26 +424,32 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
   for (int p = 0; p < kP; ++p) {
     const int i = threadIdx.x + p * kBlock;
     const int64_t j = base + i;
+    uint32_t ccell = 0xffffffffu, cq = 0u;  // this lane's contribution to the next charge grid
     if (j >= P.n) {
       if (DEP) sh.st.q[kPad(i)] = 0xFF;
-      continue;
+    } else {
+      R x = S.x[j], y = S.y[j], z = S.z[j];
+      R vx = S.vx[j], vy = S.vy[j], vz = S.vz[j];
+      const uint8_t qs0 = S.qs[j];
+      const uint32_t id = S.pid[j];
+      int Q = q_of(qs0);
+      const int s = sp_of(qs0);
+      const uint8_t ev = advance<R, HAS_E>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur);
+      S.x[j] = x;
+      S.y[j] = y;
+      S.z[j] = z;
+      S.vx[j] = vx;
+      S.vy[j] = vy;
+      S.vz[j] = vz;
+      S.qs[j] = make_qs(Q, s);
+      if (evlog) evlog[j] = ev;
+      if (chg_next && Q >= 1) {
+        ccell = cell_of<R>(P, x, y, z);
+        cq = (uint32_t)Q;
+      }
+      if (DEP) stage_cic<R>(P, sh.st, i, x, y, z, Q, mn, mx);
     }
-    R x = S.x[j], y = S.y[j], z = S.z[j];
-    R vx = S.vx[j], vy = S.vy[j], vz = S.vz[j];
-    const uint8_t qs0 = S.qs[j];
-    const uint32_t id = S.pid[j];
-    int Q = q_of(qs0);
-    const int s = sp_of(qs0);
-    const uint8_t ev = advance<R, HAS_E>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j);
-    S.x[j] = x;
-    S.y[j] = y;
-    S.z[j] = z;
-    S.vx[j] = vx;
-    S.vy[j] = vy;
-    S.vz[j] = vz;
-    S.qs[j] = make_qs(Q, s);
-    if (evlog) evlog[j] = ev;
-    if (DEP) stage_cic<R>(P, sh.st, i, x, y, z, Q, mn, mx);
+    if (chg_next) add_charge(chg_next, ccell, cq);  // all lanes together: run sums use shuffles
   }
   if (DEP) deposit_staged<R>(P, dens, sh, box, mn, mx);
 }
@@ -599,17 +628,46 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
 
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog, DevAccum *acc,
-                 double *dens, StepArg step, hipStream_t st) {
+                 double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, hipStream_t st) {
   if (P.n <= 0) return;
   const dim3 g(grid_for(P.n, kTile)), b(kBlock);
   if (ef) {
-    if (dens) hipLaunchKernelGGL((k_push<R, true, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
-    else hipLaunchKernelGGL((k_push<R, true, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
+    if (dens)
+      hipLaunchKernelGGL((k_push<R, true, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
+    else
+      hipLaunchKernelGGL((k_push<R, true, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
   } else {
-    if (dens) hipLaunchKernelGGL((k_push<R, false, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
-    else hipLaunchKernelGGL((k_push<R, false, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step);
+    if (dens)
+      hipLaunchKernelGGL((k_push<R, false, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
+    else
+      hipLaunchKernelGGL((k_push<R, false, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                         chg_next);
   }
 }
+
+// ion charge per cell of the current state (the first step after init or set_state)
+template <typename R>
+__global__ void __launch_bounds__(256) k_charge_grid(KParams P, Soa<R> S, uint32_t *__restrict__ chg) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t cell = 0xffffffffu, q = 0u;
+  if (j < P.n) {
+    const int Q = q_of(S.qs[j]);
+    if (Q >= 1) {
+      cell = cell_of<R>(P, S.x[j], S.y[j], S.z[j]);
+      q = (uint32_t)Q;
+    }
+  }
+  add_charge(chg, cell, q);  // all lanes together
+}
+
+template <typename R>
+void launch_charge_grid(const KParams &P, Soa<R> S, uint32_t *chg, hipStream_t st) {
+  if (P.n <= 0) return;
+  hipLaunchKernelGGL(k_charge_grid<R>, dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, S, chg);
+}
+
+template void launch_charge_grid<double>(const KParams &, Soa<double>, uint32_t *, hipStream_t);
+template void launch_charge_grid<float>(const KParams &, Soa<float>, uint32_t *, hipStream_t);
 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {
@@ -628,9 +686,9 @@ template void launch_deposit_pressure<float>(const KParams &, Soa<float>, double
 template void launch_init<double>(const KParams &, Soa<double>, hipStream_t);
 template void launch_init<float>(const KParams &, Soa<float>, hipStream_t);
 template void launch_push<double>(const KParams &, const Tables *, Soa<double>, const double *, uint8_t *, DevAccum *,
-                                  double *, StepArg, hipStream_t);
+                                  double *, StepArg, const uint32_t *, uint32_t *, hipStream_t);
 template void launch_push<float>(const KParams &, const Tables *, Soa<float>, const double *, uint8_t *, DevAccum *,
-                                 double *, StepArg, hipStream_t);
+                                 double *, StepArg, const uint32_t *, uint32_t *, hipStream_t);
 template void launch_deposit<double>(const KParams &, Soa<double>, double *, hipStream_t);
 template void launch_deposit<float>(const KParams &, Soa<float>, double *, hipStream_t);
 

@@ -31,6 +31,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t soa[2][9];  // offsets of x y z vx vy vz qs pid birth in buffer A and B
   size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, evlog;
+  size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
   size_t total;
 };
 
@@ -86,6 +87,10 @@ Layout make_layout(const ecr_params *p) {
   if (p->efield_nodes) o = align_up(o + 8 * 3 * (size_t)nnodes(p));
   L.evlog = o;
   if (p->flags & ECR_FLAG_EVENTS) o = align_up(o + N);
+  for (int b = 0; b < 2; ++b) {
+    L.chg[b] = o;
+    if (p->flags & ECR_FLAG_SELF_NE) o = align_up(o + 4 * (size_t)ncells(p));
+  }
   L.total = o + kAlign;  // slack so the arena base may be realigned
   return L;
 }
@@ -208,7 +213,8 @@ struct ecr_run {
   std::vector<Pending> pending;
   // one sort period (sort_every steps, starting with its sort) captured as a
   // HIP graph, one per SoA buffer the period starts from
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [SoA buffer][charge grid]
+  int chg_par = 0;  // charge grid of the current step (ECR_FLAG_SELF_NE)
 };
 
 namespace {
@@ -326,6 +332,8 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
       if (q < sp.z_max) {
         T.pion[s][1][q] = -expm1(-(p->ne_in_m3 * sp.k_ion_in_m3s[q]) * dt);
         T.pion[s][0][q] = -expm1(-(p->ne_out_m3 * sp.k_ion_out_m3s[q]) * dt);
+        T.kdt[s][1][q] = sp.k_ion_in_m3s[q] * dt;
+        T.kdt[s][0][q] = sp.k_ion_out_m3s[q] * dt;
       }
       if (q >= 1 && q <= sp.z_max && !((sp.cx_forbidden_mask >> q) & 1u)) ok |= 1u << q;
     }
@@ -460,12 +468,17 @@ void do_step(ecr_run *r, StepArg stepw) {
   }
   const bool dep = (pm & ECR_P_DEPOSIT) != 0;
   const bool split = (r->p.flags & ECR_FLAG_SPLIT) != 0;
+  const bool self_ne = (r->p.flags & ECR_FLAG_SELF_NE) != 0;
+  uint32_t *chg_cur = self_ne ? at<uint32_t>(r, r->L.chg[r->chg_par]) : nullptr;
+  uint32_t *chg_next = self_ne ? at<uint32_t>(r, r->L.chg[1 - r->chg_par]) : nullptr;
+  if (self_ne) launch_fill_u32(chg_next, 0u, r->ncell, r->stream);
   {
     ProfScope ps(r, (dep && !split) ? ECR_K_FUSED : ECR_K_PUSH);
     launch_push<R>(r->kp, T, soa<R>(r, r->cur), r->p.efield_nodes ? at<double>(r, r->L.efield) : nullptr,
                    (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc,
-                   (dep && !split) ? at<double>(r, r->L.dens) : nullptr, stepw, r->stream);
+                   (dep && !split) ? at<double>(r, r->L.dens) : nullptr, stepw, chg_cur, chg_next, r->stream);
   }
+  if (self_ne) r->chg_par = 1 - r->chg_par;
   if (dep && split) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
@@ -477,6 +490,16 @@ void do_step(ecr_run *r, StepArg stepw) {
   if (dep) r->dens_steps++;
   r->step++;
   r->steps++;
+}
+
+// ion charge per cell of the state just set (ECR_FLAG_SELF_NE)
+void build_charge_grid(ecr_run *r) {
+  if (!(r->p.flags & ECR_FLAG_SELF_NE)) return;
+  r->chg_par = 0;
+  uint32_t *g = at<uint32_t>(r, r->L.chg[0]);
+  launch_fill_u32(g, 0u, r->ncell, r->stream);
+  if (r->fp32) launch_charge_grid<float>(r->kp, soa<float>(r, r->cur), g, r->stream);
+  else launch_charge_grid<double>(r->kp, soa<double>(r, r->cur), g, r->stream);
 }
 
 void zero_accumulators(ecr_run *r) {
@@ -632,6 +655,7 @@ ecr_status ecr_init_ions(ecr_run *r) {
   else launch_init<double>(r->kp, soa<double>(r, 0), r->stream);
   if (r->p.flags & ECR_FLAG_EVENTS) launch_fill_u8(at<uint8_t>(r, r->L.evlog), 0, r->kp.n, r->stream);
   zero_accumulators(r);
+  build_charge_grid(r);
   r->step = 0;
   r->need_sort = true;
   r->initialized = true;
@@ -657,7 +681,7 @@ namespace {
 hipError_t capture_period(ecr_run *r, hipGraphExec_t *out) {
   const int64_t K = r->p.sort_every;
   const int64_t step0 = r->step, steps0 = r->steps, dens0 = r->dens_steps;
-  const int cur0 = r->cur;
+  const int cur0 = r->cur, par0 = r->chg_par;
   const bool need0 = r->need_sort;
   const uint32_t *base = at<uint32_t>(r, r->L.stepc);
   hipError_t e = hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal);
@@ -675,6 +699,7 @@ hipError_t capture_period(ecr_run *r, hipGraphExec_t *out) {
   r->steps = steps0;
   r->dens_steps = dens0;
   r->cur = cur0;
+  r->chg_par = par0;
   r->need_sort = need0;
   return e;
 }
@@ -696,7 +721,7 @@ ecr_status ecr_step_graph(ecr_run *r, int64_t n_steps) {
       --n_steps;
       continue;
     }
-    hipGraphExec_t &ge = r->gexec[r->cur];
+    hipGraphExec_t &ge = r->gexec[r->cur][r->chg_par];
     if (!ge) {
       const hipError_t e = capture_period(r, &ge);
       if (e != hipSuccess) {
@@ -711,6 +736,7 @@ ecr_status ecr_step_graph(ecr_run *r, int64_t n_steps) {
     r->steps += K;
     if (dep) r->dens_steps += K;
     r->cur = 1 - r->cur;  // the period's sort moved the state to the other buffer
+    if ((r->p.flags & ECR_FLAG_SELF_NE) && (K & 1)) r->chg_par = 1 - r->chg_par;
     r->need_sort = false;
     n_steps -= K;
   }
@@ -792,6 +818,7 @@ ecr_status ecr_set_state(ecr_run *r, const ecr_state_view *v) {
   } else {
     r->need_sort = true;
   }
+  build_charge_grid(r);
   r->initialized = true;
   return check_hip(r, hipGetLastError(), "set_state");
 }
@@ -844,8 +871,9 @@ ecr_status ecr_destroy(ecr_run *r) {
   if (!r) return ECR_OK;
   harvest(r);
   for (auto e : r->free_events) (void)hipEventDestroy(e);
-  for (auto &g : r->gexec)
-    if (g) (void)hipGraphExecDestroy(g);
+  for (auto &row : r->gexec)
+    for (auto &g : row)
+      if (g) (void)hipGraphExecDestroy(g);
   delete r;
   return ECR_OK;
 }

@@ -75,3 +75,18 @@ def test_graph_after_set_state_and_two_runs_on_one_stream():
         _same(c, d, "run 2")
     # the two seeds give different runs
     assert not np.array_equal(a.get_state()["vx"], c.get_state()["vx"])
+
+
+def test_graph_self_consistent_electrons_odd_period():
+    # the per-cell charge grid alternates between two buffers every step: an
+    # odd sort period starts replays on either buffer
+    import torch
+    params = W.with_(W.config("c1")[0], self_ne=True, sort_every=15)
+    stream = torch.cuda.Stream()
+    a, b = _runs(params, stream)
+    a.init_ions()
+    b.init_ions()
+    for n in (4, 26, 15, 15, 15, 30, 7):
+        a.step(n)
+        b.step_graph(n)
+        _same(a, b, f"after {a.get_state()['step']} steps")

@@ -116,6 +116,10 @@ CASES = {
     "coulomb": dict(mask=W.P_COULOMB, v_ev=0.5),
     "all": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20),
     "all_walls": dict(mask=W.P_ALL, v_ev=200.0, dt=5e-9, rf=0.9995),
+    # electrons = ion charge density per cell (Sec. II); a heavy weight so
+    # that ionisation fires in one step
+    "ionize_self_ne": dict(mask=W.P_IONIZE, v_ev=0.5, self_ne=True, weight=4e12),
+    "all_self_ne": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20, self_ne=True, weight=4e12),
 }
 
 
@@ -124,7 +128,8 @@ CASES = {
 def test_single_step_parity(case, seed):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
-    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=15, weight=4e9)
+    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=15, weight=c.get("weight", 4e9),
+                  self_ne=c.get("self_ne", False))
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     st = W.random_state(params, seed=100 + seed, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95),
@@ -139,7 +144,7 @@ def test_single_step_parity(case, seed):
     ev = o.events()
     if case in ("push_walls", "all_walls"):
         assert (ev == W.EV_WALL).sum() > 20
-    if case in ("ionize", "all"):
+    if case in ("ionize", "all", "ionize_self_ne", "all_self_ne"):
         assert (ev == W.EV_IONIZE).sum() > 5
     if case == "cx":
         assert (ev == W.EV_CX).sum() > 10
@@ -208,6 +213,26 @@ def test_multi_step_c1_from_init():
         dg, _ = g.density(f)
         do, _ = o.density(f)
         assert np.abs(dg - do).max() <= 1e-12 * np.abs(do).max()
+
+
+def test_multi_step_c1_self_consistent_electrons():
+    # C1 with the electron density taken from the ions' charge cell by cell,
+    # 150 steps across three sorts: every step's decisions bit for bit
+    params = W.with_(W.config("c1")[0], self_ne=True)
+    g = gpu_run(params, events=True)
+    g.init_ions()
+    o = oracle(params)
+    o.init_ions()
+    ionized = 0
+    for chunk in (1, 49, 50, 50):
+        g.step(chunk)
+        o.step(chunk)
+        a, b = g.get_state(), o.get_state()
+        assert np.array_equal(g.events(), o.events())
+        assert_state_close(a, b, params, what=f"c1 self-ne step {a['step']}")
+    tg = g.tallies()
+    assert_tallies_equal(tg, o.tallies(), "c1 self-ne")
+    assert tg["ionized"].sum() > 100
 
 
 def test_deposit_fused_and_split_agree():

@@ -99,7 +99,7 @@ def base_params(n, nx, ny, nz, seed=0, precision=PREC_FP64):
         B0=0.5, mirror_k=3.0, BH=1.0,
         zone_a=0.015, zone_c=0.05, ne_in=1.0e18, ne_out=0.0, Te_in_eV=1000.0, Te_out_eV=5.0,
         Ti0_eV=0.5, T_wall_eV=0.025, T_n_eV=0.025, dE_cx_eV=10.0, lnL=10.0, weight=0.0,
-        efield=None, species=[argon()])
+        efield=None, species=[argon()], self_ne=False)
 
 
 def config(name):
