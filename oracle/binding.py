@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("Ti0_eV", C.c_double), ("T_wall_eV", C.c_double), ("T_n_eV", C.c_double),
                 ("dE_cx_eV", C.c_double), ("lnL", C.c_double), ("weight", C.c_double),
                 ("efield", C.POINTER(C.c_double)), ("n_species", C.c_int32),
-                ("sp", Species * MAXS), ("self_ne", C.c_int32)]
+                ("sp", Species * MAXS), ("self_ne", C.c_int32),
+                ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double)]
 
 
 class Tallies(C.Structure):
@@ -123,6 +124,9 @@ def make_params(p):
         S.sigma_cx1 = s["sigma_cx1"]
         S.n0 = s["n0"]
     P.self_ne = 1 if p.get("self_ne") else 0
+    P.lnL_ei = float(p.get("lnL_ei", 17.0))
+    P.Te_in_eV = float(p.get("Te_in_eV", 0.0))
+    P.Te_out_eV = float(p.get("Te_out_eV", 0.0))
     return P, keep
 
 

@@ -32,7 +32,7 @@
 #define EPS_WALL 1e-9 /* re-emission offset from a wall, m */
 
 /* Philox stream ids (third counter word) */
-enum { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4 };
+enum { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5 };
 
 /* Nanbu A(s) table: nodes s = 2^e (1 + j/K) for e in [E_LO, E_HI], j in [0, K) */
 #define A_E_LO (-20)
@@ -55,6 +55,7 @@ struct orc_sim {
   double sig_w[ORC_MAXS], sig_n[ORC_MAXS], sig_i[ORC_MAXS], decx[ORC_MAXS];
   int64_t sp_end[ORC_MAXS];          /* particle ids [sp_end[s-1], sp_end[s]) are species s */
   double ia2, ic2, idx, idy, idz, hL, R0sq, rap2, nfac, Cs, w;
+  double hx, hy, hz;                 /* cell sizes */
   double c1, c2, c3, c4;
   int nx1, ny1, nz1;
   int64_t ncell, nnode;
@@ -341,6 +342,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
   if (!p || !out) return -1;
   if (p->n < 0 || p->n > 0x7fffffff || p->n_species < 1 || p->n_species > ORC_MAXS) return -1;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->sort_every < 1 || !(p->dt > 0.0)) return -1;
+  if ((p->process_mask & ORC_P_HEAT) && !(p->Te_in_eV > 0.0 && p->Te_out_eV > 0.0 && p->lnL_ei >= 0.0)) return -1;
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   if (!s) return -2;
   s->p = *p;
@@ -387,6 +389,9 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->w = (p->weight > 0.0) ? p->weight : (p->n > 0 ? p->ne_in * vzone / (double)p->n : 0.0);
   double vcell = ((2.0 * p->R0 / p->nx) * (2.0 * p->R0 / p->ny)) * (p->L / p->nz);
   s->nfac = s->w / vcell;
+  s->hx = 2.0 * p->R0 / p->nx;
+  s->hy = 2.0 * p->R0 / p->ny;
+  s->hz = p->L / p->nz;
   s->Cs = p->lnL * (E_CHARGE * E_CHARGE) * (E_CHARGE * E_CHARGE) / (4.0 * PI * EPS0 * EPS0);
   s->nx1 = p->nx + 1;
   s->ny1 = p->ny + 1;
@@ -726,6 +731,82 @@ static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Electron-ion heating and diffusion (Sec. II): each step an ion's velocity */
+/* gets the kick D (R + delta) |R| / |R + delta|.                            */
+/*   D^2 = 3.715e-6 n_e lambda_ei Q^2 dt / (M^2 sqrt(T_e)), SI (n_e in m^-3, */
+/*   dt in s, D in m/s), M in amu, T_e in eV.  The printed formula has Q     */
+/*   inside the root; the text states a heating rate quadratic in Q, and     */
+/*   with Q^2, SI units and R uniform in the cube [-1/2, 1/2]^3 (so that     */
+/*   E|R|^2 = 1/4) the mean energy gain (1/8) M D^2 per step is the NRL      */
+/*   electron-ion heating rate for T_i << T_e to within 2%: that reading.    */
+/*   R: three uniforms of one draw of the heating stream, (w + 1/2) 2^-32 -  */
+/*   1/2 each.                                                               */
+/*   delta (x and y only): the 9-point stencil of n_e around the ion's cell  */
+/*   in its z plane, times -R_L / n_e(cell), R_L = 2.38e-6 sqrt(T_e) /       */
+/*   (|B| dX): the electron Larmor radius in units of the mesh step dX = hx, */
+/*   |B| at the cell centre.  Cells beyond the mesh count as n_e = 0.        */
+/* n_e and T_e are the ionisation's: with self-consistent electrons the     */
+/* cell's ion charge density at the start of the step (no kick in a cell    */
+/* without charge), else the zone's fixed background, which is uniform, so */
+/* delta = 0.  Applied to ions that stay in the chamber, with their charge  */
+/* before ionisation and charge exchange.                                    */
+/* ------------------------------------------------------------------------ */
+static double cell_ne(const orc_sim *s, int ix, int iy, int iz) {
+  if (ix < 0 || ix >= s->p.nx || iy < 0 || iy >= s->p.ny) return 0.0;
+  return s->nfac * (double)s->chg[(int64_t)ix + (int64_t)s->p.nx * ((int64_t)iy + (int64_t)s->p.ny * iz)];
+}
+
+static void heat_kick(orc_sim *s, int64_t i) {
+  int sp = s->sp[i], Q = s->q[i];
+  double x = s->x[i], y = s->y[i], z = s->z[i];
+  int zone = (((x * x) * s->ia2 + (y * y) * s->ia2) + (z * z) * s->ic2) < 1.0;
+  double Te = zone ? s->p.Te_in_eV : s->p.Te_out_eV;
+  double ne, dlx = 0.0, dly = 0.0;
+  if (s->p.self_ne) {
+    uint32_t c = orc_cell_of(s, x, y, z);
+    int ix = (int)(c % (uint32_t)s->p.nx);
+    int iy = (int)((c / (uint32_t)s->p.nx) % (uint32_t)s->p.ny);
+    int iz = (int)(c / ((uint32_t)s->p.nx * (uint32_t)s->p.ny));
+    ne = cell_ne(s, ix, iy, iz);
+    if (!(ne > 0.0)) return;
+    double B[3];
+    orc_field(s, -s->p.R0 + (ix + 0.5) * s->hx, -s->p.R0 + (iy + 0.5) * s->hy, -s->hL + (iz + 0.5) * s->hz, B);
+    double bmag = sqrt((B[0] * B[0] + B[1] * B[1]) + B[2] * B[2]);
+    if (bmag > 0.0) {
+      double RL = (2.38e-6 * sqrt(Te)) / (bmag * s->hx);
+      double gy = (-cell_ne(s, ix, iy + 1, iz) + cell_ne(s, ix, iy - 1, iz)) +
+                  0.5 * (((-cell_ne(s, ix - 1, iy + 1, iz) - cell_ne(s, ix + 1, iy + 1, iz)) +
+                          cell_ne(s, ix + 1, iy - 1, iz)) + cell_ne(s, ix - 1, iy - 1, iz));
+      double gx = (-cell_ne(s, ix - 1, iy, iz) + cell_ne(s, ix + 1, iy, iz)) +
+                  0.5 * (((-cell_ne(s, ix - 1, iy + 1, iz) + cell_ne(s, ix + 1, iy + 1, iz)) +
+                          cell_ne(s, ix + 1, iy - 1, iz)) - cell_ne(s, ix - 1, iy - 1, iz));
+      dlx = -(RL / ne) * gy;
+      dly = -(RL / ne) * gx;
+    }
+  } else {
+    ne = zone ? s->p.ne_in : s->p.ne_out;
+    if (!(ne > 0.0)) return;
+  }
+  double A = s->p.sp[sp].mass_amu;
+  double h = (((3.715e-6 * s->p.lnL_ei) * (double)(Q * Q)) * s->p.dt) / ((A * A) * sqrt(Te));
+  double D = sqrt(ne * h);
+  uint32_t W[4];
+  draw(s, s->id[i], (uint32_t)s->step, S_HEAT, 0, W);
+  const double two_m32 = 2.3283064365386962890625e-10; /* 2^-32 */
+  double rx = ((double)W[0] + 0.5) * two_m32 - 0.5;
+  double ry = ((double)W[1] + 0.5) * two_m32 - 0.5;
+  double rz = ((double)W[2] + 0.5) * two_m32 - 0.5;
+  double sx = rx + dlx, sy = ry + dly, sz = rz;
+  double nr = sqrt((rx * rx + ry * ry) + rz * rz);
+  double ns = sqrt((sx * sx + sy * sy) + sz * sz);
+  if (!(ns > 0.0)) return;
+  double f = (D * nr) / ns;
+  s->vx[i] += f * sx;
+  s->vy[i] += f * sy;
+  s->vz[i] += f * sz;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Monte-Carlo collisions with electrons and neutrals (Sec. II).             */
 /* One uniform u decides: u < P_ion -> Q+1; u < P_ion + P_cx -> charge       */
 /* exchange.  P_ion = 1 - exp(-n_e k_Q dt) with the zone's n_e and rate;     */
@@ -844,7 +925,8 @@ static void deposit(orc_sim *s) {
 
 /* ------------------------------------------------------------------------ */
 /* One step: sort (every sort_every steps) -> Coulomb -> per particle push,  */
-/* boundary, and (without a boundary event) MCC -> deposit.                  */
+/* boundary, and (without a boundary event) heating kick and MCC ->         */
+/* deposit.                                                                  */
 /* ------------------------------------------------------------------------ */
 int orc_step(orc_sim *s, int64_t n_steps) {
   uint32_t pm = s->p.process_mask;
@@ -870,6 +952,7 @@ int orc_step(orc_sim *s, int64_t n_steps) {
               &s->vx[i], &s->vy[i], &s->vz[i]);
         ev = boundary(s, i, x0, y0, z0);
       }
+      if (ev == ORC_EV_NONE && (pm & ORC_P_HEAT) && s->q[i] >= 1) heat_kick(s, i);
       if (ev == ORC_EV_NONE && (pm & (ORC_P_IONIZE | ORC_P_CX))) ev = mcc(s, i);
       s->ev[i] = (uint8_t)ev;
       if (!(isfinite(s->x[i]) && isfinite(s->y[i]) && isfinite(s->z[i]) && isfinite(s->vx[i]) &&

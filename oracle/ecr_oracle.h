@@ -30,6 +30,7 @@ extern "C" {
 #define ORC_P_CX 4u        /* charge exchange with background neutrals */
 #define ORC_P_COULOMB 8u   /* ion-ion Coulomb scattering (TA pairing, Nanbu angle) */
 #define ORC_P_DEPOSIT 16u  /* cloud-in-cell density deposit */
+#define ORC_P_HEAT 32u     /* electron-ion heating kick, biased along the electron diamagnetic drift */
 
 /* deposit fields */
 #define ORC_F_ION_N 0  /* sum of CIC weights of ions (Q >= 1) */
@@ -72,6 +73,8 @@ typedef struct {
   int32_t n_species;
   orc_species sp[ORC_MAXS];
   int32_t self_ne;            /* 1: electron density = ion charge density of the cell (Sec. II) */
+  double lnL_ei;              /* electron-ion Coulomb logarithm (the paper: 17) */
+  double Te_in_eV, Te_out_eV; /* electron temperature inside (warm) and outside (cold) the zone */
 } orc_params;
 
 typedef struct {

@@ -27,6 +27,7 @@ P_CX = 4
 P_COULOMB = 8
 P_DEPOSIT = 16
 P_ALL = P_PUSH | P_IONIZE | P_CX | P_COULOMB | P_DEPOSIT
+P_HEAT = 32  # electron-ion heating kick (not in P_ALL: the fixed-background step of the benchmark)
 
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P = 0, 1, 2, 3
 
@@ -98,7 +99,7 @@ def base_params(n, nx, ny, nz, seed=0, precision=PREC_FP64):
         R0=R0, L=0.30, r_ap=0.01, inlet_x=R0 / 2, inlet_y=0.0,
         B0=0.5, mirror_k=3.0, BH=1.0,
         zone_a=0.015, zone_c=0.05, ne_in=1.0e18, ne_out=0.0, Te_in_eV=1000.0, Te_out_eV=5.0,
-        Ti0_eV=0.5, T_wall_eV=0.025, T_n_eV=0.025, dE_cx_eV=10.0, lnL=10.0, weight=0.0,
+        Ti0_eV=0.5, T_wall_eV=0.025, T_n_eV=0.025, dE_cx_eV=10.0, lnL=10.0, lnL_ei=17.0, weight=0.0,
         efield=None, species=[argon()], self_ne=False)
 
 
