@@ -40,10 +40,11 @@ def describe(name, p):
         "fixed electron background"
     return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, {ne}, "
             f"mesh {p['nx']}x{p['ny']}x{p['nz']}, dt {p['dt']:g} s, sort every {p['sort_every']}, "
-            f"all processes on")
+            f"all processes on" + (", with the electron-ion heating kick" if p["process_mask"] & 32 else ""))
 
 # algorithmic HBM bytes per particle per launch (FP64 structure of arrays:
-# x y z vx vy vz 8 B each, qs 1 B, pid 4 B, collision cell 4 B)
+# x y z vx vy vz 8 B each, qs 1 B, pid 4 B, birth step 4 B (moved by the sort
+# only), collision cell 4 B)
 ALG_BYTES_FP64 = {
     # read x, v, qs, pid; write x, v, qs
     "push": 48 + 1 + 4 + 48 + 1,
@@ -54,7 +55,7 @@ ALG_BYTES_FP64 = {
     # read x, qs
     "deposit": 24 + 1,
     # count pass (read x; write key, rank) + scatter (read record, key, rank; write record, cell)
-    "sort": (24 + 8) + (53 + 8) + (53 + 4),
+    "sort": (24 + 8) + (57 + 8) + (57 + 4),
     # push + deposit in one kernel: the deposit reads nothing more from HBM
     "push_deposit": 48 + 1 + 4 + 48 + 1,
 }
@@ -63,7 +64,7 @@ ALG_BYTES_FP32 = {
     "coul_order": 1 + 4 + 4 + 6,
     "coul_pairs": 6 + 12 + 1 + 12,
     "deposit": 12 + 1,
-    "sort": (12 + 8) + (29 + 8) + (29 + 4),
+    "sort": (12 + 8) + (33 + 8) + (33 + 4),
     "push_deposit": 24 + 1 + 4 + 24 + 1,
 }
 
@@ -193,6 +194,8 @@ def main():
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--self-ne", action="store_true",
                     help="electron density = ion charge density per cell (self-consistent electrons)")
+    ap.add_argument("--heat", action="store_true",
+                    help="add the electron-ion heating kick (diamagnetic bias with --self-ne)")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
     ap.add_argument("--slots", type=int, default=16, help="c5: run slots (one HIP stream each)")
     ap.add_argument("--split", action="store_true",
@@ -202,7 +205,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the ion step is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+              "sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "c5":
@@ -226,6 +229,8 @@ def main():
     params, _ = W.config(args.workload)
     if args.self_ne:
         params["self_ne"] = True
+    if args.heat:
+        params["process_mask"] |= ecr.P_HEAT
     n = params["n"]
     fp32 = params.get("precision", 0) == ecr.FP32_MIXED
     log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")

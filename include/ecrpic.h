@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ECR_ABI_VERSION 2u
+#define ECR_ABI_VERSION 3u
 #define ECR_MAX_SPECIES 4
 #define ECR_MAX_Q 32          /* charge-state slots per species: Q = 0..31 */
 #define ECR_FPT_BINS 32       /* log2 bins of first-passage times */
@@ -64,7 +64,16 @@ enum {
   ECR_P_CX = 4,       /* charge exchange with the background neutral gas */
   ECR_P_COULOMB = 8,  /* ion-ion Coulomb scattering: Takizuka-Abe pairing, Nanbu angle */
   ECR_P_DEPOSIT = 16, /* cloud-in-cell density deposit */
-  ECR_P_ALL = 31
+  ECR_P_ALL = 31,     /* the five processes above: the fixed-background step */
+  ECR_P_HEAT = 32     /* electron-ion heating and diffusion kick (Sec. II): each ion that stays in the
+                         chamber gets dV = D (R + delta) |R| / |R + delta| before ionisation and charge
+                         exchange, D^2 = 3.715e-6 n_e lnL_ei Q^2 dt / (M_amu^2 sqrt(T_e)) (SI; the printed
+                         formula's Q read as Q^2, the heating rate's stated charge law), R uniform in
+                         [-1/2, 1/2]^3 (one draw of Philox stream 5); with ECR_FLAG_SELF_NE, n_e is the
+                         cell's and delta the electron diamagnetic bias: the 9-point stencil of the cell
+                         electron density in the ion's z plane (cells beyond the mesh: 0) times
+                         -R_L / n_e(cell), R_L = 2.38e-6 sqrt(T_e) / (|B(cell centre)| hx); with the fixed
+                         background, n_e and T_e are the zone's and delta = 0 */
 };
 
 /* density fields (bit f of deposit_mask enables field f) */
@@ -125,6 +134,8 @@ typedef struct {
   double T_n_eV;                      /* neutral gas temperature (charge-exchange partners) */
   double dE_cx_eV;                    /* energy release of multiply-charged charge exchange */
   double lnL_ii;                      /* ion-ion Coulomb logarithm */
+  double lnL_ei;                      /* electron-ion Coulomb logarithm (ECR_P_HEAT; the paper: 17) */
+  double Te_in_eV, Te_out_eV;         /* electron temperature inside / outside the zone (ECR_P_HEAT; > 0) */
   double weight;                      /* real ions per macro-particle; 0: n_e,in V_zone / N */
   const double *efield_nodes;         /* host, [3][(nx+1)(ny+1)(nz+1)] V/m node field, or NULL (E = 0) */
   ecr_species species[ECR_MAX_SPECIES];

@@ -15,12 +15,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libecrpic.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAXS, MAXQ = 4, 32
 FPT_BINS = 32
 BIRTH_NONE = 0xFFFFFFFF
 FP64, FP32_MIXED = 0, 1
-P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL = 1, 2, 4, 8, 16, 31
+P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL, P_HEAT = 1, 2, 4, 8, 16, 31, 32
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P, N_FIELDS = 0, 1, 2, 3, 4
 FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE = 1, 2, 4
 K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, N_KERNELS = 0, 1, 2, 3, 4, 5, 6
@@ -57,6 +57,7 @@ class Params(C.Structure):
                 ("zone_a_m", C.c_double), ("zone_c_m", C.c_double), ("ne_in_m3", C.c_double),
                 ("ne_out_m3", C.c_double), ("Ti0_eV", C.c_double), ("T_wall_eV", C.c_double),
                 ("T_n_eV", C.c_double), ("dE_cx_eV", C.c_double), ("lnL_ii", C.c_double),
+                ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double),
                 ("weight", C.c_double), ("efield_nodes", C.POINTER(C.c_double)),
                 ("species", Species * MAXS)]
 
@@ -142,6 +143,9 @@ def make_params(p, events=False, split=False):
                      ("ne_out_m3", "ne_out"), ("Ti0_eV", "Ti0_eV"), ("T_wall_eV", "T_wall_eV"),
                      ("T_n_eV", "T_n_eV"), ("dE_cx_eV", "dE_cx_eV"), ("lnL_ii", "lnL"), ("weight", "weight")):
         setattr(P, dst, float(p[src]))
+    P.lnL_ei = float(p.get("lnL_ei", 17.0))
+    P.Te_in_eV = float(p.get("Te_in_eV", 0.0))
+    P.Te_out_eV = float(p.get("Te_out_eV", 0.0))
     keep = None
     if p.get("efield") is not None:
         keep = np.ascontiguousarray(p["efield"], dtype=np.float64)

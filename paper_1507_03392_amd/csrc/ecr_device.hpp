@@ -23,9 +23,9 @@ constexpr double kWallEps = 1e-9;            // re-emission offset from a wall, 
 
 // Philox stream ids (counter word 2); word 0 = particle id, word 1 = step,
 // word 3 = call index within the stream.
-enum : uint32_t { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4 };
+enum : uint32_t { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5 };
 enum : uint8_t { EV_NONE = 0, EV_IONIZE = 1, EV_CX = 2, EV_WALL = 3, EV_EXTRACT = 4 };
-enum : uint32_t { P_PUSH = 1, P_IONIZE = 2, P_CX = 4, P_COULOMB = 8, P_DEPOSIT = 16 };
+enum : uint32_t { P_PUSH = 1, P_IONIZE = 2, P_CX = 4, P_COULOMB = 8, P_DEPOSIT = 16, P_HEAT = 32 };
 
 // Nanbu A(s) table: ln A at s = 2^e (1 + j/K), e in [kAeLo, kAeHi], j in [0, K)
 constexpr int kAeLo = -20;
@@ -44,6 +44,10 @@ struct KParams {
   double idx, idy, idz, ia2, ic2, zone_a, zone_c;
   double B0, c1, c2, c3, c4;
   double dt, nfac, Cs;
+  double hx, hy, hz;  // cell sizes
+  // heating kick, [outside, inside] the zone: fixed-background n_e, and
+  // 2.38e-6 sqrt(T_e) (the electron Larmor radius times |B|)
+  double ne_zone[2], rl_zone[2];
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
   // per species pair (a, b): reduced mass mu = ma mb / (ma + mb), mu / ma, mu / mb
   double mu[kMaxS][kMaxS], mra[kMaxS][kMaxS], mrb[kMaxS][kMaxS];
@@ -67,6 +71,7 @@ struct Tables {
   double qmh[kMaxS][kMaxQ];      // (Q e / M) dt / 2
   double pion[kMaxS][2][kMaxQ];  // ionisation probability per step [outside, inside]
   double kdt[kMaxS][2][kMaxQ];   // rate x dt [outside, inside], for a cell's own electron density
+  double dheat[kMaxS][2][kMaxQ]; // heating kick D^2 / n_e [outside, inside]
   double lnA[kANodes];           // ln A at the Nanbu table nodes
 };
 

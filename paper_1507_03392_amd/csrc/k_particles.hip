@@ -64,7 +64,72 @@ __global__ void __launch_bounds__(256) k_init(KParams P, Soa<R> S) {
 }
 
 // ---------------------------------------------------------------------------
-// One particle: push -> wall/aperture -> ionisation / charge exchange.
+// Electron-ion heating and diffusion (Sec. II): dV = D (R + delta) |R| /
+// |R + delta| with D^2 = n_e x dheat[s][zone][Q] and R uniform in the cube
+// [-1/2, 1/2]^3 (three words of one draw of the heating stream).  With the
+// cell charge grid (self-consistent electrons) n_e is the ion's cell's and
+// delta the electron diamagnetic bias: the 9-point stencil of the cell
+// density in the ion's z plane (cells beyond the mesh count as empty) times
+// -R_L / n_e(cell), R_L = 2.38e-6 sqrt(T_e) / (|B(cell centre)| hx); a cell
+// without charge gives no kick.  With the fixed background, n_e is the
+// zone's and, the background being uniform, delta = 0.  The kick is
+// evaluated in binary64 whatever R; the neighbours' loads hit the cache
+// lines the lanes of a cell share (slots are in cell order).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__restrict__ T, uint32_t id, uint32_t step,
+                                          int s, int Q, R x, R y, R z, R &vx, R &vy, R &vz,
+                                          const uint32_t *__restrict__ chg) {
+  const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
+  double ne, dlx = 0.0, dly = 0.0;
+  if (chg) {
+    const int ix = clampi((int)floor((x + (R)P.R0) * (R)P.idx), 0, P.nx - 1);
+    const int iy = clampi((int)floor((y + (R)P.R0) * (R)P.idy), 0, P.ny - 1);
+    const int iz = clampi((int)floor((z + (R)P.hL) * (R)P.idz), 0, P.nz - 1);
+    const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny * (uint32_t)iz;
+    auto nat = [&](int jx, int jy) -> double {
+      if (jx < 0 || jx >= P.nx || jy < 0 || jy >= P.ny) return 0.0;
+      return P.nfac * (double)chg[plane + (uint32_t)jx + (uint32_t)P.nx * (uint32_t)jy];
+    };
+    ne = nat(ix, iy);
+    if (!(ne > 0.0)) return;
+    double bx, by, bz;
+    field_B<double>(P, -P.R0 + ((double)ix + 0.5) * P.hx, -P.R0 + ((double)iy + 0.5) * P.hy,
+                    -P.hL + ((double)iz + 0.5) * P.hz, bx, by, bz);
+    const double bmag = sqrt((bx * bx + by * by) + bz * bz);
+    if (bmag > 0.0) {
+      const double rl = P.rl_zone[zone] / (bmag * P.hx);
+      const double nmm = nat(ix - 1, iy - 1), nzm = nat(ix, iy - 1), npm = nat(ix + 1, iy - 1);
+      const double nmz = nat(ix - 1, iy), npz = nat(ix + 1, iy);
+      const double nmp = nat(ix - 1, iy + 1), nzp = nat(ix, iy + 1), npp = nat(ix + 1, iy + 1);
+      const double gy = (-nzp + nzm) + 0.5 * (((-nmp - npp) + npm) + nmm);
+      const double gx = (-nmz + npz) + 0.5 * (((-nmp + npp) + npm) - nmm);
+      dlx = -(rl / ne) * gy;
+      dly = -(rl / ne) * gx;
+    }
+  } else {
+    ne = P.ne_zone[zone];
+    if (!(ne > 0.0)) return;
+  }
+  const double D = sqrt(ne * T->dheat[s][zone][Q]);
+  const uint4 W = draw(P, id, step, S_HEAT, 0);
+  constexpr double k2m32 = 2.3283064365386962890625e-10;  // 2^-32
+  const double rx = ((double)W.x + 0.5) * k2m32 - 0.5;
+  const double ry = ((double)W.y + 0.5) * k2m32 - 0.5;
+  const double rz = ((double)W.z + 0.5) * k2m32 - 0.5;
+  const double sx = rx + dlx, sy = ry + dly, sz = rz;
+  const double nr = sqrt((rx * rx + ry * ry) + rz * rz);
+  const double ns = sqrt((sx * sx + sy * sy) + sz * sz);
+  if (!(ns > 0.0)) return;
+  const double f = (D * nr) / ns;
+  vx = (R)((double)vx + f * sx);
+  vy = (R)((double)vy + f * sy);
+  vz = (R)((double)vz + f * sz);
+}
+
+// ---------------------------------------------------------------------------
+// One particle: push -> wall/aperture -> heating kick -> ionisation / charge
+// exchange.
 // Tallies are rare events (~1e-4 per particle-step) and go straight to
 // 64-bit global atomics; so do the loss diagnostics (first-passage times,
 // crossing radius, lost kinetic energy), and the particle's birth step
@@ -110,6 +175,7 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
       Q = 0;
     }
   }
+  if (ev == EV_NONE && (P.pmask & P_HEAT) && Q >= 1) heat_kick<R>(P, T, id, step, s, Q, x, y, z, vx, vy, vz, chg);
   if (ev == EV_NONE && (P.pmask & (P_IONIZE | P_CX))) {
     const uint4 W = draw(P, id, step, S_STEP, 0);
     const double u = u53(W.x, W.y);

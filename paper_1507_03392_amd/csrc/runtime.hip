@@ -270,6 +270,11 @@ std::string validate(const ecr_params *p) {
   if (p->weight < 0.0 || p->lnL_ii < 0.0 || p->Ti0_eV < 0.0 || p->T_wall_eV < 0.0 || p->T_n_eV < 0.0)
     return "negative weight, Coulomb logarithm or temperature";
   if (p->ne_in_m3 < 0.0 || p->ne_out_m3 < 0.0) return "negative electron density";
+  if (p->process_mask >= 64u) return "process_mask has unknown bits";
+  if ((p->process_mask & ECR_P_HEAT) &&
+      !(p->Te_in_eV > 0.0 && p->Te_out_eV > 0.0 && isfinite(p->Te_in_eV) && isfinite(p->Te_out_eV)))
+    return "the heating kick needs positive electron temperatures";
+  if ((p->process_mask & ECR_P_HEAT) && !(p->lnL_ei >= 0.0)) return "negative electron-ion Coulomb logarithm";
   double fsum = 0.0;
   for (int s = 0; s < p->n_species; ++s) {
     const ecr_species &sp = p->species[s];
@@ -316,6 +321,16 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
   const double vcell = ((2.0 * p->R0_m / p->nx) * (2.0 * p->R0_m / p->ny)) * (p->L_m / p->nz);
   K.nfac = weight / vcell;
   K.Cs = p->lnL_ii * (kE * kE) * (kE * kE) / (4.0 * kPi * kEps0 * kEps0);
+  K.hx = 2.0 * p->R0_m / p->nx;
+  K.hy = 2.0 * p->R0_m / p->ny;
+  K.hz = p->L_m / p->nz;
+  // heating kick: D^2 = n_e x (3.715e-6 lnL_ei Q^2 dt) / (M_amu^2 sqrt(T_e)), M in amu
+  // and T_e in eV (Sec. II, the kick's charge law read as Q^2)
+  const bool heat = (p->process_mask & ECR_P_HEAT) != 0;
+  const double te[2] = {p->Te_out_eV, p->Te_in_eV};
+  K.ne_zone[0] = p->ne_out_m3;
+  K.ne_zone[1] = p->ne_in_m3;
+  for (int z = 0; z < 2; ++z) K.rl_zone[z] = heat ? 2.38e-6 * sqrt(te[z]) : 0.0;
   int64_t end = 0;
   for (int s = 0; s < p->n_species; ++s) {
     const ecr_species &sp = p->species[s];
@@ -336,6 +351,10 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
         T.kdt[s][0][q] = sp.k_ion_out_m3s[q] * dt;
       }
       if (q >= 1 && q <= sp.z_max && !((sp.cx_forbidden_mask >> q) & 1u)) ok |= 1u << q;
+      if (heat)
+        for (int z = 0; z < 2; ++z)
+          T.dheat[s][z][q] = (((3.715e-6 * p->lnL_ei) * (double)(q * q)) * dt) /
+                             ((sp.mass_amu * sp.mass_amu) * sqrt(te[z]));
     }
     K.cxok[s] = ok;
     if (s == p->n_species - 1) end = p->n_particles;

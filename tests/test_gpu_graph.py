@@ -77,11 +77,15 @@ def test_graph_after_set_state_and_two_runs_on_one_stream():
     assert not np.array_equal(a.get_state()["vx"], c.get_state()["vx"])
 
 
-def test_graph_self_consistent_electrons_odd_period():
+@pytest.mark.parametrize("heat", [False, True])
+def test_graph_self_consistent_electrons_odd_period(heat):
     # the per-cell charge grid alternates between two buffers every step: an
-    # odd sort period starts replays on either buffer
+    # odd sort period starts replays on either buffer (the heating kick reads
+    # the current one too)
     import torch
     params = W.with_(W.config("c1")[0], self_ne=True, sort_every=15)
+    if heat:
+        params["process_mask"] |= W.P_HEAT
     stream = torch.cuda.Stream()
     a, b = _runs(params, stream)
     a.init_ions()

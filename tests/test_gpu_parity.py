@@ -120,6 +120,11 @@ CASES = {
     # that ionisation fires in one step
     "ionize_self_ne": dict(mask=W.P_IONIZE, v_ev=0.5, self_ne=True, weight=4e12),
     "all_self_ne": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20, self_ne=True, weight=4e12),
+    # electron-ion heating kick: zone background (no bias), and the cell
+    # density with its diamagnetic bias
+    "heat": dict(mask=W.P_HEAT, v_ev=0.5),
+    "heat_self_ne": dict(mask=W.P_HEAT, v_ev=0.5, self_ne=True, weight=4e12),
+    "all_heat_self_ne": dict(mask=W.P_ALL | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True, weight=4e12),
 }
 
 
@@ -144,8 +149,13 @@ def test_single_step_parity(case, seed):
     ev = o.events()
     if case in ("push_walls", "all_walls"):
         assert (ev == W.EV_WALL).sum() > 20
-    if case in ("ionize", "all", "ionize_self_ne", "all_self_ne"):
+    if case in ("ionize", "all", "ionize_self_ne", "all_self_ne", "all_heat_self_ne"):
         assert (ev == W.EV_IONIZE).sum() > 5
+    if case == "all_heat_self_ne":
+        assert (ev == W.EV_WALL).sum() > 20
+    if case in ("heat", "heat_self_ne"):
+        kicked = (b["vx"] != st["vx"]).sum()
+        assert kicked > 2000, kicked
     if case == "cx":
         assert (ev == W.EV_CX).sum() > 10
     if c["mask"] & W.P_COULOMB:
@@ -215,10 +225,14 @@ def test_multi_step_c1_from_init():
         assert np.abs(dg - do).max() <= 1e-12 * np.abs(do).max()
 
 
-def test_multi_step_c1_self_consistent_electrons():
+@pytest.mark.parametrize("heat", [False, True])
+def test_multi_step_c1_self_consistent_electrons(heat):
     # C1 with the electron density taken from the ions' charge cell by cell,
-    # 150 steps across three sorts: every step's decisions bit for bit
+    # 150 steps across three sorts: every step's decisions bit for bit; with
+    # the heating kick and its diamagnetic bias as well
     params = W.with_(W.config("c1")[0], self_ne=True)
+    if heat:
+        params["process_mask"] |= W.P_HEAT
     g = gpu_run(params, events=True)
     g.init_ions()
     o = oracle(params)

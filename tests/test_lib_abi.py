@@ -56,6 +56,12 @@ def test_footprint_and_parameter_checks():
     bad["species"][0]["z_max"] = 40
     with pytest.raises(ecr.EcrError):
         ecr.footprint(bad)
+    # the heating kick needs positive electron temperatures; unknown process bits are refused
+    with pytest.raises(ecr.EcrError, match="temperature"):
+        ecr.footprint(W.with_(p, process_mask=W.P_ALL | W.P_HEAT, Te_out_eV=0.0))
+    assert ecr.footprint(W.with_(p, process_mask=W.P_ALL | W.P_HEAT)) == nb
+    with pytest.raises(ecr.EcrError, match="process_mask"):
+        ecr.footprint(W.with_(p, process_mask=64))
     P, _keep = ecr.make_params(p)
     P.abi_version = 99
     import ctypes as C
