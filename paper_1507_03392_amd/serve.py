@@ -15,7 +15,10 @@ state on the device from admission to retirement and works like this:
 * the host loop polls one event per run: a run whose period has finished
   gets its next period queued, or, when done, its tallies and density read
   back and its slot and memory released, after which the queue head may be
-  admitted.
+  admitted;
+* a request may ask for a warm-up: its first `warmup` steps are run, the
+  tallies read at that point, and the result reports the tallies of the
+  remaining steps only (the stationary window the paper's outputs refer to).
 
 Runs on different slots overlap on the device (their streams map to
 separate hardware queues); a run's result depends only on its own
@@ -39,6 +42,7 @@ class Request:
     arrival: float      # seconds after the start of the serving loop
     params: dict
     steps: int
+    warmup: int = 0     # leading steps left out of the reported tallies
 
 
 @dataclasses.dataclass
@@ -49,6 +53,7 @@ class Result:
     admitted: float = float("nan")
     finished: float = float("nan")
     nbytes: int = 0
+    steps_run: int = 0
     tallies: dict | None = None
     density: dict | None = None
     error: str | None = None
@@ -66,6 +71,7 @@ class _Active:
     slot: int
     done: int = 0
     event: object = None
+    base: dict | None = None  # tallies at the end of the warm-up
 
 
 class Server:
@@ -113,6 +119,12 @@ class Server:
             while waiting and free:
                 req = waiting[0]
                 res = Result(rid=req.rid, n=int(req.params["n"]), arrival=req.arrival)
+                if not 0 <= req.warmup < req.steps:
+                    waiting.popleft()
+                    res.error, res.finished = f"warmup {req.warmup} must be in [0, steps {req.steps})", now()
+                    results[req.rid] = res
+                    note("reject", req.rid)
+                    continue
                 try:
                     nb = footprint(req.params)
                 except EcrError as e:
@@ -151,13 +163,21 @@ class Server:
                 if a.event is not None and not a.event.query():
                     continue
                 moved = True
+                if a.req.warmup > 0 and a.base is None and a.done >= a.req.warmup:
+                    try:
+                        a.base = a.run.tallies()
+                    except EcrError as e:
+                        a.res.error = str(e)
+                        a.done = a.req.steps
                 if a.done >= a.req.steps:
                     try:
-                        a.res.tallies = a.run.tallies()
+                        t = a.run.tallies()
+                        a.res.tallies = tallies_window(t, a.base) if a.base is not None else t
                         a.res.density = {f: a.run.density(f)[0] for f in self.fields}
                     except EcrError as e:
                         a.res.error = str(e)
                     a.res.finished = now()
+                    a.res.steps_run = a.done
                     results[a.req.rid] = a.res
                     a.run.close()
                     del active[slot]
@@ -166,7 +186,8 @@ class Server:
                     note("finish", a.req.rid)
                     continue
                 k = self.period or int(a.req.params["sort_every"])
-                n = min(k, a.req.steps - a.done)
+                stop = a.req.warmup if a.base is None and a.done < a.req.warmup else a.req.steps
+                n = min(k, stop - a.done)
                 try:
                     a.run.step_graph(n)
                 except EcrError as e:
@@ -187,11 +208,19 @@ class Server:
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 
-def summary(results, steps_key="steps"):
+def tallies_window(t, base):
+    """Tallies accumulated between two reads of one run (t later than base)."""
+    out = {}
+    for k, v in t.items():
+        out[k] = v - base[k]
+    return out
+
+
+def summary(results):
     """p50/p99 latency (s) and throughput (particle-steps/s) of served results."""
     ok = [r for r in results if r.error is None]
     lat = np.array([r.latency for r in ok])
-    work = sum(r.n * (r.tallies or {}).get(steps_key, 0) for r in ok)
+    work = sum(r.n * r.steps_run for r in ok)
     span = max(r.finished for r in ok) - min(r.arrival for r in ok) if ok else float("nan")
     return dict(requests=len(results), completed=len(ok),
                 p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
