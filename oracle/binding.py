@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libecr_oracle.so")
 
 MAXS, MAXQ = 4, 32
+MAXN = 4
 FPT_BINS = 32
 BIRTH_NONE = 0xFFFFFFFF
 
@@ -17,7 +18,9 @@ BIRTH_NONE = 0xFFFFFFFF
 class Species(C.Structure):
     _fields_ = [("mass_amu", C.c_double), ("z_max", C.c_int32), ("cx_forbidden_mask", C.c_uint32),
                 ("fraction", C.c_double), ("k_in", C.c_double * MAXQ), ("k_out", C.c_double * MAXQ),
-                ("sigma_cx1", C.c_double), ("n0", C.c_double)]
+                ("sigma_cx1", C.c_double), ("n0", C.c_double),
+                ("k_multi_in", (C.c_double * MAXQ) * (MAXN - 1)), ("k_multi_out", (C.c_double * MAXQ) * (MAXN - 1)),
+                ("sigma_el1", C.c_double)]
 
 
 class Params(C.Structure):
@@ -42,7 +45,8 @@ class Tallies(C.Structure):
                 ("steps", C.c_int64), ("coul_dp", C.c_double * 3), ("coul_de", C.c_double),
                 ("coul_e", C.c_double), ("fpt_n", (C.c_uint64 * MAXQ) * MAXS),
                 ("fpt_sum", (C.c_uint64 * MAXQ) * MAXS), ("fpt_hist", (C.c_uint64 * FPT_BINS) * MAXS),
-                ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS)]
+                ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS),
+                ("ionized_n", (C.c_uint64 * MAXN) * MAXS), ("elastic", (C.c_uint64 * MAXQ) * MAXS)]
 
 
 _lib = None
@@ -123,6 +127,13 @@ def make_params(p):
             S.k_out[q] = s["k_out"][q]
         S.sigma_cx1 = s["sigma_cx1"]
         S.n0 = s["n0"]
+        for k in ("k_multi_in", "k_multi_out"):
+            tab = s.get(k)
+            if tab is not None:
+                for j in range(MAXN - 1):
+                    for q in range(MAXQ):
+                        getattr(S, k)[j][q] = tab[j][q]
+        S.sigma_el1 = s.get("sigma_el1", 0.0)
     P.self_ne = 1 if p.get("self_ne") else 0
     P.lnL_ei = float(p.get("lnL_ei", 17.0))
     P.Te_in_eV = float(p.get("Te_in_eV", 0.0))
@@ -280,4 +291,6 @@ def tallies_to_dict(t):
         fpt_sum=np.array([t.fpt_sum[s][:] for s in range(MAXS)], dtype=np.uint64),
         fpt_hist=np.array([t.fpt_hist[s][:] for s in range(MAXS)], dtype=np.uint64),
         extracted_r=np.array([t.extracted_r[s][:] for s in range(MAXS)], dtype=np.float64),
-        lost_ke=np.array(t.lost_ke[:], dtype=np.float64))
+        lost_ke=np.array(t.lost_ke[:], dtype=np.float64),
+        ionized_n=np.array([t.ionized_n[s][:] for s in range(MAXS)], dtype=np.uint64),
+        elastic=np.array([t.elastic[s][:] for s in range(MAXS)], dtype=np.uint64))

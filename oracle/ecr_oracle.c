@@ -32,7 +32,7 @@
 #define EPS_WALL 1e-9 /* re-emission offset from a wall, m */
 
 /* Philox stream ids (third counter word) */
-enum { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5 };
+enum { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5, S_EL = 6 };
 
 /* Nanbu A(s) table: nodes s = 2^e (1 + j/K) for e in [E_LO, E_HI], j in [0, K) */
 #define A_E_LO (-20)
@@ -48,9 +48,12 @@ struct orc_sim {
   /* derived constants */
   double M[ORC_MAXS];                /* species mass, kg */
   double qmh[ORC_MAXS][ORC_MAXQ];    /* (Q e / M) dt / 2 */
-  double pion[ORC_MAXS][2][ORC_MAXQ];/* ionisation probability per step [outside, inside] */
-  double kdt[ORC_MAXS][2][ORC_MAXQ]; /* rate x dt [outside, inside] (self-consistent electrons) */
+  /* ionisation Q -> Q+n ([n-1]) per step [outside, inside]: probability with
+   * the fixed background, rate x dt for self-consistent electrons */
+  double pion[ORC_MAXS][2][ORC_MAXN][ORC_MAXQ];
+  double kdt[ORC_MAXS][2][ORC_MAXN][ORC_MAXQ];
   double ccx[ORC_MAXS];              /* n0 sigma1 dt */
+  double cel[ORC_MAXS];              /* n0 sigma_el1 dt */
   int cxok[ORC_MAXS][ORC_MAXQ];
   double sig_w[ORC_MAXS], sig_n[ORC_MAXS], sig_i[ORC_MAXS], decx[ORC_MAXS];
   int64_t sp_end[ORC_MAXS];          /* particle ids [sp_end[s-1], sp_end[s]) are species s */
@@ -356,13 +359,20 @@ int orc_create(const orc_params *p, orc_sim **out) {
     for (int Q = 0; Q < ORC_MAXQ; Q++) {
       s->qmh[k][Q] = ((double)Q * E_CHARGE / s->M[k]) * (dt * 0.5);
       /* probability of one ionisation in dt: 1 - exp(-n_e k dt) */
-      s->pion[k][1][Q] = (Q < sp->z_max) ? -expm1(-(p->ne_in * sp->k_in[Q]) * dt) : 0.0;
-      s->pion[k][0][Q] = (Q < sp->z_max) ? -expm1(-(p->ne_out * sp->k_out[Q]) * dt) : 0.0;
-      s->kdt[k][1][Q] = (Q < sp->z_max) ? sp->k_in[Q] * dt : 0.0;
-      s->kdt[k][0][Q] = (Q < sp->z_max) ? sp->k_out[Q] * dt : 0.0;
+      /* channel n only up to z_max; each channel 1 - exp(-n_e k dt) */
+      for (int n = 1; n <= ORC_MAXN; n++) {
+        double kin = n == 1 ? sp->k_in[Q] : sp->k_multi_in[n - 2][Q];
+        double kout = n == 1 ? sp->k_out[Q] : sp->k_multi_out[n - 2][Q];
+        int ok = Q + n <= sp->z_max;
+        s->pion[k][1][n - 1][Q] = ok ? -expm1(-(p->ne_in * kin) * dt) : 0.0;
+        s->pion[k][0][n - 1][Q] = ok ? -expm1(-(p->ne_out * kout) * dt) : 0.0;
+        s->kdt[k][1][n - 1][Q] = ok ? kin * dt : 0.0;
+        s->kdt[k][0][n - 1][Q] = ok ? kout * dt : 0.0;
+      }
       s->cxok[k][Q] = (Q >= 1 && Q <= sp->z_max && !((sp->cx_forbidden_mask >> Q) & 1u));
     }
     s->ccx[k] = (sp->n0 * sp->sigma_cx1) * dt;
+    s->cel[k] = (sp->n0 * sp->sigma_el1) * dt;
     s->sig_w[k] = sqrt(p->T_wall_eV * E_CHARGE / s->M[k]);
     s->sig_n[k] = sqrt(p->T_n_eV * E_CHARGE / s->M[k]);
     s->sig_i[k] = sqrt(p->Ti0_eV * E_CHARGE / s->M[k]);
@@ -808,14 +818,47 @@ static void heat_kick(orc_sim *s, int64_t i) {
 
 /* ------------------------------------------------------------------------ */
 /* Monte-Carlo collisions with electrons and neutrals (Sec. II).             */
-/* One uniform u decides: u < P_ion -> Q+1; u < P_ion + P_cx -> charge       */
-/* exchange.  P_ion = 1 - exp(-n_e k_Q dt) with the zone's n_e and rate;     */
-/* P_cx = n0 (Q sigma1) |v| dt (cross-section scaled linearly with Q, no     */
-/* exchange for forbidden Q such as Ar2+).  Exchange with a neutral drawn    */
-/* from a Maxwellian at T_n: Q = 1 takes the neutral's velocity (resonant);  */
-/* Q >= 3 goes to Q-1 and the energy release dE is shared equally in the     */
-/* centre-of-mass frame of the two equal-mass partners.                      */
+/* One uniform u decides between the channels, taken in this order:         */
+/*   ionisation Q -> Q+n, n = 1..4: P_n = 1 - exp(-n_e k_{Q,n} dt) with the  */
+/*     zone's n_e and rates (channels that would pass z_max are closed);     */
+/*   charge exchange: P_cx = n0 (Q sigma1) |v| dt (cross-section scaled      */
+/*     linearly with Q, none for forbidden Q such as Ar2+);                  */
+/*   elastic ion-atom scattering: P_el = n0 (Q sigma_el1) |v| dt;            */
+/* u below the running sum of the channels up to one picks that channel.    */
+/* Exchange is with a neutral drawn from a Maxwellian at T_n: Q = 1 takes    */
+/* the neutral's velocity (resonant); Q >= 3 goes to Q-1 and the energy      */
+/* release dE is shared equally in the centre-of-mass frame of the two       */
+/* equal-mass partners.  Elastic scattering is isotropic in the centre-of-   */
+/* mass frame of the ion and a neutral drawn the same way (its own stream):  */
+/* the relative speed is kept and turned into a uniformly random direction. */
 /* ------------------------------------------------------------------------ */
+static void neutral_partner(const orc_sim *s, int64_t i, uint32_t stream, int sp, double w[3]) {
+  uint32_t G[4], H[4];
+  draw(s, s->id[i], (uint32_t)s->step, stream, 0, G);
+  draw(s, s->id[i], (uint32_t)s->step, stream, 1, H);
+  double n0, n1, n2, ndis;
+  box_muller(orc_u53(G[0], G[1]), orc_u53(G[2], G[3]), &n0, &n1);
+  box_muller(orc_u53(H[0], H[1]), orc_u53(H[2], H[3]), &n2, &ndis);
+  double sg = s->sig_n[sp];
+  w[0] = sg * n0; w[1] = sg * n1; w[2] = sg * n2;
+}
+
+/* v -> V_cm + (|g'|/2) n, n isotropic from call 2 of the stream; |g'|^2 = |v - w|^2 + extra */
+static void cm_isotropic(orc_sim *s, int64_t i, uint32_t stream, const double w[3], double extra) {
+  uint32_t I[4];
+  draw(s, s->id[i], (uint32_t)s->step, stream, 2, I);
+  double ct = 1.0 - 2.0 * orc_u53(I[0], I[1]);
+  double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
+  double ph = 2.0 * PI * orc_u53(I[2], I[3]);
+  double nxv = st * cos(ph), nyv = st * sin(ph), nzv = ct;
+  double gx = s->vx[i] - w[0], gy = s->vy[i] - w[1], gz = s->vz[i] - w[2];
+  double g2 = (gx * gx + gy * gy) + gz * gz + extra;
+  double hg = 0.5 * sqrt(g2);
+  s->vx[i] = (s->vx[i] + w[0]) * 0.5 + hg * nxv;
+  s->vy[i] = (s->vy[i] + w[1]) * 0.5 + hg * nyv;
+  s->vz[i] = (s->vz[i] + w[2]) * 0.5 + hg * nzv;
+}
+
 static int mcc(orc_sim *s, int64_t i) {
   uint32_t W[4];
   draw(s, s->id[i], (uint32_t)s->step, S_STEP, 0, W);
@@ -823,62 +866,58 @@ static int mcc(orc_sim *s, int64_t i) {
   int sp = s->sp[i], Q = s->q[i];
   double x = s->x[i], y = s->y[i], z = s->z[i];
   int zone = (((x * x) * s->ia2 + (y * y) * s->ia2) + (z * z) * s->ic2) < 1.0;
-  /* ionisation probability: the fixed background's 1 - exp(-n_e k dt), or
+  /* ionisation channels: the fixed background's 1 - exp(-n_e k dt), or
    * with self-consistent electrons n_e k dt, n_e = weight x (ion charge of
    * the cell at the start of the step) / cell volume */
-  double pi = 0.0;
-  if (s->p.process_mask & ORC_P_IONIZE) {
-    if (s->p.self_ne) {
-      double ne = s->nfac * (double)s->chg[orc_cell_of(s, x, y, z)];
-      pi = ne * s->kdt[sp][zone][Q];
-    } else {
-      pi = s->pion[sp][zone][Q];
-    }
+  double cum[ORC_MAXN];
+  double acc = 0.0;
+  double ne = 0.0;
+  if ((s->p.process_mask & ORC_P_IONIZE) && s->p.self_ne) ne = s->nfac * (double)s->chg[orc_cell_of(s, x, y, z)];
+  for (int n = 1; n <= ORC_MAXN; n++) {
+    double pn = 0.0;
+    if (s->p.process_mask & ORC_P_IONIZE)
+      pn = s->p.self_ne ? ne * s->kdt[sp][zone][n - 1][Q] : s->pion[sp][zone][n - 1][Q];
+    acc = acc + pn;
+    cum[n - 1] = acc;
   }
+  double speed = sqrt((s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i]);
   double pc = 0.0;
-  if ((s->p.process_mask & ORC_P_CX) && s->cxok[sp][Q]) {
-    double sp2 = (s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i];
-    pc = (s->ccx[sp] * (double)Q) * sqrt(sp2);
-  }
-  double pt = pi + pc;
-  if (pt > 0.1) s->t.anomalies++;
-  if (u < pi) {
-    s->t.ionized[sp][Q]++;
-    if (Q == 0) s->birth[i] = (uint32_t)s->step; /* an ion is made from an atom */
-    s->q[i] = (uint8_t)(Q + 1);
-    return ORC_EV_IONIZE;
+  if ((s->p.process_mask & ORC_P_CX) && s->cxok[sp][Q]) pc = (s->ccx[sp] * (double)Q) * speed;
+  double pe = 0.0;
+  if (s->p.process_mask & ORC_P_ELASTIC) pe = (s->cel[sp] * (double)Q) * speed;
+  double pt = acc + pc;
+  double pall = pt + pe;
+  if (pall > 0.1) s->t.anomalies++;
+  for (int n = 1; n <= ORC_MAXN; n++) {
+    if (u < cum[n - 1]) {
+      s->t.ionized[sp][Q]++;
+      s->t.ionized_n[sp][n - 1]++;
+      if (Q == 0) s->birth[i] = (uint32_t)s->step; /* an ion is made from an atom */
+      s->q[i] = (uint8_t)(Q + n);
+      return ORC_EV_IONIZE;
+    }
   }
   if (u < pt) {
     s->t.cx[sp][Q]++;
     /* resonant exchange hands the charge to the neutral: a new ion */
     if (Q == 1) s->birth[i] = (uint32_t)s->step;
-    uint32_t G[4], H[4];
-    draw(s, s->id[i], (uint32_t)s->step, S_CX, 0, G);
-    draw(s, s->id[i], (uint32_t)s->step, S_CX, 1, H);
-    double n0, n1, n2, ndis;
-    box_muller(orc_u53(G[0], G[1]), orc_u53(G[2], G[3]), &n0, &n1);
-    box_muller(orc_u53(H[0], H[1]), orc_u53(H[2], H[3]), &n2, &ndis);
-    double sg = s->sig_n[sp];
-    double wx = sg * n0, wy = sg * n1, wz = sg * n2;
+    double w[3];
+    neutral_partner(s, i, S_CX, sp, w);
     if (Q == 1) {
-      s->vx[i] = wx; s->vy[i] = wy; s->vz[i] = wz;
+      s->vx[i] = w[0]; s->vy[i] = w[1]; s->vz[i] = w[2];
     } else {
-      uint32_t I[4];
-      draw(s, s->id[i], (uint32_t)s->step, S_CX, 2, I);
-      double ct = 1.0 - 2.0 * orc_u53(I[0], I[1]);
-      double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
-      double ph = 2.0 * PI * orc_u53(I[2], I[3]);
-      double nxv = st * cos(ph), nyv = st * sin(ph), nzv = ct;
-      double gx = s->vx[i] - wx, gy = s->vy[i] - wy, gz = s->vz[i] - wz;
-      double g2 = (gx * gx + gy * gy) + gz * gz + s->decx[sp];
-      double hg = 0.5 * sqrt(g2);
-      s->vx[i] = (s->vx[i] + wx) * 0.5 + hg * nxv;
-      s->vy[i] = (s->vy[i] + wy) * 0.5 + hg * nyv;
-      s->vz[i] = (s->vz[i] + wz) * 0.5 + hg * nzv;
+      cm_isotropic(s, i, S_CX, w, s->decx[sp]);
       s->q[i] = (uint8_t)(Q - 1);
       s->t.cx_products[sp]++;
     }
     return ORC_EV_CX;
+  }
+  if (u < pall) {
+    s->t.elastic[sp][Q]++;
+    double w[3];
+    neutral_partner(s, i, S_EL, sp, w);
+    cm_isotropic(s, i, S_EL, w, 0.0);
+    return ORC_EV_ELASTIC;
   }
   return ORC_EV_NONE;
 }
@@ -953,7 +992,7 @@ int orc_step(orc_sim *s, int64_t n_steps) {
         ev = boundary(s, i, x0, y0, z0);
       }
       if (ev == ORC_EV_NONE && (pm & ORC_P_HEAT) && s->q[i] >= 1) heat_kick(s, i);
-      if (ev == ORC_EV_NONE && (pm & (ORC_P_IONIZE | ORC_P_CX))) ev = mcc(s, i);
+      if (ev == ORC_EV_NONE && (pm & (ORC_P_IONIZE | ORC_P_CX | ORC_P_ELASTIC))) ev = mcc(s, i);
       s->ev[i] = (uint8_t)ev;
       if (!(isfinite(s->x[i]) && isfinite(s->y[i]) && isfinite(s->z[i]) && isfinite(s->vx[i]) &&
             isfinite(s->vy[i]) && isfinite(s->vz[i])))

@@ -21,6 +21,7 @@ extern "C" {
 
 #define ORC_MAXS 4   /* species */
 #define ORC_MAXQ 32  /* charge-state slots per species, Q = 0..31 */
+#define ORC_MAXN 4   /* electrons removed by one ionisation, n = 1..4 */
 #define ORC_FPT_BINS 32            /* log2 bins of first-passage times */
 #define ORC_BIRTH_NONE 0xFFFFFFFFu /* birth of an atom or of an ion of unknown origin */
 
@@ -31,6 +32,7 @@ extern "C" {
 #define ORC_P_COULOMB 8u   /* ion-ion Coulomb scattering (TA pairing, Nanbu angle) */
 #define ORC_P_DEPOSIT 16u  /* cloud-in-cell density deposit */
 #define ORC_P_HEAT 32u     /* electron-ion heating kick, biased along the electron diamagnetic drift */
+#define ORC_P_ELASTIC 64u  /* elastic ion-atom scattering on the background neutrals, isotropic */
 
 /* deposit fields */
 #define ORC_F_ION_N 0  /* sum of CIC weights of ions (Q >= 1) */
@@ -45,6 +47,7 @@ extern "C" {
 #define ORC_EV_CX 2
 #define ORC_EV_WALL 3
 #define ORC_EV_EXTRACT 4
+#define ORC_EV_ELASTIC 5
 
 typedef struct {
   double mass_amu;
@@ -55,6 +58,9 @@ typedef struct {
   double k_out[ORC_MAXQ];     /* same, outside the zone */
   double sigma_cx1;           /* charge-exchange cross-section of Q=1, m^2 */
   double n0;                  /* background neutral density, m^-3 */
+  double k_multi_in[ORC_MAXN - 1][ORC_MAXQ];  /* rate Q -> Q+n, n = 2..4 ([n-2]), inside the zone */
+  double k_multi_out[ORC_MAXN - 1][ORC_MAXQ]; /* same, outside */
+  double sigma_el1;           /* elastic ion-atom cross-section of Q=1, m^2 (Q scales it linearly) */
 } orc_species;
 
 typedef struct {
@@ -98,6 +104,8 @@ typedef struct {
   uint64_t fpt_hist[ORC_MAXS][ORC_FPT_BINS]; /* bin floor(log2 t), t <= 1 in bin 0 */
   double extracted_r[ORC_MAXS][ORC_MAXQ];    /* sum of the crossing radius of extracted particles, m */
   double lost_ke[ORC_MAXS];             /* kinetic energy of ions (Q >= 1) lost to walls and aperture, J */
+  uint64_t ionized_n[ORC_MAXS][ORC_MAXN];  /* ionisations by electrons removed ([n-1]) */
+  uint64_t elastic[ORC_MAXS][ORC_MAXQ];    /* elastic ion-atom collisions, by charge */
 } orc_tallies;
 
 typedef struct orc_sim orc_sim;
