@@ -38,9 +38,10 @@
 extern "C" {
 #endif
 
-#define ECR_ABI_VERSION 3u
+#define ECR_ABI_VERSION 4u
 #define ECR_MAX_SPECIES 4
 #define ECR_MAX_Q 32          /* charge-state slots per species: Q = 0..31 */
+#define ECR_MAX_NION 4        /* electrons one ionisation may remove: Q -> Q+n, n = 1..4 */
 #define ECR_FPT_BINS 32       /* log2 bins of first-passage times */
 #define ECR_BIRTH_NONE 0xffffffffu /* birth step of an atom, or of an ion of unknown origin */
 
@@ -60,12 +61,12 @@ typedef enum { ECR_FP64 = 0, ECR_FP32_MIXED = 1 } ecr_precision;
 /* process switches (process_mask) */
 enum {
   ECR_P_PUSH = 1,     /* Boris push in the magnetic (and optional electric) field + wall/aperture loss */
-  ECR_P_IONIZE = 2,   /* electron-impact ionisation Q -> Q+1 */
+  ECR_P_IONIZE = 2,   /* electron-impact ionisation Q -> Q+n (n = 1, and 2..4 where the species gives rates) */
   ECR_P_CX = 4,       /* charge exchange with the background neutral gas */
   ECR_P_COULOMB = 8,  /* ion-ion Coulomb scattering: Takizuka-Abe pairing, Nanbu angle */
   ECR_P_DEPOSIT = 16, /* cloud-in-cell density deposit */
   ECR_P_ALL = 31,     /* the five processes above: the fixed-background step */
-  ECR_P_HEAT = 32     /* electron-ion heating and diffusion kick (Sec. II): each ion that stays in the
+  ECR_P_HEAT = 32,    /* electron-ion heating and diffusion kick (Sec. II): each ion that stays in the
                          chamber gets dV = D (R + delta) |R| / |R + delta| before ionisation and charge
                          exchange, D^2 = 3.715e-6 n_e lnL_ei Q^2 dt / (M_amu^2 sqrt(T_e)) (SI; the printed
                          formula's Q read as Q^2, the heating rate's stated charge law), R uniform in
@@ -74,6 +75,8 @@ enum {
                          electron density in the ion's z plane (cells beyond the mesh: 0) times
                          -R_L / n_e(cell), R_L = 2.38e-6 sqrt(T_e) / (|B(cell centre)| hx); with the fixed
                          background, n_e and T_e are the zone's and delta = 0 */
+  ECR_P_ELASTIC = 64  /* elastic ion-atom scattering on the background neutrals (Sec. II): isotropic in the
+                         centre-of-mass frame of the ion and a Maxwellian neutral at T_n (Philox stream 6) */
 };
 
 /* density fields (bit f of deposit_mask enables field f) */
@@ -97,7 +100,7 @@ enum {
 };
 
 /* event codes returned by ecr_event_log */
-enum { ECR_EV_NONE = 0, ECR_EV_IONIZE = 1, ECR_EV_CX = 2, ECR_EV_WALL = 3, ECR_EV_EXTRACT = 4 };
+enum { ECR_EV_NONE = 0, ECR_EV_IONIZE = 1, ECR_EV_CX = 2, ECR_EV_WALL = 3, ECR_EV_EXTRACT = 4, ECR_EV_ELASTIC = 5 };
 
 /* One ion species (the paper models argon, Sec. II; a second species is allowed). */
 typedef struct {
@@ -109,6 +112,13 @@ typedef struct {
   double k_ion_out_m3s[ECR_MAX_Q];    /* same, outside the zone */
   double sigma_cx1_m2;                /* charge-exchange cross-section of Q = 1; Q scales it linearly */
   double n0_m3;                       /* background neutral density (charge-exchange target) */
+  /* Sec. II, multiple ionisation: rate of Q -> Q+n for n = 2..ECR_MAX_NION ([n-2]); entries whose Q + n
+     passes z_max are ignored.  One uniform picks among the channels n = 1..4, charge exchange and elastic
+     scattering by running sums of their probabilities, in that order. */
+  double k_ion_multi_in_m3s[ECR_MAX_NION - 1][ECR_MAX_Q];
+  double k_ion_multi_out_m3s[ECR_MAX_NION - 1][ECR_MAX_Q];
+  double sigma_el1_m2;                /* elastic ion-atom cross-section of Q = 1 (ECR_P_ELASTIC); Q scales it
+                                         linearly, P_el = n0 (Q sigma_el1) |v| dt */
 } ecr_species;
 
 typedef struct {
@@ -165,6 +175,8 @@ typedef struct {
   uint64_t fpt_hist[ECR_MAX_SPECIES][ECR_FPT_BINS]; /* all charges: bin k counts times t with floor(log2 t) = k (t <= 1 in bin 0) */
   double extracted_r[ECR_MAX_SPECIES][ECR_MAX_Q];   /* sum of sqrt(x^2 + y^2) where the extracted ions cross the flange, m */
   double lost_ke[ECR_MAX_SPECIES];                  /* kinetic energy of the ions (Q >= 1) lost to the walls and the aperture, J */
+  uint64_t ionized_n[ECR_MAX_SPECIES][ECR_MAX_NION];/* ionisation events by electrons removed ([n-1]) */
+  uint64_t elastic[ECR_MAX_SPECIES][ECR_MAX_Q];     /* elastic ion-atom collisions, by charge */
 } ecr_tallies;
 
 /* Host particle arrays indexed by particle id (length n). */

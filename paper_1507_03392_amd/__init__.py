@@ -15,12 +15,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libecrpic.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAXS, MAXQ = 4, 32
+MAXN = 4  # electrons one ionisation may remove
 FPT_BINS = 32
 BIRTH_NONE = 0xFFFFFFFF
 FP64, FP32_MIXED = 0, 1
-P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL, P_HEAT = 1, 2, 4, 8, 16, 31, 32
+P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL, P_HEAT, P_ELASTIC = 1, 2, 4, 8, 16, 31, 32, 64
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P, N_FIELDS = 0, 1, 2, 3, 4
 FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE = 1, 2, 4
 K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, N_KERNELS = 0, 1, 2, 3, 4, 5, 6
@@ -43,7 +44,9 @@ class EcrError(RuntimeError):
 class Species(C.Structure):
     _fields_ = [("mass_amu", C.c_double), ("z_max", C.c_int32), ("cx_forbidden_mask", C.c_uint32),
                 ("fraction", C.c_double), ("k_ion_in_m3s", C.c_double * MAXQ),
-                ("k_ion_out_m3s", C.c_double * MAXQ), ("sigma_cx1_m2", C.c_double), ("n0_m3", C.c_double)]
+                ("k_ion_out_m3s", C.c_double * MAXQ), ("sigma_cx1_m2", C.c_double), ("n0_m3", C.c_double),
+                ("k_ion_multi_in_m3s", (C.c_double * MAXQ) * (MAXN - 1)),
+                ("k_ion_multi_out_m3s", (C.c_double * MAXQ) * (MAXN - 1)), ("sigma_el1_m2", C.c_double)]
 
 
 class Params(C.Structure):
@@ -69,7 +72,8 @@ class Tallies(C.Structure):
                 ("steps", C.c_int64), ("coul_dp", C.c_double * 3), ("coul_de", C.c_double),
                 ("coul_e", C.c_double), ("fpt_n", (C.c_uint64 * MAXQ) * MAXS),
                 ("fpt_sum", (C.c_uint64 * MAXQ) * MAXS), ("fpt_hist", (C.c_uint64 * FPT_BINS) * MAXS),
-                ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS)]
+                ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS),
+                ("ionized_n", (C.c_uint64 * MAXN) * MAXS), ("elastic", (C.c_uint64 * MAXQ) * MAXS)]
 
 
 class StateView(C.Structure):
@@ -161,6 +165,13 @@ def make_params(p, events=False, split=False):
             S.k_ion_out_m3s[q] = s["k_out"][q]
         S.sigma_cx1_m2 = s["sigma_cx1"]
         S.n0_m3 = s["n0"]
+        for key, dst in (("k_multi_in", S.k_ion_multi_in_m3s), ("k_multi_out", S.k_ion_multi_out_m3s)):
+            tab = s.get(key)
+            if tab is not None:
+                for j in range(MAXN - 1):
+                    for q in range(MAXQ):
+                        dst[j][q] = tab[j][q]
+        S.sigma_el1_m2 = s.get("sigma_el1", 0.0)
     return P, keep
 
 
@@ -182,7 +193,8 @@ def tallies_to_dict(t):
                 cx_products=np.array(t.cx_products[:], dtype=np.uint64), recycled=int(t.recycled),
                 anomalies=int(t.anomalies), steps=int(t.steps), coul_dp=np.array(t.coul_dp[:]),
                 coul_de=float(t.coul_de), coul_e=float(t.coul_e), fpt_n=g(t.fpt_n), fpt_sum=g(t.fpt_sum),
-                fpt_hist=g(t.fpt_hist), extracted_r=d(t.extracted_r), lost_ke=np.array(t.lost_ke[:]))
+                fpt_hist=g(t.fpt_hist), extracted_r=d(t.extracted_r), lost_ke=np.array(t.lost_ke[:]),
+                ionized_n=g(t.ionized_n), elastic=g(t.elastic))
 
 
 class Run:

@@ -23,9 +23,9 @@ constexpr double kWallEps = 1e-9;            // re-emission offset from a wall, 
 
 // Philox stream ids (counter word 2); word 0 = particle id, word 1 = step,
 // word 3 = call index within the stream.
-enum : uint32_t { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5 };
-enum : uint8_t { EV_NONE = 0, EV_IONIZE = 1, EV_CX = 2, EV_WALL = 3, EV_EXTRACT = 4 };
-enum : uint32_t { P_PUSH = 1, P_IONIZE = 2, P_CX = 4, P_COULOMB = 8, P_DEPOSIT = 16, P_HEAT = 32 };
+enum : uint32_t { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5, S_EL = 6 };
+enum : uint8_t { EV_NONE = 0, EV_IONIZE = 1, EV_CX = 2, EV_WALL = 3, EV_EXTRACT = 4, EV_ELASTIC = 5 };
+enum : uint32_t { P_PUSH = 1, P_IONIZE = 2, P_CX = 4, P_COULOMB = 8, P_DEPOSIT = 16, P_HEAT = 32, P_ELASTIC = 64 };
 
 // Nanbu A(s) table: ln A at s = 2^e (1 + j/K), e in [kAeLo, kAeHi], j in [0, K)
 constexpr int kAeLo = -20;
@@ -37,6 +37,7 @@ constexpr double kSHi = 8.0;                  // isotropic at and above
 
 constexpr int kMaxS = 4;
 constexpr int kMaxQ = 32;
+constexpr int kMaxN = 4;  // electrons removed by one ionisation
 
 // Run constants that every kernel reads (passed by value).
 struct KParams {
@@ -49,6 +50,8 @@ struct KParams {
   // 2.38e-6 sqrt(T_e) (the electron Larmor radius times |B|)
   double ne_zone[2], rl_zone[2];
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
+  double cel[kMaxS];     // n0 sigma_el1 dt (elastic ion-atom scattering)
+  int32_t nion;          // ionisation channels with a nonzero rate: 1 .. kMaxN
   // per species pair (a, b): reduced mass mu = ma mb / (ma + mb), mu / ma, mu / mb
   double mu[kMaxS][kMaxS], mra[kMaxS][kMaxS], mrb[kMaxS][kMaxS];
   uint32_t cxok[kMaxS];  // bit Q: charge exchange allowed from Q
@@ -71,6 +74,9 @@ struct Tables {
   double qmh[kMaxS][kMaxQ];      // (Q e / M) dt / 2
   double pion[kMaxS][2][kMaxQ];  // ionisation probability per step [outside, inside]
   double kdt[kMaxS][2][kMaxQ];   // rate x dt [outside, inside], for a cell's own electron density
+  // the same for Q -> Q+n, n = 2..kMaxN ([n-2]); zero where Q + n passes z_max
+  double pmul[kMaxS][2][kMaxN - 1][kMaxQ];
+  double kmul[kMaxS][2][kMaxN - 1][kMaxQ];
   double dheat[kMaxS][2][kMaxQ]; // heating kick D^2 / n_e [outside, inside]
   double lnA[kANodes];           // ln A at the Nanbu table nodes
 };
@@ -348,34 +354,64 @@ __device__ __forceinline__ uint8_t wall_event(const KParams &P, uint32_t id, uin
 // T_n; Q = 1 takes its velocity (resonant), Q >= 3 goes to Q-1 with the
 // energy release dE shared equally in the centre-of-mass frame.
 // ---------------------------------------------------------------------------
+// a background neutral for a collision: Maxwellian at T_n, from calls 0
+// and 1 of the given stream
 template <typename R>
-__device__ __forceinline__ void cx_outcome(const KParams &P, uint32_t id, uint32_t step, int s, int Q, R &vx,
-                                           R &vy, R &vz) {
-  const uint4 G = draw(P, id, step, S_CX, 0);
-  const uint4 H = draw(P, id, step, S_CX, 1);
+__device__ __forceinline__ void neutral_partner(const KParams &P, uint32_t id, uint32_t step, uint32_t stream, int s,
+                                                R &wx, R &wy, R &wz) {
+  const uint4 G = draw(P, id, step, stream, 0);
+  const uint4 H = draw(P, id, step, stream, 1);
   double n0, n1, n2, nd;
   box_muller(u53(G.x, G.y), u53(G.z, G.w), n0, n1);
   box_muller(u53(H.x, H.y), u53(H.z, H.w), n2, nd);
   const double sg = P.sig_n[s];
-  const R wx = (R)(sg * n0), wy = (R)(sg * n1), wz = (R)(sg * n2);
-  if (Q == 1) {
-    vx = wx;
-    vy = wy;
-    vz = wz;
-    return;
-  }
-  const uint4 I = draw(P, id, step, S_CX, 2);
+  wx = (R)(sg * n0);
+  wy = (R)(sg * n1);
+  wz = (R)(sg * n2);
+}
+
+// equal masses, isotropic in the centre-of-mass frame: v -> V + (|g'|/2) n,
+// |g'|^2 = |v - w|^2 + extra, n from call 2 of the stream
+template <typename R>
+__device__ __forceinline__ void cm_isotropic(const KParams &P, uint32_t id, uint32_t step, uint32_t stream, R extra,
+                                             R wx, R wy, R wz, R &vx, R &vy, R &vz) {
+  const uint4 I = draw(P, id, step, stream, 2);
   const double ct = 1.0 - 2.0 * u53(I.x, I.y);
   const double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
   double sp, cp;
   sincos(2.0 * kPi * u53(I.z, I.w), &sp, &cp);
   const R nxv = (R)(st * cp), nyv = (R)(st * sp), nzv = (R)ct;
   const R gx = vx - wx, gy = vy - wy, gz = vz - wz;
-  const R g2 = (gx * gx + gy * gy) + gz * gz + (R)P.decx[s];
+  const R g2 = (gx * gx + gy * gy) + gz * gz + extra;
   const R hg = (R)0.5 * sqrt(g2);
   vx = (vx + wx) * (R)0.5 + hg * nxv;
   vy = (vy + wy) * (R)0.5 + hg * nyv;
   vz = (vz + wz) * (R)0.5 + hg * nzv;
+}
+
+// charge exchange with a background neutral (Sec. II): Q = 1 takes the
+// neutral's velocity; Q >= 2 shares the release dE in the centre-of-mass frame
+template <typename R>
+__device__ __forceinline__ void cx_outcome(const KParams &P, uint32_t id, uint32_t step, int s, int Q, R &vx,
+                                           R &vy, R &vz) {
+  R wx, wy, wz;
+  neutral_partner<R>(P, id, step, S_CX, s, wx, wy, wz);
+  if (Q == 1) {
+    vx = wx;
+    vy = wy;
+    vz = wz;
+    return;
+  }
+  cm_isotropic<R>(P, id, step, S_CX, (R)P.decx[s], wx, wy, wz, vx, vy, vz);
+}
+
+// elastic ion-atom scattering, isotropic in the centre-of-mass frame (Sec. II)
+template <typename R>
+__device__ __forceinline__ void elastic_outcome(const KParams &P, uint32_t id, uint32_t step, int s, R &vx, R &vy,
+                                                R &vz) {
+  R wx, wy, wz;
+  neutral_partner<R>(P, id, step, S_EL, s, wx, wy, wz);
+  cm_isotropic<R>(P, id, step, S_EL, (R)0, wx, wy, wz, vx, vy, vz);
 }
 
 // ---------------------------------------------------------------------------

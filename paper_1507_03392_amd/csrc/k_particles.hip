@@ -128,14 +128,18 @@ __device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__rest
 }
 
 // ---------------------------------------------------------------------------
-// One particle: push -> wall/aperture -> heating kick -> ionisation / charge
-// exchange.
+// One particle: push -> wall/aperture -> heating kick -> ionisation (Q -> Q+n)
+// / charge exchange / elastic ion-atom scattering.
 // Tallies are rare events (~1e-4 per particle-step) and go straight to
 // 64-bit global atomics; so do the loss diagnostics (first-passage times,
 // crossing radius, lost kinetic energy), and the particle's birth step
 // (birth[j]) is read or written only on such events.  Returns the event code.
 // ---------------------------------------------------------------------------
-template <typename R, bool HAS_E>
+// EXT: the kernel variant with the optional physics (self-consistent
+// electrons, heating kick, multiple ionisation, elastic scattering); the
+// default step runs the lean variant, which leaves those paths out of the
+// code altogether
+template <typename R, bool HAS_E, bool EXT>
 __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
                                            const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
                                            uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz,
@@ -175,17 +179,14 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
       Q = 0;
     }
   }
-  if (ev == EV_NONE && (P.pmask & P_HEAT) && Q >= 1) heat_kick<R>(P, T, id, step, s, Q, x, y, z, vx, vy, vz, chg);
-  if (ev == EV_NONE && (P.pmask & (P_IONIZE | P_CX))) {
+  if (EXT && ev == EV_NONE && (P.pmask & P_HEAT) && Q >= 1)
+    heat_kick<R>(P, T, id, step, s, Q, x, y, z, vx, vy, vz, chg);
+  if (!EXT && ev == EV_NONE && (P.pmask & (P_IONIZE | P_CX))) {
     const uint4 W = draw(P, id, step, S_STEP, 0);
     const double u = u53(W.x, W.y);
     const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
-    // ionisation: the fixed background's tabulated probability, or with
-    // ECR_FLAG_SELF_NE n_e k dt, n_e = weight x (ion charge of the cell at
-    // the start of the step) / cell volume
-    double pi = 0.0;
-    if (P.pmask & P_IONIZE)
-      pi = chg ? (P.nfac * (double)chg[cell_of<R>(P, x, y, z)]) * T->kdt[s][zone][Q] : T->pion[s][zone][Q];
+    // single ionisation with the fixed background, then charge exchange
+    const double pi = (P.pmask & P_IONIZE) ? T->pion[s][zone][Q] : 0.0;
     double pc = 0.0;
     if ((P.pmask & P_CX) && ((P.cxok[s] >> Q) & 1u)) {
       const R sp2 = (vx * vx + vy * vy) + vz * vz;
@@ -195,6 +196,7 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     if (pt > 0.1) atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
     if (u < pi) {
       atomicAdd((unsigned long long *)&acc->t.ionized[s][Q], 1ull);
+      atomicAdd((unsigned long long *)&acc->t.ionized_n[s][0], 1ull);
       if (Q == 0) birth[j] = step;  // an ion is made from an atom
       Q = Q + 1;
       ev = EV_IONIZE;
@@ -207,6 +209,67 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
         atomicAdd((unsigned long long *)&acc->t.cx_products[s], 1ull);
       }
       ev = EV_CX;
+    }
+  }
+  if (EXT && ev == EV_NONE && (P.pmask & (P_IONIZE | P_CX | P_ELASTIC))) {
+    const uint4 W = draw(P, id, step, S_STEP, 0);
+    const double u = u53(W.x, W.y);
+    const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
+    // ionisation channels Q -> Q+n: the fixed background's tabulated
+    // probabilities, or with ECR_FLAG_SELF_NE n_e k dt, n_e = weight x (ion
+    // charge of the cell at the start of the step) / cell volume.  One
+    // uniform picks the channel by running sums: ionisation n = 1..4, then
+    // charge exchange, then elastic scattering.
+    double pi = 0.0, ne = 0.0;
+    if (P.pmask & P_IONIZE) {
+      if (chg) {
+        ne = P.nfac * (double)chg[cell_of<R>(P, x, y, z)];
+        pi = ne * T->kdt[s][zone][Q];
+      } else {
+        pi = T->pion[s][zone][Q];
+      }
+    }
+    double c2 = pi, c3 = pi, c4 = pi;  // running sums through n = 2, 3, 4
+    if ((P.pmask & P_IONIZE) && P.nion > 1) {
+      const double p2 = chg ? ne * T->kmul[s][zone][0][Q] : T->pmul[s][zone][0][Q];
+      const double p3 = chg ? ne * T->kmul[s][zone][1][Q] : T->pmul[s][zone][1][Q];
+      const double p4 = chg ? ne * T->kmul[s][zone][2][Q] : T->pmul[s][zone][2][Q];
+      c2 = pi + p2;
+      c3 = c2 + p3;
+      c4 = c3 + p4;
+    }
+    const bool cxon = (P.pmask & P_CX) && ((P.cxok[s] >> Q) & 1u);
+    const bool elon = (P.pmask & P_ELASTIC) != 0;
+    double speed = 0.0;
+    if (cxon || elon) {
+      const R sp2 = (vx * vx + vy * vy) + vz * vz;
+      speed = (double)sqrt(sp2);
+    }
+    double pc = 0.0;
+    if (cxon) pc = (P.ccx[s] * (double)Q) * speed;
+    const double pt = c4 + pc;
+    const double pall = elon ? pt + (P.cel[s] * (double)Q) * speed : pt;
+    if (pall > 0.1) atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
+    if (u < c4) {
+      const int n = u < pi ? 1 : (u < c2 ? 2 : (u < c3 ? 3 : 4));
+      atomicAdd((unsigned long long *)&acc->t.ionized[s][Q], 1ull);
+      atomicAdd((unsigned long long *)&acc->t.ionized_n[s][n - 1], 1ull);
+      if (Q == 0) birth[j] = step;  // an ion is made from an atom
+      Q = Q + n;
+      ev = EV_IONIZE;
+    } else if (u < pt) {
+      atomicAdd((unsigned long long *)&acc->t.cx[s][Q], 1ull);
+      if (Q == 1) birth[j] = step;  // resonant exchange: the ion is the former neutral
+      cx_outcome<R>(P, id, step, s, Q, vx, vy, vz);
+      if (Q >= 2) {
+        Q = Q - 1;
+        atomicAdd((unsigned long long *)&acc->t.cx_products[s], 1ull);
+      }
+      ev = EV_CX;
+    } else if (u < pall) {
+      atomicAdd((unsigned long long *)&acc->t.elastic[s][Q], 1ull);
+      elastic_outcome<R>(P, id, step, s, vx, vy, vz);
+      ev = EV_ELASTIC;
     }
   }
   if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) && isfinite(vz)))
@@ -474,7 +537,7 @@ __device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t 
   if (head && cell != 0xffffffffu && q != 0u) atomicAdd(&chg[cell], q);
 }
 
-template <typename R, bool HAS_E, bool DEP>
+template <typename R, bool HAS_E, bool DEP, bool EXT>
 __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                  const double *__restrict__ ef, uint8_t *__restrict__ evlog,
                                                  DevAccum *__restrict__ acc, double *__restrict__ dens,
@@ -500,7 +563,7 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
       const uint32_t id = S.pid[j];
       int Q = q_of(qs0);
       const int s = sp_of(qs0);
-      const uint8_t ev = advance<R, HAS_E>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur);
+      const uint8_t ev = advance<R, HAS_E, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur);
       S.x[j] = x;
       S.y[j] = y;
       S.z[j] = z;
@@ -509,13 +572,13 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
       S.vz[j] = vz;
       S.qs[j] = make_qs(Q, s);
       if (evlog) evlog[j] = ev;
-      if (chg_next && Q >= 1) {
+      if (EXT && chg_next && Q >= 1) {
         ccell = cell_of<R>(P, x, y, z);
         cq = (uint32_t)Q;
       }
       if (DEP) stage_cic<R>(P, sh.st, i, x, y, z, Q, mn, mx);
     }
-    if (chg_next) add_charge(chg_next, ccell, cq);  // all lanes together: run sums use shuffles
+    if (EXT && chg_next) add_charge(chg_next, ccell, cq);  // all lanes together: run sums use shuffles
   }
   if (DEP) deposit_staged<R>(P, dens, sh, box, mn, mx);
 }
@@ -692,23 +755,37 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
   hipLaunchKernelGGL(k_init<R>, dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, S);
 }
 
+template <typename R, bool EXT>
+static void launch_push_v(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
+                          DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
+                          hipStream_t st) {
+  const dim3 g(grid_for(P.n, kTile)), b(kBlock);
+  if (ef) {
+    if (dens)
+      hipLaunchKernelGGL((k_push<R, true, true, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                         chg_next);
+    else
+      hipLaunchKernelGGL((k_push<R, true, false, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                         chg_next);
+  } else {
+    if (dens)
+      hipLaunchKernelGGL((k_push<R, false, true, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                         chg_next);
+    else
+      hipLaunchKernelGGL((k_push<R, false, false, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                         chg_next);
+  }
+}
+
 template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog, DevAccum *acc,
                  double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, hipStream_t st) {
   if (P.n <= 0) return;
-  const dim3 g(grid_for(P.n, kTile)), b(kBlock);
-  if (ef) {
-    if (dens)
-      hipLaunchKernelGGL((k_push<R, true, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
-    else
-      hipLaunchKernelGGL((k_push<R, true, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
-  } else {
-    if (dens)
-      hipLaunchKernelGGL((k_push<R, false, true>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
-    else
-      hipLaunchKernelGGL((k_push<R, false, false>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
-                         chg_next);
-  }
+  const bool ext = chg_cur || chg_next || (P.pmask & (P_HEAT | P_ELASTIC)) || P.nion > 1;
+  if (ext)
+    launch_push_v<R, true>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
+  else
+    launch_push_v<R, false>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
 }
 
 // ion charge per cell of the current state (the first step after init or set_state)

@@ -270,7 +270,7 @@ std::string validate(const ecr_params *p) {
   if (p->weight < 0.0 || p->lnL_ii < 0.0 || p->Ti0_eV < 0.0 || p->T_wall_eV < 0.0 || p->T_n_eV < 0.0)
     return "negative weight, Coulomb logarithm or temperature";
   if (p->ne_in_m3 < 0.0 || p->ne_out_m3 < 0.0) return "negative electron density";
-  if (p->process_mask >= 64u) return "process_mask has unknown bits";
+  if (p->process_mask >= 128u) return "process_mask has unknown bits";
   if ((p->process_mask & ECR_P_HEAT) &&
       !(p->Te_in_eV > 0.0 && p->Te_out_eV > 0.0 && isfinite(p->Te_in_eV) && isfinite(p->Te_out_eV)))
     return "the heating kick needs positive electron temperatures";
@@ -281,9 +281,13 @@ std::string validate(const ecr_params *p) {
     if (!(sp.mass_amu > 0.0)) return "species mass must be positive";
     if (sp.z_max < 0 || sp.z_max >= ECR_MAX_Q) return "z_max must be 0..31";
     if (sp.fraction < 0.0) return "species fraction must be >= 0";
-    if (sp.sigma_cx1_m2 < 0.0 || sp.n0_m3 < 0.0) return "negative cross-section or neutral density";
-    for (int q = 0; q < ECR_MAX_Q; ++q)
+    if (sp.sigma_cx1_m2 < 0.0 || sp.n0_m3 < 0.0 || sp.sigma_el1_m2 < 0.0)
+      return "negative cross-section or neutral density";
+    for (int q = 0; q < ECR_MAX_Q; ++q) {
       if (sp.k_ion_in_m3s[q] < 0.0 || sp.k_ion_out_m3s[q] < 0.0) return "negative ionisation rate";
+      for (int n = 0; n < ECR_MAX_NION - 1; ++n)
+        if (sp.k_ion_multi_in_m3s[n][q] < 0.0 || sp.k_ion_multi_out_m3s[n][q] < 0.0) return "negative ionisation rate";
+    }
     fsum += sp.fraction;
   }
   (void)fsum;
@@ -321,6 +325,7 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
   const double vcell = ((2.0 * p->R0_m / p->nx) * (2.0 * p->R0_m / p->ny)) * (p->L_m / p->nz);
   K.nfac = weight / vcell;
   K.Cs = p->lnL_ii * (kE * kE) * (kE * kE) / (4.0 * kPi * kEps0 * kEps0);
+  K.nion = 1;
   K.hx = 2.0 * p->R0_m / p->nx;
   K.hy = 2.0 * p->R0_m / p->ny;
   K.hz = p->L_m / p->nz;
@@ -341,6 +346,7 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
     K.sig_i[s] = sqrt(p->Ti0_eV * kE / M);
     K.decx[s] = 4.0 * p->dE_cx_eV * kE / M;
     K.ccx[s] = (sp.n0_m3 * sp.sigma_cx1_m2) * dt;
+    K.cel[s] = (sp.n0_m3 * sp.sigma_el1_m2) * dt;
     uint32_t ok = 0;
     for (int q = 0; q < kMaxQ; ++q) {
       T.qmh[s][q] = ((double)q * kE / M) * (dt * 0.5);
@@ -349,6 +355,16 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
         T.pion[s][0][q] = -expm1(-(p->ne_out_m3 * sp.k_ion_out_m3s[q]) * dt);
         T.kdt[s][1][q] = sp.k_ion_in_m3s[q] * dt;
         T.kdt[s][0][q] = sp.k_ion_out_m3s[q] * dt;
+      }
+      // Q -> Q+n, n >= 2, while Q + n stays within z_max
+      for (int n = 2; n <= kMaxN; ++n) {
+        if (q + n > sp.z_max) continue;
+        const double kin = sp.k_ion_multi_in_m3s[n - 2][q], kout = sp.k_ion_multi_out_m3s[n - 2][q];
+        T.pmul[s][1][n - 2][q] = -expm1(-(p->ne_in_m3 * kin) * dt);
+        T.pmul[s][0][n - 2][q] = -expm1(-(p->ne_out_m3 * kout) * dt);
+        T.kmul[s][1][n - 2][q] = kin * dt;
+        T.kmul[s][0][n - 2][q] = kout * dt;
+        if (kin > 0.0 || kout > 0.0) K.nion = K.nion > n ? K.nion : n;
       }
       if (q >= 1 && q <= sp.z_max && !((sp.cx_forbidden_mask >> q) & 1u)) ok |= 1u << q;
       if (heat)
@@ -396,9 +412,14 @@ double max_probability(const ecr_params *p, const KParams &K, const Tables &T) {
     const double vcap = 10.0 * sqrt(2.0 * Tm * kE / K.mass[s]);
     for (int q = 0; q <= p->species[s].z_max; ++q)
       for (int z = 0; z < 2; ++z) {
-        double pi = (p->process_mask & ECR_P_IONIZE) ? T.pion[s][z][q] : 0.0;
+        double pi = 0.0;
+        if (p->process_mask & ECR_P_IONIZE) {
+          pi = T.pion[s][z][q];
+          for (int n = 0; n < kMaxN - 1; ++n) pi += T.pmul[s][z][n][q];
+        }
         double pc = ((p->process_mask & ECR_P_CX) && ((K.cxok[s] >> q) & 1u)) ? K.ccx[s] * q * vcap : 0.0;
-        worst = fmax(worst, pi + pc);
+        double pe = (p->process_mask & ECR_P_ELASTIC) ? K.cel[s] * q * vcap : 0.0;
+        worst = fmax(worst, pi + pc + pe);
       }
   }
   return worst;

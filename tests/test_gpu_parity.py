@@ -31,20 +31,20 @@ def oracle(params):
     return OracleSim(params)
 
 
-def assert_state_close(a, b, params, ids=None, what=""):
+def assert_state_close(a, b, params, ids=None, what="", tol=XTOL):
     sel = slice(None) if ids is None else ids
     assert np.array_equal(a["q"][sel], b["q"]), f"{what}: charge states differ"
     for k in ("x", "y", "z"):
         d = np.abs(a[k][sel] - b[k]) / np.maximum(np.abs(b[k]), params["R0"])
-        assert d.max(initial=0) <= XTOL, f"{what}: {k} rel err {d.max()}"
+        assert d.max(initial=0) <= tol, f"{what}: {k} rel err {d.max()}"
     for k in ("vx", "vy", "vz"):
         d = np.abs(a[k][sel] - b[k]) / np.maximum(np.abs(b[k]), VSCALE)
-        assert d.max(initial=0) <= XTOL, f"{what}: {k} rel err {d.max()}"
+        assert d.max(initial=0) <= tol, f"{what}: {k} rel err {d.max()}"
     assert np.array_equal(a["birth"][sel], b["birth"]), f"{what}: birth steps differ"
 
 
 def assert_tallies_equal(tg, to, what=""):
-    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "fpt_n", "fpt_sum", "fpt_hist"):
+    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "fpt_n", "fpt_sum", "fpt_hist", "ionized_n", "elastic"):
         assert np.array_equal(tg[k], to[k]), f"{what}: tally {k} differs"
     for k in ("recycled", "anomalies", "steps"):
         assert tg[k] == to[k], f"{what}: {k} {tg[k]} vs {to[k]}"
@@ -125,6 +125,12 @@ CASES = {
     "heat": dict(mask=W.P_HEAT, v_ev=0.5),
     "heat_self_ne": dict(mask=W.P_HEAT, v_ev=0.5, self_ne=True, weight=4e12),
     "all_heat_self_ne": dict(mask=W.P_ALL | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True, weight=4e12),
+    # multiple ionisation (synthetic rates for n = 2..4) and elastic ion-atom scattering
+    "multi_ionize": dict(mask=W.P_IONIZE, v_ev=0.5, dt=3e-9, ext=True),
+    "elastic": dict(mask=W.P_ELASTIC, v_ev=50.0, n0=1e20, ext=True),
+    "all_extended": dict(mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, n0=5e18, ext=True),
+    "extended_self_ne": dict(mask=W.P_IONIZE | W.P_CX | W.P_ELASTIC, v_ev=50.0, n0=3e19, self_ne=True, weight=4e12,
+                             ext=True),
 }
 
 
@@ -137,6 +143,8 @@ def test_single_step_parity(case, seed):
                   self_ne=c.get("self_ne", False))
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
+    if c.get("ext"):
+        params["species"] = [W.with_extended_mcc(params["species"][0])]
     st = W.random_state(params, seed=100 + seed, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95),
                         birth_max=17 + seed)
     g, o = run_pair(params, st, 1, step0=17 + seed)
@@ -151,8 +159,12 @@ def test_single_step_parity(case, seed):
         assert (ev == W.EV_WALL).sum() > 20
     if case in ("ionize", "all", "ionize_self_ne", "all_self_ne", "all_heat_self_ne"):
         assert (ev == W.EV_IONIZE).sum() > 5
-    if case == "all_heat_self_ne":
+    if case in ("all_heat_self_ne", "all_extended"):
         assert (ev == W.EV_WALL).sum() > 20
+    if case in ("multi_ionize", "all_extended", "extended_self_ne"):
+        assert to["ionized_n"][0][1:].sum() > 0 and (ev == W.EV_IONIZE).sum() > 5
+    if case in ("elastic", "all_extended", "extended_self_ne"):
+        assert (ev == W.EV_ELASTIC).sum() > 10
     if case in ("heat", "heat_self_ne"):
         kicked = (b["vx"] != st["vx"]).sum()
         assert kicked > 2000, kicked
@@ -247,6 +259,35 @@ def test_multi_step_c1_self_consistent_electrons(heat):
     tg = g.tallies()
     assert_tallies_equal(tg, o.tallies(), "c1 self-ne")
     assert tg["ionized"].sum() > 100
+
+
+def test_multi_step_c1_extended_mcc():
+    # C1 with multiple ionisation, elastic ion-atom scattering and the heating
+    # kick on top of every default process, a denser neutral background, 120
+    # steps across two sorts.  Decisions stay bit for bit.  The scattering
+    # directions of charge exchange and elastic collisions go through sin and
+    # cos, whose GPU and CPU results may differ in the last bit; with a
+    # thousand such collisions here, Coulomb scattering carries those
+    # differences to other ions over the steps, so the multi-step bar for x
+    # and v is 1e-9 (one step from an identical state keeps 1e-12: the
+    # single-step cases above)
+    params = boosted(W.config("c1")[0], n0=2e19)
+    params["species"] = [W.with_extended_mcc(params["species"][0])]
+    params["process_mask"] = W.P_ALL | W.P_ELASTIC | W.P_HEAT
+    params["ne_in"] = 1e19
+    g = gpu_run(params, events=True)
+    g.init_ions()
+    o = oracle(params)
+    o.init_ions()
+    for chunk in (1, 49, 70):
+        g.step(chunk)
+        o.step(chunk)
+        a, b = g.get_state(), o.get_state()
+        assert np.array_equal(g.events(), o.events())
+        assert_state_close(a, b, params, what=f"c1 extended step {a['step']}", tol=1e-9)
+    tg, to = g.tallies(), o.tallies()
+    assert_tallies_equal(tg, to, "c1 extended")
+    assert to["elastic"].sum() > 15 and to["ionized_n"][0][1:].sum() > 5
 
 
 def test_deposit_fused_and_split_agree():

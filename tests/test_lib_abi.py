@@ -61,7 +61,7 @@ def test_footprint_and_parameter_checks():
         ecr.footprint(W.with_(p, process_mask=W.P_ALL | W.P_HEAT, Te_out_eV=0.0))
     assert ecr.footprint(W.with_(p, process_mask=W.P_ALL | W.P_HEAT)) == nb
     with pytest.raises(ecr.EcrError, match="process_mask"):
-        ecr.footprint(W.with_(p, process_mask=64))
+        ecr.footprint(W.with_(p, process_mask=128))
     P, _keep = ecr.make_params(p)
     P.abi_version = 99
     import ctypes as C
