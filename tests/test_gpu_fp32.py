@@ -81,6 +81,9 @@ CASES = {
     "cx": dict(mask=W.P_CX, v_ev=50.0, n0=1e20),
     "coulomb": dict(mask=W.P_COULOMB, v_ev=0.5),
     "all": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20),
+    # the optional physics (the push kernel's second variant) in binary32
+    "extended": dict(mask=W.P_ALL | W.P_ELASTIC, v_ev=20.0, n0=3e19, ext=True),
+    "self_ne_heat": dict(mask=W.P_ALL | W.P_HEAT, v_ev=20.0, self_ne=True, weight=4e12),
 }
 
 
@@ -88,8 +91,11 @@ CASES = {
 def test_fp32_single_step_against_oracle(case):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=3), n0=c.get("n0", 2e19))
-    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=7, weight=4e9)
+    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=7, weight=c.get("weight", 4e9),
+                  self_ne=c.get("self_ne", False))
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
+    if c.get("ext"):
+        params["species"] = [W.with_extended_mcc(params["species"][0])]
     st = to_f32_exact(W.random_state(params, seed=300, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95)))
     g = gpu_run(fp32(params), events=True)
     g.set_state(st, step=11)
@@ -100,9 +106,13 @@ def test_fp32_single_step_against_oracle(case):
     assert np.array_equal(g.events(), o.events()), "events differ"
     assert_close32(g.get_state(), o.get_state(), params, what=case)
     tg, to = g.tallies(), o.tallies()
-    for k in ("extracted", "wall", "ionized", "cx", "cx_products"):
+    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "ionized_n", "elastic"):
         assert np.array_equal(tg[k], to[k]), k
     ev = o.events()
+    if case == "extended":
+        assert (ev == W.EV_ELASTIC).sum() > 5 and to["ionized_n"][0][1:].sum() > 0
+    if case == "self_ne_heat":
+        assert (ev == W.EV_IONIZE).sum() > 20
     if case == "push_walls":
         assert (ev == W.EV_WALL).sum() > 20
     if case == "cx":
