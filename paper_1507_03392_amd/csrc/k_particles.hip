@@ -394,7 +394,9 @@ __device__ __forceinline__ void wave_segment_sum(int seg, double *v) {
 }
 
 // stage the deposit input of tile slot i (lane = slot layout)
-template <typename R>
+// NQ: the deposit mask is known to hold exactly the ion number and ion
+// charge fields (the default); the atom-field paths then compile away
+template <typename R, bool NQ>
 __device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int i, R x, R y, R z, int q, int mn[3],
                                           int mx[3]) {
   int ix, iy, iz;
@@ -402,7 +404,7 @@ __device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int
   cic_axis<R>(x, (R)P.R0, (R)P.idx, P.nx, ix, tx);
   cic_axis<R>(y, (R)P.R0, (R)P.idy, P.ny, iy, ty);
   cic_axis<R>(z, (R)P.hL, (R)P.idz, P.nz, iz, tz);
-  const uint32_t dm = P.dmask;
+  const uint32_t dm = NQ ? 3u : P.dmask;
   const bool on = (q >= 1) ? (dm & 3u) != 0 : (dm & 4u) != 0;
   const int k = kPad(i);
   st.t[0][k] = tx;
@@ -423,11 +425,12 @@ __device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int
 }
 
 // deposit a staged tile; every lane of the workgroup must call it
-template <typename R>
+template <typename R, bool NQ>
 __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restrict__ dens, DepShared<R> &sh,
                                                int *box, int mn[3], int mx[3]) {
   const int tid = threadIdx.x;
-  const uint32_t dm = P.dmask;
+  const uint32_t dm = NQ ? 3u : P.dmask;
+  constexpr int kFields = NQ ? 2 : 3;  // brick fields
   for (int off = 32; off > 0; off >>= 1)
     for (int d = 0; d < 3; ++d) {
       mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
@@ -459,9 +462,27 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
   __syncthreads();  // staging read: the brick may now reuse it
   if (!any) return;
   const int64_t nodes = (int64_t)bx * by * bz;
-  if (nodes <= kBrickNodes) {
+  // the lanes' last runs: one segmented sum per wavefront, then only the
+  // first lane of each segment (usually 2-3 per wavefront) flushes
+  auto flush_last = [&](DepRun &L, auto &&flush) {
+    const int lane = tid & 63;
+    const int key = (int)L.node;
+    const int kprev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || kprev != key;
+    const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+    if (dm & 1u) wave_segment_sum(seg, L.a);
+    if (dm & 2u) wave_segment_sum(seg, L.b);
+    if (dm & 4u) wave_segment_sum(seg, L.c);
+    if (head && key >= 0)
+      for (int k = 0; k < 8; ++k) {
+        if ((dm & 1u) && L.a[k] != 0.0) flush(key, 0, k, L.a[k]);
+        if ((dm & 2u) && L.b[k] != 0.0) flush(key, 1, k, L.b[k]);
+        if ((dm & 4u) && L.c[k] != 0.0) flush(key, 2, k, L.c[k]);
+      }
+  };
+  if (nodes <= (3 * kBrickNodes) / kFields) {
     const int nb = (int)nodes;
-    for (int i = tid; i < 3 * nb; i += kBlock) sh.brick[i] = 0.0;
+    for (int i = tid; i < kFields * nb; i += kBlock) sh.brick[i] = 0.0;
     __syncthreads();
     double *br = sh.brick;
     auto to_brick = [&](int64_t base, int f, int k, double v) {
@@ -473,24 +494,9 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
         D, dm,
         [&](int ix, int iy, int iz) -> int64_t { return (int64_t)((ix - x0) + bx * ((iy - y0) + by * (iz - z0))); },
         to_brick, L);
-    // the lanes' last runs: one segmented sum per wavefront, then only the
-    // first lane of each segment (usually 2-3 per wavefront) touches the brick
-    const int lane = tid & 63;
-    const int key = (int)L.node;
-    const int kprev = __shfl_up(key, 1, 64);
-    const bool head = lane == 0 || kprev != key;
-    const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
-    if (dm & 1u) wave_segment_sum(seg, L.a);
-    if (dm & 2u) wave_segment_sum(seg, L.b);
-    if (dm & 4u) wave_segment_sum(seg, L.c);
-    if (head && key >= 0)
-      for (int k = 0; k < 8; ++k) {
-        if ((dm & 1u) && L.a[k] != 0.0) to_brick(key, 0, k, L.a[k]);
-        if ((dm & 2u) && L.b[k] != 0.0) to_brick(key, 1, k, L.b[k]);
-        if ((dm & 4u) && L.c[k] != 0.0) to_brick(key, 2, k, L.c[k]);
-      }
+    flush_last(L, to_brick);
     __syncthreads();
-    for (int i = tid; i < 3 * nb; i += kBlock) {
+    for (int i = tid; i < kFields * nb; i += kBlock) {
       const double v = sh.brick[i];
       if (v != 0.0) {
         const int f = i / nb, li = i - f * nb;
@@ -500,16 +506,19 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
       }
     }
   } else {
+    // a tile whose nodes do not fit the brick (typically one that spans two
+    // planes of cells): runs go to HBM, still summed over the wavefront
+    // first, so that the dense cells at either end take a few atomics each
     const int nx1 = P.nx1, ny1 = P.ny1;
-    DepRun unused;
-    run_accumulate<R, false>(
-        D, dm,
-        [&](int ix, int iy, int iz) -> int64_t { return (int64_t)ix + (int64_t)nx1 * (iy + (int64_t)ny1 * iz); },
-        [&](int64_t base, int f, int k, double v) {
-          const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-          unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + base + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz)], v);
-        },
-        unused);
+    auto to_hbm = [&](int64_t base, int f, int k, double v) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+      unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + base + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz)], v);
+    };
+    DepRun L;
+    run_accumulate<R, true>(
+        D, dm, [&](int ix, int iy, int iz) -> int64_t { return (int64_t)ix + (int64_t)nx1 * (iy + (int64_t)ny1 * iz); },
+        to_hbm, L);
+    flush_last(L, to_hbm);
   }
 }
 
@@ -537,7 +546,9 @@ __device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t 
   if (head && cell != 0xffffffffu && q != 0u) atomicAdd(&chg[cell], q);
 }
 
-template <typename R, bool HAS_E, bool DEP, bool EXT>
+// DEP: 0 no deposit, 1 deposit with the run's mask, 2 deposit of exactly the
+// ion number and charge fields
+template <typename R, bool HAS_E, int DEP, bool EXT>
 __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                  const double *__restrict__ ef, uint8_t *__restrict__ evlog,
                                                  DevAccum *__restrict__ acc, double *__restrict__ dens,
@@ -576,15 +587,15 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
         ccell = cell_of<R>(P, x, y, z);
         cq = (uint32_t)Q;
       }
-      if (DEP) stage_cic<R>(P, sh.st, i, x, y, z, Q, mn, mx);
+      if (DEP) stage_cic<R, DEP == 2>(P, sh.st, i, x, y, z, Q, mn, mx);
     }
     if (EXT && chg_next) add_charge(chg_next, ccell, cq);  // all lanes together: run sums use shuffles
   }
-  if (DEP) deposit_staged<R>(P, dens, sh, box, mn, mx);
+  if (DEP) deposit_staged<R, DEP == 2>(P, dens, sh, box, mn, mx);
 }
 
 // standalone deposit (same tile code), for per-kernel timing
-template <typename R>
+template <typename R, bool NQ>
 __global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double *__restrict__ dens) {
   __shared__ DepShared<R> sh;
   __shared__ int box[6];
@@ -595,10 +606,10 @@ __global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double 
   for (int p = 0; p < kP; ++p) {
     const int i = threadIdx.x + p * kBlock;
     const int64_t j = base + i;
-    if (j < P.n) stage_cic<R>(P, sh.st, i, S.x[j], S.y[j], S.z[j], q_of(S.qs[j]), mn, mx);
+    if (j < P.n) stage_cic<R, NQ>(P, sh.st, i, S.x[j], S.y[j], S.z[j], q_of(S.qs[j]), mn, mx);
     else sh.st.q[kPad(i)] = 0xFF;
   }
-  deposit_staged<R>(P, dens, sh, box, mn, mx);
+  deposit_staged<R, NQ>(P, dens, sh, box, mn, mx);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,26 +766,30 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
   hipLaunchKernelGGL(k_init<R>, dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, S);
 }
 
+template <typename R, bool HAS_E, bool EXT>
+static void launch_push_e(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
+                          DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
+                          hipStream_t st) {
+  const dim3 g(grid_for(P.n, kTile)), b(kBlock);
+  if (!dens)
+    hipLaunchKernelGGL((k_push<R, HAS_E, 0, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                       chg_next);
+  else if ((P.dmask & 7u) == 3u)
+    hipLaunchKernelGGL((k_push<R, HAS_E, 2, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                       chg_next);
+  else
+    hipLaunchKernelGGL((k_push<R, HAS_E, 1, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                       chg_next);
+}
+
 template <typename R, bool EXT>
 static void launch_push_v(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
                           DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
                           hipStream_t st) {
-  const dim3 g(grid_for(P.n, kTile)), b(kBlock);
-  if (ef) {
-    if (dens)
-      hipLaunchKernelGGL((k_push<R, true, true, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
-                         chg_next);
-    else
-      hipLaunchKernelGGL((k_push<R, true, false, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
-                         chg_next);
-  } else {
-    if (dens)
-      hipLaunchKernelGGL((k_push<R, false, true, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
-                         chg_next);
-    else
-      hipLaunchKernelGGL((k_push<R, false, false, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
-                         chg_next);
-  }
+  if (ef)
+    launch_push_e<R, true, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
+  else
+    launch_push_e<R, false, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
 }
 
 template <typename R>
@@ -815,7 +830,10 @@ template void launch_charge_grid<float>(const KParams &, Soa<float>, uint32_t *,
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {
   if (P.n <= 0) return;
-  hipLaunchKernelGGL(k_deposit<R>, dim3(grid_for(P.n, kTile)), dim3(kBlock), 0, st, P, S, dens);
+  if ((P.dmask & 7u) == 3u)
+    hipLaunchKernelGGL((k_deposit<R, true>), dim3(grid_for(P.n, kTile)), dim3(kBlock), 0, st, P, S, dens);
+  else
+    hipLaunchKernelGGL((k_deposit<R, false>), dim3(grid_for(P.n, kTile)), dim3(kBlock), 0, st, P, S, dens);
 }
 
 template <typename R>

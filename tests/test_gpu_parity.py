@@ -116,6 +116,8 @@ CASES = {
     "coulomb": dict(mask=W.P_COULOMB, v_ev=0.5),
     "all": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20),
     "all_walls": dict(mask=W.P_ALL, v_ev=200.0, dt=5e-9, rf=0.9995),
+    # the default deposit fields only (ion number and charge: the kernels' specialised path)
+    "all_nq": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20, dm=3),
     # electrons = ion charge density per cell (Sec. II); a heavy weight so
     # that ionisation fires in one step
     "ionize_self_ne": dict(mask=W.P_IONIZE, v_ev=0.5, self_ne=True, weight=4e12),
@@ -139,7 +141,7 @@ CASES = {
 def test_single_step_parity(case, seed):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
-    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=15, weight=c.get("weight", 4e9),
+    params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=c.get("dm", 15), weight=c.get("weight", 4e9),
                   self_ne=c.get("self_ne", False))
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
