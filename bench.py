@@ -269,7 +269,10 @@ def main():
     alg = (ALG_BYTES_FP32 if fp32 else ALG_BYTES_FP64)[dom] * n
     avg_s = ms * 1e-3 / max(1, launches)
     achieved = alg / avg_s / 1e9
-    traffic = measured_traffic(args.workload, dom)
+    # the counters were taken on the default step (fixed electron background,
+    # no optional physics, fused deposit): another configuration runs other code
+    default_step = not (args.self_ne or args.heat or args.split)
+    traffic = measured_traffic(args.workload, dom) if default_step else None
 
     drift = None
     if fp32 and not args.no_drift:

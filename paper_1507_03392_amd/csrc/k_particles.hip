@@ -287,9 +287,11 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
 // and read back transposed, so that lane l owns the kP consecutive slots
 // kP*l .. kP*l+kP-1.  Consecutive slots share a cell almost always, so the
 // lane sums their weights in registers and flushes a run only when the cell
-// changes, into an LDS brick spanning the tile's nodes; the brick goes to HBM
-// with one FP64 atomic per touched node.  A tile whose nodes do not fit the
-// brick flushes its runs to HBM directly.
+// changes, into an LDS brick spanning the tile's nodes.  The lanes' last runs
+// go through a segmented sum over the wavefront, so only the first lane of
+// each run of equal cells touches the brick; the brick goes to HBM with one
+// FP64 atomic per touched node.  A tile whose nodes do not fit the brick
+// (one spanning two planes of cells) sends the same wavefront sums to HBM.
 // ---------------------------------------------------------------------------
 constexpr int kPad(int i) { return i + (i >> 2); }  // one pad slot every 4: fewer LDS bank conflicts
 constexpr int kStage = kPad(kTile);
