@@ -8,6 +8,8 @@
 // of kP x 256 slots.  Slots are in cell order (sorted every sort_every steps),
 // which the deposit exploits (see deposit_staged): it takes the deposit from
 // 16 contended global atomics per particle to a few per workgroup.
+#include <type_traits>
+
 #include "ecr_kernels.hpp"
 
 namespace ecr {
@@ -296,18 +298,40 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
 constexpr int kPad(int i) { return i + (i >> 2); }  // one pad slot every 4: fewer LDS bank conflicts
 constexpr int kStage = kPad(kTile);
 
+// unpadded: the push writes one slot per lane (consecutive addresses), and
+// lane l reads its kP consecutive slots back with wide loads, both free of
+// bank conflicts; 31 KB in binary64, so that five workgroups share a CU
 template <typename R>
-struct DepStage {
-  R t[3][kStage];
-  uint16_t c[3][kStage];
-  uint8_t q[kStage];  // charge, or 0xFF: nothing to deposit
+struct alignas(16) DepStage {
+  R t[3][kTile];
+  uint16_t c[3][kTile];
+  uint8_t q[kTile];  // charge, or 0xFF: nothing to deposit
 };
+
+// the brick reuses the staging memory: as many doubles as binary64 staging holds
+constexpr int kDepBrick = (int)(sizeof(DepStage<double>) / sizeof(double));
 
 template <typename R>
 union DepShared {
   DepStage<R> st;
-  double brick[3 * kBrickNodes];
+  double brick[kDepBrick];
 };
+
+// kP consecutive staged values of lane l (16-byte aligned: kP = 4)
+__device__ __forceinline__ void lds_load4(const double *p, double o[4]) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+__device__ __forceinline__ void lds_load4(const float *p, float o[4]) {
+  const float4 a = *reinterpret_cast<const float4 *>(p);
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = a.z;
+  o[3] = a.w;
+}
 
 template <typename R>
 struct DepIn {
@@ -408,7 +432,7 @@ __device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int
   cic_axis<R>(z, (R)P.hL, (R)P.idz, P.nz, iz, tz);
   const uint32_t dm = NQ ? 3u : P.dmask;
   const bool on = (q >= 1) ? (dm & 3u) != 0 : (dm & 4u) != 0;
-  const int k = kPad(i);
+  const int k = i;
   st.t[0][k] = tx;
   st.t[1][k] = ty;
   st.t[2][k] = tz;
@@ -444,19 +468,26 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
       atomicMax(&box[3 + d], mx[d]);
     }
   __syncthreads();  // staging and box complete
+  static_assert(kP == 4, "the wide staging reads take four slots");
   DepIn<R> D;
+  {
+    const int k0 = tid * kP;
+    lds_load4(&sh.st.t[0][k0], D.tx);
+    lds_load4(&sh.st.t[1][k0], D.ty);
+    lds_load4(&sh.st.t[2][k0], D.tz);
+    const uint32_t q4 = *reinterpret_cast<const uint32_t *>(&sh.st.q[k0]);
+    uint2 c4[3];
+    for (int a = 0; a < 3; ++a) c4[a] = *reinterpret_cast<const uint2 *>(&sh.st.c[a][k0]);
 #pragma unroll
-  for (int p = 0; p < kP; ++p) {
-    const int k = kPad(tid * kP + p);
-    const uint8_t q = sh.st.q[k];
-    D.on[p] = q != 0xFF;
-    D.q[p] = q;
-    D.tx[p] = sh.st.t[0][k];
-    D.ty[p] = sh.st.t[1][k];
-    D.tz[p] = sh.st.t[2][k];
-    D.ix[p] = sh.st.c[0][k];
-    D.iy[p] = sh.st.c[1][k];
-    D.iz[p] = sh.st.c[2][k];
+    for (int p = 0; p < kP; ++p) {
+      const uint8_t q = (uint8_t)(q4 >> (8 * p));
+      D.on[p] = q != 0xFF;
+      D.q[p] = q;
+      const int sh16 = 16 * (p & 1);
+      D.ix[p] = (int)(((p < 2 ? c4[0].x : c4[0].y) >> sh16) & 0xffffu);
+      D.iy[p] = (int)(((p < 2 ? c4[1].x : c4[1].y) >> sh16) & 0xffffu);
+      D.iz[p] = (int)(((p < 2 ? c4[2].x : c4[2].y) >> sh16) & 0xffffu);
+    }
   }
   const int x0 = box[0], y0 = box[1], z0 = box[2];
   const bool any = box[3] >= 0;
@@ -482,7 +513,7 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
         if ((dm & 4u) && L.c[k] != 0.0) flush(key, 2, k, L.c[k]);
       }
   };
-  if (nodes <= (3 * kBrickNodes) / kFields) {
+  if (nodes <= kDepBrick / kFields) {
     const int nb = (int)nodes;
     for (int i = tid; i < kFields * nb; i += kBlock) sh.brick[i] = 0.0;
     __syncthreads();
@@ -551,11 +582,10 @@ __device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t 
 // DEP: 0 no deposit, 1 deposit with the run's mask, 2 deposit of exactly the
 // ion number and charge fields
 template <typename R, bool HAS_E, int DEP, bool EXT>
-__global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
-                                                 const double *__restrict__ ef, uint8_t *__restrict__ evlog,
-                                                 DevAccum *__restrict__ acc, double *__restrict__ dens,
-                                                 StepArg sa, const uint32_t *__restrict__ chg_cur,
-                                                 uint32_t *__restrict__ chg_next) {
+__device__ __forceinline__ void push_tile(const KParams &P, const Tables *__restrict__ T, Soa<R> S,
+                                          const double *__restrict__ ef, uint8_t *__restrict__ evlog,
+                                          DevAccum *__restrict__ acc, double *__restrict__ dens, StepArg sa,
+                                          const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next) {
   __shared__ DepShared<R> sh;
   const uint32_t step = sa.get();
   __shared__ int box[6];
@@ -568,7 +598,7 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
     const int64_t j = base + i;
     uint32_t ccell = 0xffffffffu, cq = 0u;  // this lane's contribution to the next charge grid
     if (j >= P.n) {
-      if (DEP) sh.st.q[kPad(i)] = 0xFF;
+      if (DEP) sh.st.q[i] = 0xFF;
     } else {
       R x = S.x[j], y = S.y[j], z = S.z[j];
       R vx = S.vx[j], vy = S.vy[j], vz = S.vz[j];
@@ -596,6 +626,26 @@ __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__rest
   if (DEP) deposit_staged<R, DEP == 2>(P, dens, sh, box, mn, mx);
 }
 
+template <typename R, bool HAS_E, int DEP, bool EXT>
+__global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
+                                                 const double *__restrict__ ef, uint8_t *__restrict__ evlog,
+                                                 DevAccum *__restrict__ acc, double *__restrict__ dens,
+                                                 StepArg sa, const uint32_t *__restrict__ chg_cur,
+                                                 uint32_t *__restrict__ chg_next) {
+  push_tile<R, HAS_E, DEP, EXT>(P, T, S, ef, evlog, acc, dens, sa, chg_cur, chg_next);
+}
+
+// the default binary64 step (no E field, ion number and charge deposit, no
+// optional physics) held at five waves per SIMD: its 31 KB of LDS lets five
+// workgroups share a CU, and the registers fit with a few spills on cold paths
+// (measured 68 -> 65 us per launch at 2M ions)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+k_push_lean(KParams P, const Tables *__restrict__ T, Soa<double> S, const double *__restrict__ ef,
+            uint8_t *__restrict__ evlog, DevAccum *__restrict__ acc, double *__restrict__ dens, StepArg sa,
+            const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next) {
+  push_tile<double, false, 2, false>(P, T, S, ef, evlog, acc, dens, sa, chg_cur, chg_next);
+}
+
 // standalone deposit (same tile code), for per-kernel timing
 template <typename R, bool NQ>
 __global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double *__restrict__ dens) {
@@ -609,7 +659,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double 
     const int i = threadIdx.x + p * kBlock;
     const int64_t j = base + i;
     if (j < P.n) stage_cic<R, NQ>(P, sh.st, i, S.x[j], S.y[j], S.z[j], q_of(S.qs[j]), mn, mx);
-    else sh.st.q[kPad(i)] = 0xFF;
+    else sh.st.q[i] = 0xFF;
   }
   deposit_staged<R, NQ>(P, dens, sh, box, mn, mx);
 }
@@ -776,9 +826,13 @@ static void launch_push_e(const KParams &P, const Tables *T, Soa<R> S, const dou
   if (!dens)
     hipLaunchKernelGGL((k_push<R, HAS_E, 0, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
                        chg_next);
-  else if ((P.dmask & 7u) == 3u)
-    hipLaunchKernelGGL((k_push<R, HAS_E, 2, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
-                       chg_next);
+  else if ((P.dmask & 7u) == 3u) {
+    if constexpr (std::is_same<R, double>::value && !HAS_E && !EXT)
+      hipLaunchKernelGGL(k_push_lean, g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
+    else
+      hipLaunchKernelGGL((k_push<R, HAS_E, 2, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+                         chg_next);
+  }
   else
     hipLaunchKernelGGL((k_push<R, HAS_E, 1, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
                        chg_next);
