@@ -312,6 +312,38 @@ def test_deposit_fused_and_split_agree():
             assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
 
 
+@pytest.mark.parametrize("dm", [3, 15])
+def test_deposit_tiles_that_overflow_the_brick(dm):
+    # 6000 ions, cell-sorted: dense clusters at opposite corners of the mesh
+    # interleaved so that every 1024-slot tile spans the whole mesh (far more
+    # nodes than the LDS brick holds), plus one tile of a single dense cell;
+    # the deposit of both kinds of tile against the oracle's brute-force sum
+    params = W.base_params(6000, 16, 16, 32, seed=5)
+    params.update(process_mask=W.P_DEPOSIT, deposit_mask=dm)
+    rng = np.random.default_rng(8)
+    h = 2 * params["R0"] / 16, params["L"] / 32
+    n = 6000
+    corner = np.where(np.arange(n) % 2 == 0, 0, 1)
+    corner[5000:] = 2  # one dense cell in the middle: a tile that fits the brick
+    cx = np.select([corner == 0, corner == 1], [-params["R0"] + 0.5 * h[0], params["R0"] - 0.5 * h[0]], 0.2 * h[0])
+    cz = np.select([corner == 0, corner == 1], [-params["L"] / 2 + 0.5 * h[1], params["L"] / 2 - 0.5 * h[1]], 0.3 * h[1])
+    st = dict(x=cx + rng.uniform(-0.4, 0.4, n) * h[0], y=rng.uniform(-0.4, 0.4, n) * h[0],
+              z=cz + rng.uniform(-0.4, 0.4, n) * h[1], vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n),
+              q=rng.integers(0, 9, n).astype(np.uint8))
+    # slot order = the given cells' order: the alternating corners stay interleaved
+    cells = np.full(n, 7, dtype=np.uint32)
+    g, o = run_pair(params, st, 2, step0=3, cell=cells)
+    for f in (W.F_ION_N, W.F_ION_Q, W.F_ATOM_N):
+        dg, sg = g.density(f)
+        do, so = o.density(f)
+        assert sg == so == 2
+        assert np.abs(dg - do).max() <= 1e-12 * max(1.0, np.abs(do).max()), f
+        if (dm >> f) & 1:
+            assert do.max() > 100
+        else:
+            assert not dg.any()
+
+
 def test_given_cells_and_resume_bitwise():
     params = boosted(W.base_params(30_000, 16, 16, 32, seed=4))
     params.update(dt=2e-9)
