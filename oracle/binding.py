@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("dE_cx_eV", C.c_double), ("lnL", C.c_double), ("weight", C.c_double),
                 ("efield", C.POINTER(C.c_double)), ("n_species", C.c_int32),
                 ("sp", Species * MAXS), ("self_ne", C.c_int32),
-                ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double)]
+                ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double),
+                ("bfield", C.POINTER(C.c_double))]
 
 
 class Tallies(C.Structure):
@@ -111,10 +112,13 @@ def make_params(p):
     for k in ("R0", "L", "r_ap", "inlet_x", "inlet_y", "B0", "mirror_k", "BH", "zone_a", "zone_c",
               "ne_in", "ne_out", "Ti0_eV", "T_wall_eV", "T_n_eV", "dE_cx_eV", "lnL", "weight"):
         setattr(P, k, float(p[k]))
-    keep = None
+    keep = []
     if p.get("efield") is not None:
-        keep = np.ascontiguousarray(p["efield"], dtype=np.float64)
-        P.efield = keep.ctypes.data_as(C.POINTER(C.c_double))
+        keep.append(np.ascontiguousarray(p["efield"], dtype=np.float64))
+        P.efield = keep[-1].ctypes.data_as(C.POINTER(C.c_double))
+    if p.get("bfield") is not None:
+        keep.append(np.ascontiguousarray(p["bfield"], dtype=np.float64))
+        P.bfield = keep[-1].ctypes.data_as(C.POINTER(C.c_double))
     P.n_species = len(p["species"])
     for i, s in enumerate(p["species"]):
         S = P.sp[i]

@@ -160,9 +160,9 @@ static void field_B(const orc_sim *s, double x, double y, double z, double *bx, 
   *bz = (s->p.B0 + s->c1 * zz) - s->c4 * (xx + yy);
 }
 
-void orc_field(const orc_sim *s, double x, double y, double z, double B[3]) {
-  field_B(s, x, y, z, &B[0], &B[1], &B[2]);
-}
+static void magnetic(const orc_sim *s, double x, double y, double z, double B[3]);
+
+void orc_field(const orc_sim *s, double x, double y, double z, double B[3]) { magnetic(s, x, y, z, B); }
 
 /* cell-in-cell index helpers on the box [-R0,R0]^2 x [-L/2,L/2] */
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -182,8 +182,8 @@ static void cic_axis(double pos, double origin, double inv_h, int ncell, int *i,
   *t = f - (double)k;
 }
 
-/* trilinear interpolation of the node E field at (x,y,z) */
-static void gather_E(const orc_sim *s, double x, double y, double z, double E[3]) {
+/* trilinear interpolation of a node vector field [3][nnode] at (x,y,z) */
+static void gather_grid(const orc_sim *s, const double *grid, double x, double y, double z, double out[3]) {
   int ix, iy, iz;
   double tx, ty, tz;
   cic_axis(x, s->p.R0, s->idx, s->p.nx, &ix, &tx);
@@ -191,7 +191,7 @@ static void gather_E(const orc_sim *s, double x, double y, double z, double E[3]
   cic_axis(z, s->hL, s->idz, s->p.nz, &iz, &tz);
   double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
   for (int c = 0; c < 3; c++) {
-    const double *F = s->p.efield + (int64_t)c * s->nnode;
+    const double *F = grid + (int64_t)c * s->nnode;
     double acc = 0.0;
     for (int dz = 0; dz < 2; dz++)
       for (int dy = 0; dy < 2; dy++)
@@ -199,8 +199,20 @@ static void gather_E(const orc_sim *s, double x, double y, double z, double E[3]
           int64_t node = (int64_t)(ix + dx) + (int64_t)s->nx1 * ((iy + dy) + (int64_t)s->ny1 * (iz + dz));
           acc = acc + ((wx[dx] * wy[dy]) * wz[dz]) * F[node];
         }
-    E[c] = acc;
+    out[c] = acc;
   }
+}
+
+static void gather_E(const orc_sim *s, double x, double y, double z, double E[3]) {
+  gather_grid(s, s->p.efield, x, y, z, E);
+}
+
+/* the run's magnetic field: a given node map (a field-solver output such as
+ * the paper's Superfish maps), interpolated trilinearly, else the analytic
+ * field above */
+static void magnetic(const orc_sim *s, double x, double y, double z, double B[3]) {
+  if (s->p.bfield) gather_grid(s, s->p.bfield, x, y, z, B);
+  else field_B(s, x, y, z, &B[0], &B[1], &B[2]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -210,8 +222,9 @@ static void gather_E(const orc_sim *s, double x, double y, double z, double E[3]
 /* ------------------------------------------------------------------------ */
 static void boris(const orc_sim *s, double h, const double *E, double *x, double *y, double *z,
                   double *vx, double *vy, double *vz) {
-  double bx, by, bz;
-  field_B(s, *x, *y, *z, &bx, &by, &bz);
+  double B[3];
+  magnetic(s, *x, *y, *z, B);
+  double bx = B[0], by = B[1], bz = B[2];
   double vmx = *vx, vmy = *vy, vmz = *vz;
   if (E) {
     vmx = vmx + h * E[0];

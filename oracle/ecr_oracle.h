@@ -81,6 +81,8 @@ typedef struct {
   int32_t self_ne;            /* 1: electron density = ion charge density of the cell (Sec. II) */
   double lnL_ei;              /* electron-ion Coulomb logarithm (the paper: 17) */
   double Te_in_eV, Te_out_eV; /* electron temperature inside (warm) and outside (cold) the zone */
+  const double *bfield;       /* [3][(nx+1)(ny+1)(nz+1)] node magnetic field, T, interpolated trilinearly
+                                 in place of the analytic field; or NULL */
 } orc_params;
 
 typedef struct {
