@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ECR_ABI_VERSION 4u
+#define ECR_ABI_VERSION 5u
 #define ECR_MAX_SPECIES 4
 #define ECR_MAX_Q 32          /* charge-state slots per species: Q = 0..31 */
 #define ECR_MAX_NION 4        /* electrons one ionisation may remove: Q -> Q+n, n = 1..4 */
@@ -148,6 +148,11 @@ typedef struct {
   double Te_in_eV, Te_out_eV;         /* electron temperature inside / outside the zone (ECR_P_HEAT; > 0) */
   double weight;                      /* real ions per macro-particle; 0: n_e,in V_zone / N */
   const double *efield_nodes;         /* host, [3][(nx+1)(ny+1)(nz+1)] V/m node field, or NULL (E = 0) */
+  const double *bfield_nodes;         /* host, [3][(nx+1)(ny+1)(nz+1)] T node magnetic field (a field-solver map,
+                                         as the paper's Superfish maps), node index ix + (nx+1)(iy + (ny+1) iz),
+                                         interpolated trilinearly at the particle in place of the analytic
+                                         B0/mirror_k/BH field, and at the cell centre for the heating kick;
+                                         copied into the arena at create; or NULL (analytic field) */
   ecr_species species[ECR_MAX_SPECIES];
 } ecr_params;
 

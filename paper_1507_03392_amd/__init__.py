@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libecrpic.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAXS, MAXQ = 4, 32
 MAXN = 4  # electrons one ionisation may remove
 FPT_BINS = 32
@@ -62,6 +62,7 @@ class Params(C.Structure):
                 ("T_n_eV", C.c_double), ("dE_cx_eV", C.c_double), ("lnL_ii", C.c_double),
                 ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double),
                 ("weight", C.c_double), ("efield_nodes", C.POINTER(C.c_double)),
+                ("bfield_nodes", C.POINTER(C.c_double)),
                 ("species", Species * MAXS)]
 
 
@@ -151,9 +152,14 @@ def make_params(p, events=False, split=False):
     P.Te_in_eV = float(p.get("Te_in_eV", 0.0))
     P.Te_out_eV = float(p.get("Te_out_eV", 0.0))
     keep = None
+    if p.get("efield") is not None or p.get("bfield") is not None:
+        keep = []
     if p.get("efield") is not None:
-        keep = np.ascontiguousarray(p["efield"], dtype=np.float64)
-        P.efield_nodes = keep.ctypes.data_as(C.POINTER(C.c_double))
+        keep.append(np.ascontiguousarray(p["efield"], dtype=np.float64))
+        P.efield_nodes = keep[-1].ctypes.data_as(C.POINTER(C.c_double))
+    if p.get("bfield") is not None:
+        keep.append(np.ascontiguousarray(p["bfield"], dtype=np.float64))
+        P.bfield_nodes = keep[-1].ctypes.data_as(C.POINTER(C.c_double))
     for i, s in enumerate(p["species"]):
         S = P.species[i]
         S.mass_amu = s["mass_amu"]

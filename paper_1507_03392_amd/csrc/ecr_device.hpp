@@ -49,6 +49,7 @@ struct KParams {
   // heating kick, [outside, inside] the zone: fixed-background n_e, and
   // 2.38e-6 sqrt(T_e) (the electron Larmor radius times |B|)
   double ne_zone[2], rl_zone[2];
+  const double *bmap;  // device [3][nnode] node magnetic field (T), or null: the analytic field
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
   double cel[kMaxS];     // n0 sigma_el1 dt (elastic ion-atom scattering)
   int32_t nion;          // ionisation channels with a nonzero rate: 1 .. kMaxN
@@ -187,7 +188,8 @@ __device__ __forceinline__ uint32_t cell_of(const KParams &P, R x, R y, R z) {
   return (uint32_t)ix + (uint32_t)P.nx * ((uint32_t)iy + (uint32_t)P.ny * (uint32_t)iz);
 }
 
-// trilinear gather of the node electric field [3][nnode]
+// trilinear gather of a node vector field [3][nnode] (the electric field,
+// or a magnetic field map)
 template <typename R>
 __device__ __forceinline__ void gather_E(const KParams &P, const double *__restrict__ ef, R x, R y, R z,
                                          R E[3]) {
@@ -214,13 +216,23 @@ __device__ __forceinline__ void gather_E(const KParams &P, const double *__restr
 // Boris push: v- = v + hE; t = hB; s = 2t/(1 + t.t); v' = v- + v- x t;
 // v+ = v- + v' x s; v = v+ + hE; x += v dt with h = (Q e/M) dt/2.
 // ---------------------------------------------------------------------------
-template <typename R, bool HAS_E>
+// FLD: bit 0 an electric field grid, bit 1 a magnetic field map (P.bmap)
+// in place of the analytic field
+template <typename R, int FLD>
 __device__ __forceinline__ void boris(const KParams &P, R h, const R E[3], R &x, R &y, R &z, R &vx, R &vy,
                                       R &vz) {
   R bx, by, bz;
-  field_B<R>(P, x, y, z, bx, by, bz);
+  if (FLD & 2) {
+    R B[3];
+    gather_E<R>(P, P.bmap, x, y, z, B);
+    bx = B[0];
+    by = B[1];
+    bz = B[2];
+  } else {
+    field_B<R>(P, x, y, z, bx, by, bz);
+  }
   R vmx = vx, vmy = vy, vmz = vz;
-  if (HAS_E) {
+  if (FLD & 1) {
     vmx = vmx + h * E[0];
     vmy = vmy + h * E[1];
     vmz = vmz + h * E[2];
@@ -235,7 +247,7 @@ __device__ __forceinline__ void boris(const KParams &P, R h, const R E[3], R &x,
   R nvx = vmx + (vpy * sz - vpz * sy);
   R nvy = vmy + (vpz * sx - vpx * sz);
   R nvz = vmz + (vpx * sy - vpy * sx);
-  if (HAS_E) {
+  if (FLD & 1) {
     nvx = nvx + h * E[0];
     nvy = nvy + h * E[1];
     nvz = nvz + h * E[2];

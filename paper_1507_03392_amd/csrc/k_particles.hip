@@ -96,8 +96,17 @@ __device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__rest
     ne = nat(ix, iy);
     if (!(ne > 0.0)) return;
     double bx, by, bz;
-    field_B<double>(P, -P.R0 + ((double)ix + 0.5) * P.hx, -P.R0 + ((double)iy + 0.5) * P.hy,
-                    -P.hL + ((double)iz + 0.5) * P.hz, bx, by, bz);
+    const double xc = -P.R0 + ((double)ix + 0.5) * P.hx, yc = -P.R0 + ((double)iy + 0.5) * P.hy;
+    const double zc = -P.hL + ((double)iz + 0.5) * P.hz;
+    if (P.bmap) {
+      double B[3];
+      gather_E<double>(P, P.bmap, xc, yc, zc, B);
+      bx = B[0];
+      by = B[1];
+      bz = B[2];
+    } else {
+      field_B<double>(P, xc, yc, zc, bx, by, bz);
+    }
     const double bmag = sqrt((bx * bx + by * by) + bz * bz);
     if (bmag > 0.0) {
       const double rl = P.rl_zone[zone] / (bmag * P.hx);
@@ -141,7 +150,7 @@ __device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__rest
 // electrons, heating kick, multiple ionisation, elastic scattering); the
 // default step runs the lean variant, which leaves those paths out of the
 // code altogether
-template <typename R, bool HAS_E, bool EXT>
+template <typename R, int FLD, bool EXT>
 __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
                                            const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
                                            uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz,
@@ -152,8 +161,8 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     const R x0 = x, y0 = y, z0 = z;
     const R h = (R)T->qmh[s][Q];
     R E[3] = {(R)0, (R)0, (R)0};
-    if (HAS_E) gather_E<R>(P, ef, x, y, z, E);
-    boris<R, HAS_E>(P, h, E, x, y, z, vx, vy, vz);
+    if (FLD & 1) gather_E<R>(P, ef, x, y, z, E);
+    boris<R, FLD>(P, h, E, x, y, z, vx, vy, vz);
     R f;
     const int kind = segment_exit<R>(P, x0, y0, z0, x, y, z, f);
     if (kind != X_NONE) {
@@ -581,7 +590,7 @@ __device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t 
 
 // DEP: 0 no deposit, 1 deposit with the run's mask, 2 deposit of exactly the
 // ion number and charge fields
-template <typename R, bool HAS_E, int DEP, bool EXT>
+template <typename R, int FLD, int DEP, bool EXT>
 __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__restrict__ T, Soa<R> S,
                                           const double *__restrict__ ef, uint8_t *__restrict__ evlog,
                                           DevAccum *__restrict__ acc, double *__restrict__ dens, StepArg sa,
@@ -606,7 +615,7 @@ __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__rest
       const uint32_t id = S.pid[j];
       int Q = q_of(qs0);
       const int s = sp_of(qs0);
-      const uint8_t ev = advance<R, HAS_E, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur);
+      const uint8_t ev = advance<R, FLD, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur);
       S.x[j] = x;
       S.y[j] = y;
       S.z[j] = z;
@@ -626,13 +635,13 @@ __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__rest
   if (DEP) deposit_staged<R, DEP == 2>(P, dens, sh, box, mn, mx);
 }
 
-template <typename R, bool HAS_E, int DEP, bool EXT>
+template <typename R, int FLD, int DEP, bool EXT>
 __global__ void __launch_bounds__(kBlock) k_push(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                                  const double *__restrict__ ef, uint8_t *__restrict__ evlog,
                                                  DevAccum *__restrict__ acc, double *__restrict__ dens,
                                                  StepArg sa, const uint32_t *__restrict__ chg_cur,
                                                  uint32_t *__restrict__ chg_next) {
-  push_tile<R, HAS_E, DEP, EXT>(P, T, S, ef, evlog, acc, dens, sa, chg_cur, chg_next);
+  push_tile<R, FLD, DEP, EXT>(P, T, S, ef, evlog, acc, dens, sa, chg_cur, chg_next);
 }
 
 // the default binary64 step (no E field, ion number and charge deposit, no
@@ -643,7 +652,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
 k_push_lean(KParams P, const Tables *__restrict__ T, Soa<double> S, const double *__restrict__ ef,
             uint8_t *__restrict__ evlog, DevAccum *__restrict__ acc, double *__restrict__ dens, StepArg sa,
             const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next) {
-  push_tile<double, false, 2, false>(P, T, S, ef, evlog, acc, dens, sa, chg_cur, chg_next);
+  push_tile<double, 0, 2, false>(P, T, S, ef, evlog, acc, dens, sa, chg_cur, chg_next);
 }
 
 // standalone deposit (same tile code), for per-kernel timing
@@ -818,34 +827,36 @@ void launch_init(const KParams &P, Soa<R> S, hipStream_t st) {
   hipLaunchKernelGGL(k_init<R>, dim3(grid_for(P.n, 256)), dim3(256), 0, st, P, S);
 }
 
-template <typename R, bool HAS_E, bool EXT>
+template <typename R, int FLD, bool EXT>
 static void launch_push_e(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
                           DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
                           hipStream_t st) {
   const dim3 g(grid_for(P.n, kTile)), b(kBlock);
   if (!dens)
-    hipLaunchKernelGGL((k_push<R, HAS_E, 0, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+    hipLaunchKernelGGL((k_push<R, FLD, 0, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
                        chg_next);
   else if ((P.dmask & 7u) == 3u) {
-    if constexpr (std::is_same<R, double>::value && !HAS_E && !EXT)
+    if constexpr (std::is_same<R, double>::value && FLD == 0 && !EXT)
       hipLaunchKernelGGL(k_push_lean, g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next);
     else
-      hipLaunchKernelGGL((k_push<R, HAS_E, 2, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+      hipLaunchKernelGGL((k_push<R, FLD, 2, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
                          chg_next);
-  }
-  else
-    hipLaunchKernelGGL((k_push<R, HAS_E, 1, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
+  } else {
+    hipLaunchKernelGGL((k_push<R, FLD, 1, EXT>), g, b, 0, st, P, T, S, ef, evlog, acc, dens, step, chg_cur,
                        chg_next);
+  }
 }
 
 template <typename R, bool EXT>
 static void launch_push_v(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
                           DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
                           hipStream_t st) {
-  if (ef)
-    launch_push_e<R, true, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
-  else
-    launch_push_e<R, false, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
+  switch ((ef ? 1 : 0) | (P.bmap ? 2 : 0)) {
+    case 0: launch_push_e<R, 0, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st); break;
+    case 1: launch_push_e<R, 1, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st); break;
+    case 2: launch_push_e<R, 2, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st); break;
+    default: launch_push_e<R, 3, EXT>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st); break;
+  }
 }
 
 template <typename R>

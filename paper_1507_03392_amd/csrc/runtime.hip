@@ -30,7 +30,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t soa[2][9];  // offsets of x y z vx vy vz qs pid birth in buffer A and B
-  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, evlog;
+  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, bfield,
+      evlog;
   size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
   size_t total;
 };
@@ -85,6 +86,8 @@ Layout make_layout(const ecr_params *p) {
   o = align_up(o + 4);
   L.efield = o;
   if (p->efield_nodes) o = align_up(o + 8 * 3 * (size_t)nnodes(p));
+  L.bfield = o;
+  if (p->bfield_nodes) o = align_up(o + 8 * 3 * (size_t)nnodes(p));
   L.evlog = o;
   if (p->flags & ECR_FLAG_EVENTS) o = align_up(o + N);
   for (int b = 0; b < 2; ++b) {
@@ -675,6 +678,9 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   if (e == hipSuccess && params->efield_nodes)
     e = hipMemcpyAsync(at<double>(r, L.efield), params->efield_nodes, 8 * 3 * (size_t)r->nnode,
                        hipMemcpyHostToDevice, r->stream);
+  if (e == hipSuccess && params->bfield_nodes)
+    e = hipMemcpyAsync(at<double>(r, L.bfield), params->bfield_nodes, 8 * 3 * (size_t)r->nnode,
+                       hipMemcpyHostToDevice, r->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
   if (e != hipSuccess) {
     g_thread_err = std::string("upload failed: ") + hipGetErrorString(e);
@@ -682,6 +688,8 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
     return ECR_EDEVICE;
   }
   r->p.efield_nodes = params->efield_nodes ? (const double *)1 : nullptr;  // only its presence is kept
+  r->p.bfield_nodes = nullptr;  // the kernels read the arena copy through kp.bmap
+  r->kp.bmap = params->bfield_nodes ? at<double>(r, L.bfield) : nullptr;
   zero_accumulators(r);
   *out = r;
   return ECR_OK;

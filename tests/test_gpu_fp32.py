@@ -84,6 +84,7 @@ CASES = {
     # the optional physics (the push kernel's second variant) in binary32
     "extended": dict(mask=W.P_ALL | W.P_ELASTIC, v_ev=20.0, n0=3e19, ext=True),
     "self_ne_heat": dict(mask=W.P_ALL | W.P_HEAT, v_ev=20.0, self_ne=True, weight=4e12),
+    "bfield_map": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20, bmap=True),
 }
 
 
@@ -96,6 +97,11 @@ def test_fp32_single_step_against_oracle(case):
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     if c.get("ext"):
         params["species"] = [W.with_extended_mcc(params["species"][0])]
+    if c.get("bmap"):
+        nn = (params["nx"] + 1) * (params["ny"] + 1) * (params["nz"] + 1)
+        m = np.random.default_rng(6).normal(size=(3, nn)) * 0.05
+        m[2] += 0.5
+        params["bfield"] = m
     st = to_f32_exact(W.random_state(params, seed=300, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95)))
     g = gpu_run(fp32(params), events=True)
     g.set_state(st, step=11)

@@ -133,6 +133,9 @@ CASES = {
     "all_extended": dict(mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, n0=5e18, ext=True),
     "extended_self_ne": dict(mask=W.P_IONIZE | W.P_CX | W.P_ELASTIC, v_ev=50.0, n0=3e19, self_ne=True, weight=4e12,
                              ext=True),
+    # every process with a magnetic field map (the kick reads |B| at cell centres from it)
+    "map_all_heat_self_ne": dict(mask=W.P_ALL | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True, weight=4e12,
+                                 bmap=True),
 }
 
 
@@ -147,6 +150,8 @@ def test_single_step_parity(case, seed):
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     if c.get("ext"):
         params["species"] = [W.with_extended_mcc(params["species"][0])]
+    if c.get("bmap"):
+        params["bfield"] = _random_bmap(params, 40 + seed)
     st = W.random_state(params, seed=100 + seed, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95),
                         birth_max=17 + seed)
     g, o = run_pair(params, st, 1, step0=17 + seed)
@@ -161,7 +166,7 @@ def test_single_step_parity(case, seed):
         assert (ev == W.EV_WALL).sum() > 20
     if case in ("ionize", "all", "ionize_self_ne", "all_self_ne", "all_heat_self_ne"):
         assert (ev == W.EV_IONIZE).sum() > 5
-    if case in ("all_heat_self_ne", "all_extended"):
+    if case in ("all_heat_self_ne", "all_extended", "map_all_heat_self_ne"):
         assert (ev == W.EV_WALL).sum() > 20
     if case in ("multi_ionize", "all_extended", "extended_self_ne"):
         assert to["ionized_n"][0][1:].sum() > 0 and (ev == W.EV_IONIZE).sum() > 5
@@ -216,6 +221,35 @@ def test_efield_push_parity():
     g, o = run_pair(params, st, 3)
     assert_state_close(g.get_state(), o.get_state(), params, what="efield")
     assert np.array_equal(g.events(), o.events())
+
+
+def _random_bmap(params, seed):
+    # a node field map: a uniform 0.5 T along z plus node-to-node noise
+    nn = (params["nx"] + 1) * (params["ny"] + 1) * (params["nz"] + 1)
+    rng = np.random.default_rng(seed)
+    m = rng.normal(size=(3, nn)) * 0.05
+    m[2] += 0.5
+    return m
+
+
+@pytest.mark.parametrize("with_e", [False, True])
+def test_bfield_map_push_parity(with_e):
+    # a magnetic field map in place of the analytic field (and an E grid with it)
+    params = W.base_params(5003, 8, 8, 16)
+    params.update(process_mask=W.P_PUSH | W.P_DEPOSIT, bfield=_random_bmap(params, 4), dt=1e-8)
+    if with_e:
+        params["efield"] = np.random.default_rng(3).normal(size=(3, 9 * 9 * 17)) * 2000.0
+    st = W.random_state(params, seed=5, q_max=10, v_ev=300.0, radius_frac=0.9995)
+    g, o = run_pair(params, st, 3)
+    assert_state_close(g.get_state(), o.get_state(), params, what="bfield map")
+    assert np.array_equal(g.events(), o.events())
+    assert_tallies_equal(g.tallies(), o.tallies(), "bfield map")
+    assert o.tallies()["wall"].sum() > 20
+    # and the map is what moved them: the analytic field gives other orbits
+    a = oracle(dict(params, bfield=None))
+    a.set_state(st, step=0)
+    a.step(3)
+    assert np.abs(a.get_state()["vx"] - o.get_state()["vx"]).max() > 1.0
 
 
 def test_multi_step_c1_from_init():
