@@ -93,10 +93,12 @@ enum {
 enum {
   ECR_FLAG_EVENTS = 1, /* record each particle's event code of the last step */
   ECR_FLAG_SPLIT = 2,  /* deposit in its own kernel instead of inside the push kernel (per-kernel timing) */
-  ECR_FLAG_SELF_NE = 4 /* electron density = ion charge density of the particle's cell at the start of the
+  ECR_FLAG_SELF_NE = 4, /* electron density = ion charge density of the particle's cell at the start of the
                           step (Sec. II: charge neutrality) instead of the fixed ne_in/ne_out background;
                           the zone still picks the rate table (warm inside, cold outside), and the
                           ionisation probability is n_e k_Q dt (ne_in/ne_out only bound the dt check) */
+  ECR_FLAG_HEAT_ISOTROPIC = 8 /* the heating kick without its diamagnetic bias (delta = 0): the paper's
+                                 ablation that switches off the plasma diffusion by e-i collisions (Sec. IV) */
 };
 
 /* event codes returned by ecr_event_log */

@@ -771,7 +771,8 @@ static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
 /* n_e and T_e are the ionisation's: with self-consistent electrons the     */
 /* cell's ion charge density at the start of the step (no kick in a cell    */
 /* without charge), else the zone's fixed background, which is uniform, so */
-/* delta = 0.  Applied to ions that stay in the chamber, with their charge  */
+/* delta = 0; so does the isotropic-heating switch (the ablation of Sec.    */
+/* IV).  Applied to ions that stay in the chamber, with their charge        */
 /* before ionisation and charge exchange.                                    */
 /* ------------------------------------------------------------------------ */
 static double cell_ne(const orc_sim *s, int ix, int iy, int iz) {
@@ -795,7 +796,7 @@ static void heat_kick(orc_sim *s, int64_t i) {
     double B[3];
     orc_field(s, -s->p.R0 + (ix + 0.5) * s->hx, -s->p.R0 + (iy + 0.5) * s->hy, -s->hL + (iz + 0.5) * s->hz, B);
     double bmag = sqrt((B[0] * B[0] + B[1] * B[1]) + B[2] * B[2]);
-    if (bmag > 0.0) {
+    if (bmag > 0.0 && !s->p.heat_isotropic) {
       double RL = (2.38e-6 * sqrt(Te)) / (bmag * s->hx);
       double gy = (-cell_ne(s, ix, iy + 1, iz) + cell_ne(s, ix, iy - 1, iz)) +
                   0.5 * (((-cell_ne(s, ix - 1, iy + 1, iz) - cell_ne(s, ix + 1, iy + 1, iz)) +

@@ -83,6 +83,7 @@ typedef struct {
   double Te_in_eV, Te_out_eV; /* electron temperature inside (warm) and outside (cold) the zone */
   const double *bfield;       /* [3][(nx+1)(ny+1)(nz+1)] node magnetic field, T, interpolated trilinearly
                                  in place of the analytic field; or NULL */
+  int32_t heat_isotropic;     /* 1: the heating kick without its diamagnetic bias (Sec. IV ablation) */
 } orc_params;
 
 typedef struct {

@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) k_init(KParams P, Soa<R> S) {
 // density in the ion's z plane (cells beyond the mesh count as empty) times
 // -R_L / n_e(cell), R_L = 2.38e-6 sqrt(T_e) / (|B(cell centre)| hx); a cell
 // without charge gives no kick.  With the fixed background, n_e is the
-// zone's and, the background being uniform, delta = 0.  The kick is
+// zone's and, the background being uniform, delta = 0; ECR_FLAG_HEAT_ISOTROPIC
+// also sets delta = 0 (the isotropic-heating ablation).  The kick is
 // evaluated in binary64 whatever R; the neighbours' loads hit the cache
 // lines the lanes of a cell share (slots are in cell order).
 // ---------------------------------------------------------------------------
@@ -108,7 +109,7 @@ __device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__rest
       field_B<double>(P, xc, yc, zc, bx, by, bz);
     }
     const double bmag = sqrt((bx * bx + by * by) + bz * bz);
-    if (bmag > 0.0) {
+    if (bmag > 0.0 && !(P.flags & ECR_FLAG_HEAT_ISOTROPIC)) {
       const double rl = P.rl_zone[zone] / (bmag * P.hx);
       const double nmm = nat(ix - 1, iy - 1), nzm = nat(ix, iy - 1), npm = nat(ix + 1, iy - 1);
       const double nmz = nat(ix - 1, iy), npz = nat(ix + 1, iy);

@@ -274,6 +274,7 @@ std::string validate(const ecr_params *p) {
     return "negative weight, Coulomb logarithm or temperature";
   if (p->ne_in_m3 < 0.0 || p->ne_out_m3 < 0.0) return "negative electron density";
   if (p->process_mask >= 128u) return "process_mask has unknown bits";
+  if (p->flags >= 16u) return "flags has unknown bits";
   if ((p->process_mask & ECR_P_HEAT) &&
       !(p->Te_in_eV > 0.0 && p->Te_out_eV > 0.0 && isfinite(p->Te_in_eV) && isfinite(p->Te_out_eV)))
     return "the heating kick needs positive electron temperatures";

@@ -126,6 +126,7 @@ CASES = {
     # density with its diamagnetic bias
     "heat": dict(mask=W.P_HEAT, v_ev=0.5),
     "heat_self_ne": dict(mask=W.P_HEAT, v_ev=0.5, self_ne=True, weight=4e12),
+    "heat_iso_self_ne": dict(mask=W.P_HEAT, v_ev=0.5, self_ne=True, weight=4e12, heat_isotropic=True),
     "all_heat_self_ne": dict(mask=W.P_ALL | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True, weight=4e12),
     # multiple ionisation (synthetic rates for n = 2..4) and elastic ion-atom scattering
     "multi_ionize": dict(mask=W.P_IONIZE, v_ev=0.5, dt=3e-9, ext=True),
@@ -145,7 +146,7 @@ def test_single_step_parity(case, seed):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
     params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=c.get("dm", 15), weight=c.get("weight", 4e9),
-                  self_ne=c.get("self_ne", False))
+                  self_ne=c.get("self_ne", False), heat_isotropic=c.get("heat_isotropic", False))
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     if c.get("ext"):
@@ -172,7 +173,7 @@ def test_single_step_parity(case, seed):
         assert to["ionized_n"][0][1:].sum() > 0 and (ev == W.EV_IONIZE).sum() > 5
     if case in ("elastic", "all_extended", "extended_self_ne"):
         assert (ev == W.EV_ELASTIC).sum() > 10
-    if case in ("heat", "heat_self_ne"):
+    if case in ("heat", "heat_self_ne", "heat_iso_self_ne"):
         kicked = (b["vx"] != st["vx"]).sum()
         assert kicked > 2000, kicked
     if case == "cx":

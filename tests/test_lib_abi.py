@@ -63,6 +63,12 @@ def test_footprint_and_parameter_checks():
     with pytest.raises(ecr.EcrError, match="process_mask"):
         ecr.footprint(W.with_(p, process_mask=128))
     P, _keep = ecr.make_params(p)
+    P.flags = 16
+    import ctypes as C
+    n = C.c_size_t()
+    assert ecr.lib().ecr_footprint(C.byref(P), C.byref(n)) == -1
+    assert b"flags" in ecr.lib().ecr_last_error(None)
+    P, _keep = ecr.make_params(p)
     P.abi_version = 99
     import ctypes as C
     n = C.c_size_t()

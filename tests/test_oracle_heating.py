@@ -17,6 +17,8 @@
   is the electron diamagnetic drift's for B along +z, (dn/dy, -dn/dx).  At
   the mesh edge the missing neighbours count as zero density.
 * No kick for atoms, with zero electron density, or with the switch off.
+* The isotropic-heating switch (the paper's ablation, Sec. IV) drops the
+  bias: the same ramp gives no mean drift, and the same kick magnitudes.
 """
 import math
 
@@ -171,3 +173,26 @@ def test_no_kick_for_atoms_empty_backgrounds_or_switch_off():
     o.set_state(st, step=0)
     o.step(1)
     assert np.array_equal(o.get_state()["vx"], st["vx"])
+
+
+def test_isotropic_switch_removes_the_bias_only():
+    nx = 16
+    p = _uniform_b(W.base_params(1, nx, nx, 16, seed=12))
+    p.update(process_mask=W.P_HEAT, self_ne=True, zone_a=1.0, zone_c=1.0, dt=1e-8, weight=2e9,
+             Te_in_eV=4000.0, B0=0.25)
+    st, cells = _gradient_state(p, 20, 6, range(2, 14), 40)
+    p["n"] = len(st["x"])
+    out = []
+    for iso in (False, True):
+        o = OracleSim(dict(p, heat_isotropic=iso))
+        o.set_state(st, step=3)
+        o.step(1)
+        a = o.get_state()
+        out.append(np.stack([a["vx"], a["vy"], a["vz"]], axis=1))
+    sel = (cells[:, 0] >= 3) & (cells[:, 0] <= 12) & (cells[:, 1] >= 3) & (cells[:, 1] <= 12)
+    biased, iso = out[0][sel], out[1][sel]
+    se = iso.std(0) / math.sqrt(sel.sum())
+    assert np.all(np.abs(iso.mean(0)) <= 4.5 * se)
+    assert biased[:, 1].mean() < -4.5 * se[1]
+    # |dV| = D |R| either way: the same draws give the same magnitudes
+    np.testing.assert_allclose(np.linalg.norm(iso, axis=1), np.linalg.norm(biased, axis=1), rtol=1e-12)
