@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("efield", C.POINTER(C.c_double)), ("n_species", C.c_int32),
                 ("sp", Species * MAXS), ("self_ne", C.c_int32),
                 ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double),
-                ("bfield", C.POINTER(C.c_double)), ("heat_isotropic", C.c_int32)]
+                ("bfield", C.POINTER(C.c_double)), ("heat_isotropic", C.c_int32),
+                ("self_n0", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -141,6 +142,7 @@ def make_params(p):
     P.self_ne = 1 if p.get("self_ne") else 0
     P.lnL_ei = float(p.get("lnL_ei", 17.0))
     P.heat_isotropic = 1 if p.get("heat_isotropic") else 0
+    P.self_n0 = 1 if p.get("self_n0") else 0
     P.Te_in_eV = float(p.get("Te_in_eV", 0.0))
     P.Te_out_eV = float(p.get("Te_out_eV", 0.0))
     return P, keep

@@ -54,6 +54,7 @@ struct orc_sim {
   double kdt[ORC_MAXS][2][ORC_MAXN][ORC_MAXQ];
   double ccx[ORC_MAXS];              /* n0 sigma1 dt */
   double cel[ORC_MAXS];              /* n0 sigma_el1 dt */
+  double sdt_cx[ORC_MAXS], sdt_el[ORC_MAXS]; /* sigma1 dt, sigma_el1 dt (neutrals from the tracked atoms) */
   int cxok[ORC_MAXS][ORC_MAXQ];
   double sig_w[ORC_MAXS], sig_n[ORC_MAXS], sig_i[ORC_MAXS], decx[ORC_MAXS];
   int64_t sp_end[ORC_MAXS];          /* particle ids [sp_end[s-1], sp_end[s]) are species s */
@@ -71,6 +72,7 @@ struct orc_sim {
   uint32_t *cell;
   uint32_t *birth;  /* step the ion was made from an atom, or ORC_BIRTH_NONE */
   uint32_t *chg;    /* self-consistent electrons: ion charge per cell at the start of the step */
+  uint32_t *atoms;  /* tracked neutrals: atoms per species and cell at the start of the step [s][cell] */
   /* cell order */
   uint32_t *order, *cell_off;
   int64_t step;
@@ -386,6 +388,8 @@ int orc_create(const orc_params *p, orc_sim **out) {
     }
     s->ccx[k] = (sp->n0 * sp->sigma_cx1) * dt;
     s->cel[k] = (sp->n0 * sp->sigma_el1) * dt;
+    s->sdt_cx[k] = sp->sigma_cx1 * dt;
+    s->sdt_el[k] = sp->sigma_el1 * dt;
     s->sig_w[k] = sqrt(p->T_wall_eV * E_CHARGE / s->M[k]);
     s->sig_n[k] = sqrt(p->T_n_eV * E_CHARGE / s->M[k]);
     s->sig_i[k] = sqrt(p->Ti0_eV * E_CHARGE / s->M[k]);
@@ -432,9 +436,10 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->pool = calloc(nd, 4); s->pkey = calloc(nd, 4); s->birth = calloc(nd, 4);
   s->cell_off = calloc((size_t)s->ncell + 1, 4);
   s->chg = calloc((size_t)s->ncell, 4);
+  s->atoms = calloc((size_t)s->ncell * ORC_MAXS, 4);
   for (int f = 0; f < ORC_NFIELDS; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
-      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->chg || !s->dens[0] ||
+      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->chg || !s->atoms || !s->dens[0] ||
       !s->dens[1] || !s->dens[2] || !s->dens[3]) {
     orc_destroy(s);
     return -2;
@@ -452,7 +457,7 @@ void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
   free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order); free(s->id);
-  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off); free(s->chg);
+  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off); free(s->chg); free(s->atoms);
   for (int f = 0; f < ORC_NFIELDS; f++) free(s->dens[f]);
   free(s);
 }
@@ -895,10 +900,19 @@ static int mcc(orc_sim *s, int64_t i) {
     cum[n - 1] = acc;
   }
   double speed = sqrt((s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i]) + s->vz[i] * s->vz[i]);
+  /* neutral partners: the species' uniform n0, or with tracked neutrals
+   * n0 = weight x (atoms of the species in the cell at the start of the
+   * step) / cell volume */
+  double ccx = s->ccx[sp], cel = s->cel[sp];
+  if (s->p.self_n0 && (s->p.process_mask & (ORC_P_CX | ORC_P_ELASTIC))) {
+    double n0c = s->nfac * (double)s->atoms[(int64_t)sp * s->ncell + orc_cell_of(s, x, y, z)];
+    ccx = n0c * s->sdt_cx[sp];
+    cel = n0c * s->sdt_el[sp];
+  }
   double pc = 0.0;
-  if ((s->p.process_mask & ORC_P_CX) && s->cxok[sp][Q]) pc = (s->ccx[sp] * (double)Q) * speed;
+  if ((s->p.process_mask & ORC_P_CX) && s->cxok[sp][Q]) pc = (ccx * (double)Q) * speed;
   double pe = 0.0;
-  if (s->p.process_mask & ORC_P_ELASTIC) pe = (s->cel[sp] * (double)Q) * speed;
+  if (s->p.process_mask & ORC_P_ELASTIC) pe = (cel * (double)Q) * speed;
   double pt = acc + pc;
   double pall = pt + pe;
   if (pall > 0.1) s->t.anomalies++;
@@ -994,6 +1008,12 @@ int orc_step(orc_sim *s, int64_t n_steps) {
       memset(s->chg, 0, (size_t)s->ncell * 4);
       for (int64_t i = 0; i < s->N; i++)
         if (s->q[i] >= 1) s->chg[orc_cell_of(s, s->x[i], s->y[i], s->z[i])] += s->q[i];
+    }
+    if (s->p.self_n0) {
+      /* the tracked atoms are the neutral gas of the collisions */
+      memset(s->atoms, 0, (size_t)s->ncell * ORC_MAXS * 4);
+      for (int64_t i = 0; i < s->N; i++)
+        if (s->q[i] == 0) s->atoms[(int64_t)s->sp[i] * s->ncell + orc_cell_of(s, s->x[i], s->y[i], s->z[i])]++;
     }
     for (int64_t i = 0; i < s->N; i++) {
       int ev = ORC_EV_NONE;

@@ -84,6 +84,8 @@ typedef struct {
   const double *bfield;       /* [3][(nx+1)(ny+1)(nz+1)] node magnetic field, T, interpolated trilinearly
                                  in place of the analytic field; or NULL */
   int32_t heat_isotropic;     /* 1: the heating kick without its diamagnetic bias (Sec. IV ablation) */
+  int32_t self_n0;            /* 1: the neutral density of charge exchange and elastic scattering is that of the
+                                 tracked atoms of the species in the ion's cell, not the species' n0 */
 } orc_params;
 
 typedef struct {
