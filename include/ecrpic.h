@@ -97,8 +97,11 @@ enum {
                           step (Sec. II: charge neutrality) instead of the fixed ne_in/ne_out background;
                           the zone still picks the rate table (warm inside, cold outside), and the
                           ionisation probability is n_e k_Q dt (ne_in/ne_out only bound the dt check) */
-  ECR_FLAG_HEAT_ISOTROPIC = 8 /* the heating kick without its diamagnetic bias (delta = 0): the paper's
-                                 ablation that switches off the plasma diffusion by e-i collisions (Sec. IV) */
+  ECR_FLAG_HEAT_ISOTROPIC = 8, /* the heating kick without its diamagnetic bias (delta = 0): the paper's
+                                  ablation that switches off the plasma diffusion by e-i collisions (Sec. IV) */
+  ECR_FLAG_SELF_N0 = 16 /* the neutral gas of charge exchange and elastic scattering is the tracked atoms (Sec. II):
+                           n0 = weight x (atoms of the ion's species in its cell at the start of the step) / cell
+                           volume, instead of the species' uniform n0_m3 (which then only bounds the dt check) */
 };
 
 /* event codes returned by ecr_event_log */

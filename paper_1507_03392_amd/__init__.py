@@ -23,7 +23,7 @@ BIRTH_NONE = 0xFFFFFFFF
 FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL, P_HEAT, P_ELASTIC = 1, 2, 4, 8, 16, 31, 32, 64
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P, N_FIELDS = 0, 1, 2, 3, 4
-FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE, FLAG_HEAT_ISOTROPIC = 1, 2, 4, 8
+FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE, FLAG_HEAT_ISOTROPIC, FLAG_SELF_N0 = 1, 2, 4, 8, 16
 K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, N_KERNELS = 0, 1, 2, 3, 4, 5, 6
 KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_pairs"]
 
@@ -135,7 +135,8 @@ def make_params(p, events=False, split=False):
     P.process_mask = p["process_mask"]
     P.deposit_mask = p["deposit_mask"]
     P.flags = (FLAG_EVENTS if events else 0) | (FLAG_SPLIT if split else 0) | \
-        (FLAG_SELF_NE if p.get("self_ne") else 0) | (FLAG_HEAT_ISOTROPIC if p.get("heat_isotropic") else 0)
+        (FLAG_SELF_NE if p.get("self_ne") else 0) | (FLAG_HEAT_ISOTROPIC if p.get("heat_isotropic") else 0) | \
+        (FLAG_SELF_N0 if p.get("self_n0") else 0)
     P.sort_every = p["sort_every"]
     P.seed = p["seed"]
     P.n_particles = p["n"]

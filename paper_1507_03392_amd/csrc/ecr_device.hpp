@@ -52,12 +52,14 @@ struct KParams {
   const double *bmap;  // device [3][nnode] node magnetic field (T), or null: the analytic field
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
   double cel[kMaxS];     // n0 sigma_el1 dt (elastic ion-atom scattering)
+  double sdt_cx[kMaxS], sdt_el[kMaxS];  // sigma1 dt, sigma_el1 dt: neutrals from the tracked atoms
   int32_t nion;          // ionisation channels with a nonzero rate: 1 .. kMaxN
   // per species pair (a, b): reduced mass mu = ma mb / (ma + mb), mu / ma, mu / mb
   double mu[kMaxS][kMaxS], mra[kMaxS][kMaxS], mrb[kMaxS][kMaxS];
   uint32_t cxok[kMaxS];  // bit Q: charge exchange allowed from Q
   int64_t sp_end[kMaxS]; // ids [sp_end[s-1], sp_end[s]) are species s
   int64_t n, nnode;
+  uint32_t ncell;  // nx ny nz: the stride of the cell grids' channels
   int32_t nx, ny, nz, nx1, ny1, nspecies;
   uint32_t seed_lo, seed_hi, pmask, dmask, flags;
 };

@@ -85,7 +85,7 @@ __device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__rest
                                           const uint32_t *__restrict__ chg) {
   const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
   double ne, dlx = 0.0, dly = 0.0;
-  if (chg) {
+  if (P.flags & ECR_FLAG_SELF_NE) {
     const int ix = clampi((int)floor((x + (R)P.R0) * (R)P.idx), 0, P.nx - 1);
     const int iy = clampi((int)floor((y + (R)P.R0) * (R)P.idy), 0, P.ny - 1);
     const int iz = clampi((int)floor((z + (R)P.hL) * (R)P.idz), 0, P.nz - 1);
@@ -232,9 +232,10 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     // charge of the cell at the start of the step) / cell volume.  One
     // uniform picks the channel by running sums: ionisation n = 1..4, then
     // charge exchange, then elastic scattering.
+    const bool self_ne = (P.flags & ECR_FLAG_SELF_NE) != 0;
     double pi = 0.0, ne = 0.0;
     if (P.pmask & P_IONIZE) {
-      if (chg) {
+      if (self_ne) {
         ne = P.nfac * (double)chg[cell_of<R>(P, x, y, z)];
         pi = ne * T->kdt[s][zone][Q];
       } else {
@@ -243,9 +244,9 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
     }
     double c2 = pi, c3 = pi, c4 = pi;  // running sums through n = 2, 3, 4
     if ((P.pmask & P_IONIZE) && P.nion > 1) {
-      const double p2 = chg ? ne * T->kmul[s][zone][0][Q] : T->pmul[s][zone][0][Q];
-      const double p3 = chg ? ne * T->kmul[s][zone][1][Q] : T->pmul[s][zone][1][Q];
-      const double p4 = chg ? ne * T->kmul[s][zone][2][Q] : T->pmul[s][zone][2][Q];
+      const double p2 = self_ne ? ne * T->kmul[s][zone][0][Q] : T->pmul[s][zone][0][Q];
+      const double p3 = self_ne ? ne * T->kmul[s][zone][1][Q] : T->pmul[s][zone][1][Q];
+      const double p4 = self_ne ? ne * T->kmul[s][zone][2][Q] : T->pmul[s][zone][2][Q];
       c2 = pi + p2;
       c3 = c2 + p3;
       c4 = c3 + p4;
@@ -257,10 +258,18 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
       const R sp2 = (vx * vx + vy * vy) + vz * vz;
       speed = (double)sqrt(sp2);
     }
+    // neutral partners: the species' uniform n0, or with ECR_FLAG_SELF_N0
+    // weight x (atoms of the species in the cell at the start of the step) / cell volume
+    double ccx = P.ccx[s], cel = P.cel[s];
+    if ((P.flags & ECR_FLAG_SELF_N0) && (cxon || elon)) {
+      const double n0c = P.nfac * (double)chg[(uint32_t)(1 + s) * P.ncell + cell_of<R>(P, x, y, z)];
+      ccx = n0c * P.sdt_cx[s];
+      cel = n0c * P.sdt_el[s];
+    }
     double pc = 0.0;
-    if (cxon) pc = (P.ccx[s] * (double)Q) * speed;
+    if (cxon) pc = (ccx * (double)Q) * speed;
     const double pt = c4 + pc;
-    const double pall = elon ? pt + (P.cel[s] * (double)Q) * speed : pt;
+    const double pall = elon ? pt + (cel * (double)Q) * speed : pt;
     if (pall > 0.1) atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
     if (u < c4) {
       const int n = u < pi ? 1 : (u < c2 ? 2 : (u < c3 ? 3 : 4));
@@ -573,9 +582,10 @@ __device__ __forceinline__ void box_init(int *box) {
 // ---------------------------------------------------------------------------
 // Push + wall/aperture + MCC (+ deposit): slot j = tile + tid + 256 p.
 // ---------------------------------------------------------------------------
-// the ion charge Q of a lane's particle added to its cell (chg_next): lanes
-// hold consecutive slots, mostly of one cell, so the first lane of each run
-// of equal cells adds the run's sum with one atomic
+// a lane's contribution to the next step's cell grids (chg_next: the ion
+// charge Q in channel 0, or one atom in its species' channel): lanes hold
+// consecutive slots, mostly of one cell, so the first lane of each run of
+// equal entries adds the run's sum with one atomic
 __device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t cell, uint32_t q) {
   const int lane = threadIdx.x & 63;
   const uint32_t prev = __shfl_up(cell, 1, 64);
@@ -625,9 +635,12 @@ __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__rest
       S.vz[j] = vz;
       S.qs[j] = make_qs(Q, s);
       if (evlog) evlog[j] = ev;
-      if (EXT && chg_next && Q >= 1) {
-        ccell = cell_of<R>(P, x, y, z);
-        cq = (uint32_t)Q;
+      if (EXT && chg_next) {
+        // the next step's cell grids: ion charge in channel 0, atoms of
+        // species s in channel 1 + s
+        const uint32_t c = cell_of<R>(P, x, y, z);
+        ccell = Q >= 1 ? c : (uint32_t)(1 + s) * P.ncell + c;
+        cq = Q >= 1 ? (uint32_t)Q : 1u;
       }
       if (DEP) stage_cic<R, DEP == 2>(P, sh.st, i, x, y, z, Q, mn, mx);
     }
@@ -871,17 +884,17 @@ void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, 
     launch_push_v<R, false>(P, T, S, ef, evlog, acc, dens, step, chg_cur, chg_next, st);
 }
 
-// ion charge per cell of the current state (the first step after init or set_state)
+// ion charge and atoms per cell of the current state (the first step after init or set_state)
 template <typename R>
 __global__ void __launch_bounds__(256) k_charge_grid(KParams P, Soa<R> S, uint32_t *__restrict__ chg) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t cell = 0xffffffffu, q = 0u;
   if (j < P.n) {
-    const int Q = q_of(S.qs[j]);
-    if (Q >= 1) {
-      cell = cell_of<R>(P, S.x[j], S.y[j], S.z[j]);
-      q = (uint32_t)Q;
-    }
+    const uint8_t qs = S.qs[j];
+    const int Q = q_of(qs);
+    const uint32_t c = cell_of<R>(P, S.x[j], S.y[j], S.z[j]);
+    cell = Q >= 1 ? c : (uint32_t)(1 + sp_of(qs)) * P.ncell + c;
+    q = Q >= 1 ? (uint32_t)Q : 1u;
   }
   add_charge(chg, cell, q);  // all lanes together
 }

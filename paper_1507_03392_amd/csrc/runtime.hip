@@ -92,7 +92,8 @@ Layout make_layout(const ecr_params *p) {
   if (p->flags & ECR_FLAG_EVENTS) o = align_up(o + N);
   for (int b = 0; b < 2; ++b) {
     L.chg[b] = o;
-    if (p->flags & ECR_FLAG_SELF_NE) o = align_up(o + 4 * (size_t)ncells(p));
+    if (p->flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0))
+      o = align_up(o + 4 * (size_t)ncells(p) * (size_t)(1 + p->n_species));
   }
   L.total = o + kAlign;  // slack so the arena base may be realigned
   return L;
@@ -274,7 +275,9 @@ std::string validate(const ecr_params *p) {
     return "negative weight, Coulomb logarithm or temperature";
   if (p->ne_in_m3 < 0.0 || p->ne_out_m3 < 0.0) return "negative electron density";
   if (p->process_mask >= 128u) return "process_mask has unknown bits";
-  if (p->flags >= 16u) return "flags has unknown bits";
+  if (p->flags >= 32u) return "flags has unknown bits";
+  if ((p->flags & ECR_FLAG_SELF_N0) && (int64_t)ncells(p) * (1 + p->n_species) >= (1LL << 32) - 1)
+    return "mesh too large for the per-species atom grids";
   if ((p->process_mask & ECR_P_HEAT) &&
       !(p->Te_in_eV > 0.0 && p->Te_out_eV > 0.0 && isfinite(p->Te_in_eV) && isfinite(p->Te_out_eV)))
     return "the heating kick needs positive electron temperatures";
@@ -351,6 +354,8 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
     K.decx[s] = 4.0 * p->dE_cx_eV * kE / M;
     K.ccx[s] = (sp.n0_m3 * sp.sigma_cx1_m2) * dt;
     K.cel[s] = (sp.n0_m3 * sp.sigma_el1_m2) * dt;
+    K.sdt_cx[s] = sp.sigma_cx1_m2 * dt;
+    K.sdt_el[s] = sp.sigma_el1_m2 * dt;
     uint32_t ok = 0;
     for (int q = 0; q < kMaxQ; ++q) {
       T.qmh[s][q] = ((double)q * kE / M) * (dt * 0.5);
@@ -393,6 +398,7 @@ void derive(const ecr_params *p, KParams &K, Tables &T, double &weight) {
     for (int j = 0; j < kAK; ++j) T.lnA[(e - kAeLo) * kAK + j] = nanbu_lnA_lib(ldexp(1.0 + (double)j / kAK, e));
   T.lnA[kANodes - 1] = nanbu_lnA_lib(kSHi);
   K.n = p->n_particles;
+  K.ncell = (uint32_t)ncells(p);
   K.nnode = nnodes(p);
   K.nx = p->nx;
   K.ny = p->ny;
@@ -512,17 +518,17 @@ void do_step(ecr_run *r, StepArg stepw) {
   }
   const bool dep = (pm & ECR_P_DEPOSIT) != 0;
   const bool split = (r->p.flags & ECR_FLAG_SPLIT) != 0;
-  const bool self_ne = (r->p.flags & ECR_FLAG_SELF_NE) != 0;
-  uint32_t *chg_cur = self_ne ? at<uint32_t>(r, r->L.chg[r->chg_par]) : nullptr;
-  uint32_t *chg_next = self_ne ? at<uint32_t>(r, r->L.chg[1 - r->chg_par]) : nullptr;
-  if (self_ne) launch_fill_u32(chg_next, 0u, r->ncell, r->stream);
+  const bool grids = (r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0)) != 0;
+  uint32_t *chg_cur = grids ? at<uint32_t>(r, r->L.chg[r->chg_par]) : nullptr;
+  uint32_t *chg_next = grids ? at<uint32_t>(r, r->L.chg[1 - r->chg_par]) : nullptr;
+  if (grids) launch_fill_u32(chg_next, 0u, r->ncell * (1 + r->p.n_species), r->stream);
   {
     ProfScope ps(r, (dep && !split) ? ECR_K_FUSED : ECR_K_PUSH);
     launch_push<R>(r->kp, T, soa<R>(r, r->cur), r->p.efield_nodes ? at<double>(r, r->L.efield) : nullptr,
                    (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc,
                    (dep && !split) ? at<double>(r, r->L.dens) : nullptr, stepw, chg_cur, chg_next, r->stream);
   }
-  if (self_ne) r->chg_par = 1 - r->chg_par;
+  if (grids) r->chg_par = 1 - r->chg_par;
   if (dep && split) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
@@ -536,12 +542,13 @@ void do_step(ecr_run *r, StepArg stepw) {
   r->steps++;
 }
 
-// ion charge per cell of the state just set (ECR_FLAG_SELF_NE)
+// ion charge and atoms per cell of the state just set (ECR_FLAG_SELF_NE,
+// ECR_FLAG_SELF_N0)
 void build_charge_grid(ecr_run *r) {
-  if (!(r->p.flags & ECR_FLAG_SELF_NE)) return;
+  if (!(r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0))) return;
   r->chg_par = 0;
   uint32_t *g = at<uint32_t>(r, r->L.chg[0]);
-  launch_fill_u32(g, 0u, r->ncell, r->stream);
+  launch_fill_u32(g, 0u, r->ncell * (1 + r->p.n_species), r->stream);
   if (r->fp32) launch_charge_grid<float>(r->kp, soa<float>(r, r->cur), g, r->stream);
   else launch_charge_grid<double>(r->kp, soa<double>(r, r->cur), g, r->stream);
 }
@@ -785,7 +792,7 @@ ecr_status ecr_step_graph(ecr_run *r, int64_t n_steps) {
     r->steps += K;
     if (dep) r->dens_steps += K;
     r->cur = 1 - r->cur;  // the period's sort moved the state to the other buffer
-    if ((r->p.flags & ECR_FLAG_SELF_NE) && (K & 1)) r->chg_par = 1 - r->chg_par;
+    if ((r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0)) && (K & 1)) r->chg_par = 1 - r->chg_par;
     r->need_sort = false;
     n_steps -= K;
   }

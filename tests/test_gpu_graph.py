@@ -94,3 +94,20 @@ def test_graph_self_consistent_electrons_odd_period(heat):
         a.step(n)
         b.step_graph(n)
         _same(a, b, f"after {a.get_state()['step']} steps")
+
+
+def test_graph_tracked_neutrals_odd_period():
+    # the cell grids (ion charge and atoms) alternate buffers every step
+    import torch
+    params = W.with_(W.base_params(20_011, 16, 16, 32, seed=7), sort_every=15, self_n0=True, self_ne=True,
+                     process_mask=W.P_ALL | W.P_ELASTIC, weight=1e12, dt=2e-9)
+    params["species"] = [W.with_extended_mcc(dict(params["species"][0], n0=2e19))]
+    st = W.random_state(params, seed=70, q_max=8, v_ev=40.0, frac_atoms=0.5)
+    stream = torch.cuda.Stream()
+    a, b = _runs(params, stream)
+    a.set_state(st, step=0)
+    b.set_state(st, step=0)
+    for n in (4, 26, 15, 15, 30, 7):
+        a.step(n)
+        b.step_graph(n)
+        _same(a, b, f"after {a.get_state()['step']} steps")

@@ -134,6 +134,10 @@ CASES = {
     "all_extended": dict(mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, n0=5e18, ext=True),
     "extended_self_ne": dict(mask=W.P_IONIZE | W.P_CX | W.P_ELASTIC, v_ev=50.0, n0=3e19, self_ne=True, weight=4e12,
                              ext=True),
+    # the neutral gas from the tracked atoms of the ion's species in its cell
+    "cx_self_n0": dict(mask=W.P_CX | W.P_ELASTIC, v_ev=50.0, self_n0=True, weight=1e13, ext=True, fa=0.5),
+    "all_self_n0_ne": dict(mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True,
+                           self_n0=True, weight=4e12, ext=True, n0=5e18),
     # every process with a magnetic field map (the kick reads |B| at cell centres from it)
     "map_all_heat_self_ne": dict(mask=W.P_ALL | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True, weight=4e12,
                                  bmap=True),
@@ -146,7 +150,8 @@ def test_single_step_parity(case, seed):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
     params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=c.get("dm", 15), weight=c.get("weight", 4e9),
-                  self_ne=c.get("self_ne", False), heat_isotropic=c.get("heat_isotropic", False))
+                  self_ne=c.get("self_ne", False), heat_isotropic=c.get("heat_isotropic", False),
+                  self_n0=c.get("self_n0", False))
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     if c.get("ext"):
@@ -154,7 +159,7 @@ def test_single_step_parity(case, seed):
     if c.get("bmap"):
         params["bfield"] = _random_bmap(params, 40 + seed)
     st = W.random_state(params, seed=100 + seed, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95),
-                        birth_max=17 + seed)
+                        birth_max=17 + seed, frac_atoms=c.get("fa", 0.1))
     g, o = run_pair(params, st, 1, step0=17 + seed)
     a, b = g.get_state(), o.get_state()
     assert np.array_equal(g.events(), o.events()), "events differ"
@@ -171,8 +176,10 @@ def test_single_step_parity(case, seed):
         assert (ev == W.EV_WALL).sum() > 20
     if case in ("multi_ionize", "all_extended", "extended_self_ne"):
         assert to["ionized_n"][0][1:].sum() > 0 and (ev == W.EV_IONIZE).sum() > 5
-    if case in ("elastic", "all_extended", "extended_self_ne"):
+    if case in ("elastic", "all_extended", "extended_self_ne", "cx_self_n0", "all_self_n0_ne"):
         assert (ev == W.EV_ELASTIC).sum() > 10
+    if case == "cx_self_n0":
+        assert (ev == W.EV_CX).sum() > 10
     if case in ("heat", "heat_self_ne", "heat_iso_self_ne"):
         kicked = (b["vx"] != st["vx"]).sum()
         assert kicked > 2000, kicked
@@ -325,6 +332,30 @@ def test_multi_step_c1_extended_mcc():
     tg, to = g.tallies(), o.tallies()
     assert_tallies_equal(tg, to, "c1 extended")
     assert to["elastic"].sum() > 15 and to["ionized_n"][0][1:].sum() > 5
+
+
+def test_multi_step_tracked_neutrals_and_electrons():
+    # half the particles atoms: the collisions' neutral gas and the
+    # electrons both follow the particles cell by cell, 60 steps across
+    # three sorts, every decision bit for bit
+    params = boosted(W.base_params(20_011, 16, 16, 32, seed=6))
+    params["species"] = [W.with_extended_mcc(params["species"][0])]
+    params.update(process_mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, self_ne=True, self_n0=True, weight=1e12,
+                  sort_every=20, dt=2e-9, zone_a=0.03, zone_c=0.14)
+    st = W.random_state(params, seed=61, q_max=8, v_ev=40.0, frac_atoms=0.5)
+    g = gpu_run(params, events=True)
+    g.set_state(st, step=0)
+    o = oracle(params)
+    o.set_state(st, step=0)
+    for chunk in (1, 29, 30):
+        g.step(chunk)
+        o.step(chunk)
+        a, b = g.get_state(), o.get_state()
+        assert np.array_equal(g.events(), o.events())
+        assert_state_close(a, b, params, what=f"tracked neutrals step {a['step']}", tol=1e-9)
+    to = o.tallies()
+    assert_tallies_equal(g.tallies(), to, "tracked neutrals")
+    assert to["cx"].sum() > 20 and to["elastic"].sum() > 20 and to["ionized"].sum() > 20
 
 
 def test_deposit_fused_and_split_agree():

@@ -63,7 +63,7 @@ def test_footprint_and_parameter_checks():
     with pytest.raises(ecr.EcrError, match="process_mask"):
         ecr.footprint(W.with_(p, process_mask=128))
     P, _keep = ecr.make_params(p)
-    P.flags = 16
+    P.flags = 32
     import ctypes as C
     n = C.c_size_t()
     assert ecr.lib().ecr_footprint(C.byref(P), C.byref(n)) == -1
