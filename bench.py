@@ -38,6 +38,8 @@ def describe(name, p):
                      for s in p["species"])
     ne = "self-consistent electrons (n_e = ion charge density per cell)" if p.get("self_ne") else \
         "fixed electron background"
+    if p.get("self_n0"):
+        ne += ", neutrals from the tracked atoms per cell"
     return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, {ne}, "
             f"mesh {p['nx']}x{p['ny']}x{p['nz']}, dt {p['dt']:g} s, sort every {p['sort_every']}, "
             f"all processes on" + (", with the electron-ion heating kick" if p["process_mask"] & 32 else ""))
@@ -194,6 +196,8 @@ def main():
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--self-ne", action="store_true",
                     help="electron density = ion charge density per cell (self-consistent electrons)")
+    ap.add_argument("--self-n0", action="store_true",
+                    help="neutral gas of charge exchange and elastic scattering from the tracked atoms per cell")
     ap.add_argument("--heat", action="store_true",
                     help="add the electron-ion heating kick (diamagnetic bias with --self-ne)")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
@@ -231,6 +235,8 @@ def main():
         params["self_ne"] = True
     if args.heat:
         params["process_mask"] |= ecr.P_HEAT
+    if args.self_n0:
+        params["self_n0"] = True
     n = params["n"]
     fp32 = params.get("precision", 0) == ecr.FP32_MIXED
     log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")
@@ -271,7 +277,7 @@ def main():
     achieved = alg / avg_s / 1e9
     # the counters were taken on the default step (fixed electron background,
     # no optional physics, fused deposit): another configuration runs other code
-    default_step = not (args.self_ne or args.heat or args.split)
+    default_step = not (args.self_ne or args.heat or args.split or args.self_n0)
     traffic = measured_traffic(args.workload, dom) if default_step else None
 
     drift = None
