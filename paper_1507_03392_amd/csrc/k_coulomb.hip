@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 }
 
 // collisions, one per lane, so that every collision of the step is in
-// flight at once.  Grid (2 ceil(nchunks / 8) 8, 2), one wavefront per
+// flight at once.  Grid (nchunks, 1 + kPairRows), one wavefront per
 // workgroup.  Row 0
 // holds the triplet waves: the triplets of a group of kTriChunks chunks are
 // numbered in chunk order, and wave k of the group (column k * ngroups + g
@@ -337,12 +337,9 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
 // more), one triplet per lane, three dependent collisions each ((a,b),
 // (b,c), (c,a) with dt/2).  The k = 0 waves, usually the only busy ones, thus
 // sit side by side at the front, spread over the XCDs (consecutive
-// workgroups go to different XCDs), and start before the pair waves.  Row
-// 1 holds the pair waves: wave y of chunk b takes pairs 64y..64y+63 (then
-// 64(y + kPairRows).. if the chunk has more), and the two waves of a chunk
-// sit 8 columns apart, so they run on the XCD that ordered the chunk, one
-// after the other, sharing its L2 (49.5 -> 48.0 us per launch at 2M
-// ions).  Triplets and pairs touch
+// workgroups go to different XCDs), and start before the pair waves;
+// row 1 + y, column b takes pairs 64y..64y+63 of chunk b (then
+// 64(y + kPairRows).. if the chunk has more).  Triplets and pairs touch
 // disjoint particles.  At most 4 waves per SIMD: the triplet path alone
 // would need a few more registers than that allows, for nothing.
 template <typename R>
@@ -356,7 +353,6 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
   const int lane = (int)threadIdx.x;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (blockIdx.y == 0) {
-    if ((int64_t)blockIdx.x >= nchunks) return;  // the row is padded to the pair row's width
     // triplet wave kw of the group starting at chunk b: lane j < kTriChunks
     // holds chunk b + j's first slot, pair count and inclusive triplet prefix
     const int64_t ngroups = (nchunks + kTriChunks - 1) / kTriChunks;
@@ -407,15 +403,8 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
     }
     return;
   }
-  // pair row: block k takes chunk 8 (k / 16) + k % 8, pairs 64 ((k / 8) % 2)
-  // onwards: the two waves of a chunk are 8 blocks apart, so the round-robin
-  // dispatch puts them on one XCD one after the other and the second finds
-  // the chunk's velocities in that XCD's L2
-  static_assert(kPairRows == 2, "the pair-row mapping interleaves two rows");
-  const int64_t k = blockIdx.x;
-  const int64_t b = 8 * (k / 16) + k % 8;
-  const int y = (int)((k / 8) % 2);
-  if (b >= nchunks) return;
+  const int64_t b = blockIdx.x;
+  const int y = (int)blockIdx.y - 1;
   const int64_t s_lo = chunk_lo[b];
   const int ns = (int)((int64_t)chunk_lo[b + 1] - s_lo);
   if (ns <= 1 || ns > kCoulMaxE) return;
@@ -490,11 +479,8 @@ void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32
                        const uint2 *counts, double *moments, StepArg step, hipStream_t st) {
   if (P.n <= 1) return;
   const int64_t nc = coul_nchunks(P.n);
-  // row 0: triplet waves; row 1: the pair waves of every chunk (kPairRows
-  // per chunk), 16 blocks per 8 chunks
-  const int64_t gx = 2 * ((nc + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)gx, 2), dim3(64), 0, st, P, T, S, chunk_lo, items, counts,
-                     moments, step, nc);
+  hipLaunchKernelGGL(k_coul_pairs<R>, dim3((unsigned)nc, 1 + kPairRows), dim3(64), 0, st, P, T, S, chunk_lo,
+                     items, counts, moments, step, nc);
 }
 
 template void launch_coul_order<double>(const KParams &, Soa<double>, const uint32_t *, const uint32_t *, DevAccum *,
