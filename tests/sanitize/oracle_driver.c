@@ -3,8 +3,8 @@
  * sorts, Coulomb pools (pairs and triplets), push with an E grid and a
  * magnetic map, walls and the aperture, ionisation Q -> Q+n, charge
  * exchange, elastic scattering, the heating kick with self-consistent
- * electrons, all four density fields, state round trips and a second
- * species.  Prints the tallies' totals; exits non-zero on an API error. */
+ * electrons, the tracked-neutral density (second pass), all four density
+ * fields, state round trips and a second species.  Prints the tallies' totals; exits non-zero on an API error. */
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -58,6 +58,14 @@ int main(void) {
   for (int pass = 0; pass < 2; pass++) {
     p.bfield = pass ? bf : NULL;
     p.heat_isotropic = pass;
+    p.self_n0 = pass;
+    /* the tracked atoms give about 1e18 m^-3 here: raise the cross-sections
+     * so exchange and elastic scattering still occur, keeping n0 sigma */
+    for (int k = 0; k < 2; k++) {
+      p.sp[k].sigma_cx1 = pass ? 1e-17 : 5e-19;
+      p.sp[k].sigma_el1 = pass ? 6e-18 : 3e-19;
+      p.sp[k].n0 = pass ? 1e18 : 2e19;
+    }
     orc_sim *s = NULL;
     if (orc_create(&p, &s) != 0) { fprintf(stderr, "create failed\n"); return 1; }
     if (orc_init_ions(s) != 0) return 1;
@@ -68,6 +76,10 @@ int main(void) {
     uint8_t *q = malloc(n), *spc = malloc(n);
     uint32_t *cell = malloc(4 * n), *birth = malloc(4 * n);
     orc_get_state(s, &step, a, a + n, a + 2 * n, a + 3 * n, a + 4 * n, a + 5 * n, q, spc, cell, birth);
+    /* init makes ions only: in the tracked-neutral pass turn every third
+     * particle into an atom, so that the cells hold atoms to collide with */
+    if (pass)
+      for (int64_t i = 0; i < n; i += 3) q[i] = 0;
     if (orc_set_state(s, step, a, a + n, a + 2 * n, a + 3 * n, a + 4 * n, a + 5 * n, q, cell, birth) != 0) return 1;
     if (orc_step(s, 23) != 0) return 1;
     orc_tallies t;
