@@ -26,8 +26,8 @@
 //    gathers the triplets of kTriChunks chunks), with no LDS and no
 //    barriers, so the long dependent FP64 chains and scattered loads of the
 //    collisions are all in flight at once.  Pairs are disjoint, so no two
-//    lanes touch one particle, and the item order (set by LDS atomics) does
-//    not change results.
+//    lanes touch one particle, and the item order does not change any
+//    particle (it only regroups the FP64 momentum and energy sums).
 #include "ecr_kernels.hpp"
 
 namespace ecr {
@@ -113,7 +113,7 @@ struct CoulShared {
   uint16_t hbase[kCoulMaxE + 1];    // first bucket of each cell
   uint8_t hlog[kCoulMaxE];          // log2 of the cell's bucket count
   uint16_t ord[kCoulMaxE];          // members bucket by bucket
-  uint32_t npair, ntri;
+  uint32_t lead[kEPT * (kCB / 64)];  // leaders per (pass, wavefront): pairs | triplets << 16
   uint32_t wsum[kCB / 64];
 };
 
@@ -180,10 +180,6 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     return;
   }
   uint32_t *flags = sh.r1;
-  if (tid == 0) {
-    sh.npair = 0u;
-    sh.ntri = 0u;
-  }
   // 1. coalesced loads: cell, pool flag, pairing key
   bool pool[kEPT];
   uint32_t key[kEPT];
@@ -283,34 +279,59 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     }
   }
   __syncthreads();
-  // 9. pool order (element of every pool position)
+  // 9. pool order (element of every pool position), and the pair and
+  //    triplet leaders counted per pass and wavefront for step 10 (one
+  //    barrier for both)
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int i = tid + k * kCB;
     if (i < ns && pool[k]) sh.ord[pos[k]] = (uint16_t)i;
   }
-  __syncthreads();
-  // 10. pair leaders write their work items into the chunk's own list region:
-  //     pairs first, then the odd pools' triplets (order within each part is
-  //     that of LDS atomics; the items are disjoint, so it does not matter)
+  const int lane = tid & 63, wv = tid >> 6;
+  const int nk = (ns + kCB - 1) / kCB;  // passes that hold slots of the chunk
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   int lt[kEPT], li[kEPT];
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int i = tid + k * kCB;
     lt[k] = 0;
     li[k] = 0;
-    if (i < ns && pool[k]) {
-      const int m = mm[k], r = rr[k];
-      if (m >= 2) {
-        if ((m & 1) && r == 0) lt[k] = 2;                              // triplet
-        else if ((m & 1) ? (r >= 3 && (r & 1)) : !(r & 1)) lt[k] = 1;  // pair
+    if (k < nk) {  // uniform over the workgroup
+      if (i < ns && pool[k]) {
+        const int m = mm[k], r = rr[k];
+        if (m >= 2) {
+          if ((m & 1) && r == 0) lt[k] = 2;                              // triplet
+          else if ((m & 1) ? (r >= 3 && (r & 1)) : !(r & 1)) lt[k] = 1;  // pair
+        }
       }
-      if (lt[k] == 1) li[k] = (int)atomicAdd(&sh.npair, 1u);
-      if (lt[k] == 2) li[k] = (int)atomicAdd(&sh.ntri, 1u);
+      const uint64_t bp = __ballot(lt[k] == 1), bt = __ballot(lt[k] == 2);
+      li[k] = __popcll((lt[k] == 2 ? bt : bp) & below);
+      if (lane == 0) sh.lead[k * (kCB / 64) + wv] = (uint32_t)__popcll(bp) | ((uint32_t)__popcll(bt) << 16);
     }
   }
   __syncthreads();
-  const int np = (int)sh.npair;
+  // 10. pair leaders write their work items into the chunk's own list region:
+  //     pairs first, then the odd pools' triplets, each numbered in the slot
+  //     order of its leader, hence cell by cell: the chunk's first pair
+  //     wavefront then takes the cells at its front and the second those at
+  //     its back, so the two share few cache lines of the state (the items
+  //     are disjoint, so their order does not change any particle)
+  // exclusive scan of the leader counts in (pass, wavefront) order, which is
+  // slot order; pairs and triplets side by side in one word (each at most
+  // kCoulItems, so the low half never carries into the high one)
+  constexpr int kLead = kEPT * (kCB / 64);
+  const uint32_t c = lane < nk * (kCB / 64) ? sh.lead[lane] : 0u;
+  uint32_t incl = c;
+#pragma unroll
+  for (int o = 1; o < kLead; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t tot = __shfl(incl, kLead - 1, 64);
+  const int np = (int)(tot & 0xffffu);
+  uint32_t before[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) before[k] = __shfl(incl - c, k * (kCB / 64) + wv, 64);
   CoulItem *out = items + (int64_t)blockIdx.x * kCoulItems;
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
@@ -322,10 +343,10 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
       e.c = lt[k] == 2 ? sh.ord[p + 2] : (uint16_t)0;
       e.m = (uint16_t)mm[k];
       e.id = (uint32_t)sh.skey[e.a];
-      out[lt[k] == 1 ? li[k] : np + li[k]] = e;
+      out[lt[k] == 1 ? (int)(before[k] & 0xffffu) + li[k] : np + (int)(before[k] >> 16) + li[k]] = e;
     }
   }
-  if (tid == 0) counts[blockIdx.x] = make_uint2((uint32_t)np, sh.ntri);
+  if (tid == 0) counts[blockIdx.x] = make_uint2((uint32_t)np, tot >> 16);
 }
 
 // collisions, one per lane, so that every collision of the step is in
