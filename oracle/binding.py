@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("sp", Species * MAXS), ("self_ne", C.c_int32),
                 ("lnL_ei", C.c_double), ("Te_in_eV", C.c_double), ("Te_out_eV", C.c_double),
                 ("bfield", C.POINTER(C.c_double)), ("heat_isotropic", C.c_int32),
-                ("self_n0", C.c_int32)]
+                ("self_n0", C.c_int32), ("cx_partner", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -48,7 +48,8 @@ class Tallies(C.Structure):
                 ("coul_e", C.c_double), ("fpt_n", (C.c_uint64 * MAXQ) * MAXS),
                 ("fpt_sum", (C.c_uint64 * MAXQ) * MAXS), ("fpt_hist", (C.c_uint64 * FPT_BINS) * MAXS),
                 ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS),
-                ("ionized_n", (C.c_uint64 * MAXN) * MAXS), ("elastic", (C.c_uint64 * MAXQ) * MAXS)]
+                ("ionized_n", (C.c_uint64 * MAXN) * MAXS), ("elastic", (C.c_uint64 * MAXQ) * MAXS),
+                ("cx_unmatched", C.c_uint64 * MAXS)]
 
 
 _lib = None
@@ -143,6 +144,7 @@ def make_params(p):
     P.lnL_ei = float(p.get("lnL_ei", 17.0))
     P.heat_isotropic = 1 if p.get("heat_isotropic") else 0
     P.self_n0 = 1 if p.get("self_n0") else 0
+    P.cx_partner = 1 if p.get("cx_partner") else 0
     P.Te_in_eV = float(p.get("Te_in_eV", 0.0))
     P.Te_out_eV = float(p.get("Te_out_eV", 0.0))
     return P, keep
@@ -300,4 +302,5 @@ def tallies_to_dict(t):
         extracted_r=np.array([t.extracted_r[s][:] for s in range(MAXS)], dtype=np.float64),
         lost_ke=np.array(t.lost_ke[:], dtype=np.float64),
         ionized_n=np.array([t.ionized_n[s][:] for s in range(MAXS)], dtype=np.uint64),
-        elastic=np.array([t.elastic[s][:] for s in range(MAXS)], dtype=np.uint64))
+        elastic=np.array([t.elastic[s][:] for s in range(MAXS)], dtype=np.uint64),
+        cx_unmatched=np.array(t.cx_unmatched[:], dtype=np.uint64))

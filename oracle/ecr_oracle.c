@@ -73,6 +73,7 @@ struct orc_sim {
   uint32_t *birth;  /* step the ion was made from an atom, or ORC_BIRTH_NONE */
   uint32_t *chg;    /* self-consistent electrons: ion charge per cell at the start of the step */
   uint32_t *atoms;  /* tracked neutrals: atoms per species and cell at the start of the step [s][cell] */
+  uint32_t *cxreq;  /* cx_partner: exchanges of the step per species and collision cell [s][cell] */
   /* cell order */
   uint32_t *order, *cell_off;
   int64_t step;
@@ -361,6 +362,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
   if (p->n < 0 || p->n > 0x7fffffff || p->n_species < 1 || p->n_species > ORC_MAXS) return -1;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->sort_every < 1 || !(p->dt > 0.0)) return -1;
   if ((p->process_mask & ORC_P_HEAT) && !(p->Te_in_eV > 0.0 && p->Te_out_eV > 0.0 && p->lnL_ei >= 0.0)) return -1;
+  if (p->cx_partner && !p->self_n0) return -1; /* the partners are the tracked atoms */
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   if (!s) return -2;
   s->p = *p;
@@ -437,9 +439,10 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->cell_off = calloc((size_t)s->ncell + 1, 4);
   s->chg = calloc((size_t)s->ncell, 4);
   s->atoms = calloc((size_t)s->ncell * ORC_MAXS, 4);
+  s->cxreq = calloc((size_t)s->ncell * ORC_MAXS, 4);
   for (int f = 0; f < ORC_NFIELDS; f++) s->dens[f] = calloc((size_t)s->nnode, 8);
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->q || !s->sp || !s->ev ||
-      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->chg || !s->atoms || !s->dens[0] ||
+      !s->cell || !s->order || !s->id || !s->pool || !s->pkey || !s->birth || !s->cell_off || !s->chg || !s->atoms || !s->cxreq || !s->dens[0] ||
       !s->dens[1] || !s->dens[2] || !s->dens[3]) {
     orc_destroy(s);
     return -2;
@@ -457,7 +460,7 @@ void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->x); free(s->y); free(s->z); free(s->vx); free(s->vy); free(s->vz);
   free(s->q); free(s->sp); free(s->ev); free(s->cell); free(s->order); free(s->id);
-  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off); free(s->chg); free(s->atoms);
+  free(s->pool); free(s->pkey); free(s->birth); free(s->cell_off); free(s->chg); free(s->atoms); free(s->cxreq);
   for (int f = 0; f < ORC_NFIELDS; f++) free(s->dens[f]);
   free(s);
 }
@@ -719,7 +722,9 @@ static int boundary(orc_sim *s, int64_t i, double x0, double y0, double z0) {
     s->t.lost_ke[sp] += 0.5 * s->M[sp] * v2;
   }
   uint32_t born = s->birth[i];
-  s->birth[i] = ORC_BIRTH_NONE;
+  /* with exchange partners an atom remembers the step it became one, so
+   * that a particle recycled in this step is not taken as a partner */
+  s->birth[i] = s->p.cx_partner ? (uint32_t)s->step : ORC_BIRTH_NONE;
   if (kind == X_EXT_FLANGE && xc * xc + yc * yc <= s->rap2) {
     s->t.extracted[sp][Q]++;
     s->t.recycled++;
@@ -927,6 +932,17 @@ static int mcc(orc_sim *s, int64_t i) {
   }
   if (u < pt) {
     s->t.cx[sp][Q]++;
+    if (s->p.cx_partner) {
+      /* the electron comes from a tracked atom of the ion's collision cell,
+       * chosen at the end of the step; a Q = 1 ion is now an atom and keeps
+       * its velocity (resonant: no energy is released) */
+      s->cxreq[(int64_t)sp * s->ncell + s->cell[i]]++;
+      if (Q == 1) {
+        s->q[i] = 0;
+        s->birth[i] = (uint32_t)s->step;
+        return ORC_EV_CX;
+      }
+    }
     /* resonant exchange hands the charge to the neutral: a new ion */
     if (Q == 1) s->birth[i] = (uint32_t)s->step;
     double w[3];
@@ -948,6 +964,72 @@ static int mcc(orc_sim *s, int64_t i) {
     return ORC_EV_ELASTIC;
   }
   return ORC_EV_NONE;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exchange partners (cx_partner): at the end of the step, in each collision */
+/* cell, the exchanges of species s take tracked atoms of species s that     */
+/* did not become atoms in this step, in the order of (key, id), key = word  */
+/* 3 of the particle's STEP draw; each becomes a Q = 1 ion born in the step. */
+/* Exchanges left without an atom are counted.                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  uint32_t group; /* species * ncell + cell */
+  uint32_t key, id;
+  int64_t i;
+} partner_cand;
+
+static int cmp_cand(const void *a, const void *b) {
+  const partner_cand *x = a, *y = b;
+  if (x->group != y->group) return x->group < y->group ? -1 : 1;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->id != y->id) return x->id < y->id ? -1 : 1;
+  return 0;
+}
+
+static void match_partners(orc_sim *s) {
+  int64_t nc = 0;
+  for (int64_t i = 0; i < s->N; i++)
+    if (s->q[i] == 0 && s->birth[i] != (uint32_t)s->step && s->cxreq[(int64_t)s->sp[i] * s->ncell + s->cell[i]])
+      nc++;
+  partner_cand *c = malloc(sizeof(partner_cand) * (size_t)(nc > 0 ? nc : 1));
+  int64_t k = 0;
+  for (int64_t i = 0; i < s->N; i++) {
+    int64_t g = (int64_t)s->sp[i] * s->ncell + s->cell[i];
+    if (s->q[i] == 0 && s->birth[i] != (uint32_t)s->step && s->cxreq[g]) {
+      uint32_t W[4];
+      draw(s, s->id[i], (uint32_t)s->step, S_STEP, 0, W);
+      c[k].group = (uint32_t)g;
+      c[k].key = W[3];
+      c[k].id = s->id[i];
+      c[k].i = i;
+      k++;
+    }
+  }
+  qsort(c, (size_t)nc, sizeof(partner_cand), cmp_cand);
+  /* walk each group: its first cxreq[group] candidates become ions */
+  for (int64_t a = 0; a < nc;) {
+    int64_t b = a;
+    while (b < nc && c[b].group == c[a].group) b++;
+    uint32_t want = s->cxreq[c[a].group];
+    for (int64_t t = a; t < b && (uint32_t)(t - a) < want; t++) {
+      int64_t i = c[t].i;
+      s->q[i] = 1;
+      s->birth[i] = (uint32_t)s->step;
+      s->ev[i] = ORC_EV_CX_PARTNER;
+    }
+    if ((int64_t)want > b - a) s->t.cx_unmatched[c[a].group / s->ncell] += (uint64_t)want - (uint64_t)(b - a);
+    s->cxreq[c[a].group] = 0;
+    a = b;
+  }
+  /* groups with requests and no candidate at all */
+  for (int64_t g = 0; g < s->ncell * s->p.n_species; g++) {
+    if (s->cxreq[g]) {
+      s->t.cx_unmatched[g / s->ncell] += s->cxreq[g];
+      s->cxreq[g] = 0;
+    }
+  }
+  free(c);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1033,6 +1115,7 @@ int orc_step(orc_sim *s, int64_t n_steps) {
         s->t.anomalies++;
     }
     if (pm & ORC_P_DEPOSIT) deposit(s);
+    if (s->p.cx_partner) match_partners(s);
     s->step++;
     s->t.steps++;
   }

@@ -48,6 +48,7 @@ extern "C" {
 #define ORC_EV_WALL 3
 #define ORC_EV_EXTRACT 4
 #define ORC_EV_ELASTIC 5
+#define ORC_EV_CX_PARTNER 6 /* an atom made an ion as the partner of an exchange (cx_partner) */
 
 typedef struct {
   double mass_amu;
@@ -86,6 +87,9 @@ typedef struct {
   int32_t heat_isotropic;     /* 1: the heating kick without its diamagnetic bias (Sec. IV ablation) */
   int32_t self_n0;            /* 1: the neutral density of charge exchange and elastic scattering is that of the
                                  tracked atoms of the species in the ion's cell, not the species' n0 */
+  int32_t cx_partner;         /* 1 (needs self_n0): every charge exchange ionises a tracked atom of the ion's
+                                 species and collision cell at the end of the step; a Q = 1 ion becomes an
+                                 atom with its own velocity */
 } orc_params;
 
 typedef struct {
@@ -111,6 +115,7 @@ typedef struct {
   double lost_ke[ORC_MAXS];             /* kinetic energy of ions (Q >= 1) lost to walls and aperture, J */
   uint64_t ionized_n[ORC_MAXS][ORC_MAXN];  /* ionisations by electrons removed ([n-1]) */
   uint64_t elastic[ORC_MAXS][ORC_MAXQ];    /* elastic ion-atom collisions, by charge */
+  uint64_t cx_unmatched[ORC_MAXS];         /* cx_partner: exchanges that found no atom in their cell */
 } orc_tallies;
 
 typedef struct orc_sim orc_sim;

@@ -3,7 +3,8 @@
  * sorts, Coulomb pools (pairs and triplets), push with an E grid and a
  * magnetic map, walls and the aperture, ionisation Q -> Q+n, charge
  * exchange, elastic scattering, the heating kick with self-consistent
- * electrons, the tracked-neutral density (second pass), all four density
+ * electrons, the tracked-neutral density and exchange partners (second
+ * pass), all four density
  * fields, state round trips and a second species.  Prints the tallies' totals; exits non-zero on an API error. */
 #include <math.h>
 #include <stdio.h>
@@ -59,6 +60,7 @@ int main(void) {
     p.bfield = pass ? bf : NULL;
     p.heat_isotropic = pass;
     p.self_n0 = pass;
+    p.cx_partner = pass; /* exchange partners taken from the tracked atoms */
     /* the tracked atoms give about 1e18 m^-3 here: raise the cross-sections
      * so exchange and elastic scattering still occur, keeping n0 sigma */
     for (int k = 0; k < 2; k++) {

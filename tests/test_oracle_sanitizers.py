@@ -3,7 +3,7 @@
 A small C driver (tests/sanitize/oracle_driver.c) runs every process of the
 oracle, with two species, an E grid, a magnetic map, self-consistent
 electrons, the heating kick and (second pass) the tracked-neutral
-density, sorts every 7 steps and round-trips the
+density and exchange partners, sorts every 7 steps and round-trips the
 state; the build aborts on the first invalid access, leak or undefined
 operation.  Host code only, built with gcc.
 """

@@ -31,6 +31,7 @@ P_HEAT = 32  # electron-ion heating kick (not in P_ALL: the fixed-background ste
 P_ELASTIC = 64  # elastic ion-atom scattering (not in P_ALL)
 MAXN = 4  # electrons removed by one ionisation, 1..MAXN
 EV_ELASTIC = 5
+EV_CX_PARTNER = 6  # a tracked atom made an ion as the partner of an exchange
 
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P = 0, 1, 2, 3
 
