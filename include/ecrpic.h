@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ECR_ABI_VERSION 5u
+#define ECR_ABI_VERSION 6u
 #define ECR_MAX_SPECIES 4
 #define ECR_MAX_Q 32          /* charge-state slots per species: Q = 0..31 */
 #define ECR_MAX_NION 4        /* electrons one ionisation may remove: Q -> Q+n, n = 1..4 */
@@ -99,13 +99,31 @@ enum {
                           ionisation probability is n_e k_Q dt (ne_in/ne_out only bound the dt check) */
   ECR_FLAG_HEAT_ISOTROPIC = 8, /* the heating kick without its diamagnetic bias (delta = 0): the paper's
                                   ablation that switches off the plasma diffusion by e-i collisions (Sec. IV) */
-  ECR_FLAG_SELF_N0 = 16 /* the neutral gas of charge exchange and elastic scattering is the tracked atoms (Sec. II):
+  ECR_FLAG_SELF_N0 = 16, /* the neutral gas of charge exchange and elastic scattering is the tracked atoms (Sec. II):
                            n0 = weight x (atoms of the ion's species in its cell at the start of the step) / cell
                            volume, instead of the species' uniform n0_m3 (which then only bounds the dt check) */
+  ECR_FLAG_CX_PARTNER = 32 /* needs ECR_FLAG_SELF_N0.  Every charge exchange takes its electron from a tracked atom
+                              (Sec. II): at the end of the step, in each collision cell (the cell at the last sort),
+                              the exchanges of species s ionise that many atoms of species s, picked in the order
+                              of (word 3 of the particle's Philox stream-1 draw, id) among the cell's atoms that did
+                              not become atoms in this step; each becomes a Q = 1 ion born in the step
+                              (ECR_EV_CX_PARTNER).  A Q = 1 ion that exchanges becomes an atom with its own velocity;
+                              Q >= 2 exchanges are as without the flag.  Exchanges left without an atom are counted
+                              in cx_unmatched.  The density of the step is deposited before the partners change.
+                              With this flag an atom's birth is the step it became one (walls, aperture, resonant
+                              exchange) instead of ECR_BIRTH_NONE. */
 };
 
 /* event codes returned by ecr_event_log */
-enum { ECR_EV_NONE = 0, ECR_EV_IONIZE = 1, ECR_EV_CX = 2, ECR_EV_WALL = 3, ECR_EV_EXTRACT = 4, ECR_EV_ELASTIC = 5 };
+enum {
+  ECR_EV_NONE = 0,
+  ECR_EV_IONIZE = 1,
+  ECR_EV_CX = 2,
+  ECR_EV_WALL = 3,
+  ECR_EV_EXTRACT = 4,
+  ECR_EV_ELASTIC = 5,
+  ECR_EV_CX_PARTNER = 6 /* an atom made a Q = 1 ion as the partner of an exchange (ECR_FLAG_CX_PARTNER) */
+};
 
 /* One ion species (the paper models argon, Sec. II; a second species is allowed). */
 typedef struct {
@@ -187,6 +205,7 @@ typedef struct {
   double lost_ke[ECR_MAX_SPECIES];                  /* kinetic energy of the ions (Q >= 1) lost to the walls and the aperture, J */
   uint64_t ionized_n[ECR_MAX_SPECIES][ECR_MAX_NION];/* ionisation events by electrons removed ([n-1]) */
   uint64_t elastic[ECR_MAX_SPECIES][ECR_MAX_Q];     /* elastic ion-atom collisions, by charge */
+  uint64_t cx_unmatched[ECR_MAX_SPECIES];           /* ECR_FLAG_CX_PARTNER: exchanges that found no atom in their cell */
 } ecr_tallies;
 
 /* Host particle arrays indexed by particle id (length n). */

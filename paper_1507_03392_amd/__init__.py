@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libecrpic.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 MAXS, MAXQ = 4, 32
 MAXN = 4  # electrons one ionisation may remove
 FPT_BINS = 32
@@ -23,7 +23,7 @@ BIRTH_NONE = 0xFFFFFFFF
 FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL, P_HEAT, P_ELASTIC = 1, 2, 4, 8, 16, 31, 32, 64
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P, N_FIELDS = 0, 1, 2, 3, 4
-FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE, FLAG_HEAT_ISOTROPIC, FLAG_SELF_N0 = 1, 2, 4, 8, 16
+FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE, FLAG_HEAT_ISOTROPIC, FLAG_SELF_N0, FLAG_CX_PARTNER = 1, 2, 4, 8, 16, 32
 K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, N_KERNELS = 0, 1, 2, 3, 4, 5, 6
 KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_pairs"]
 
@@ -74,7 +74,8 @@ class Tallies(C.Structure):
                 ("coul_e", C.c_double), ("fpt_n", (C.c_uint64 * MAXQ) * MAXS),
                 ("fpt_sum", (C.c_uint64 * MAXQ) * MAXS), ("fpt_hist", (C.c_uint64 * FPT_BINS) * MAXS),
                 ("extracted_r", (C.c_double * MAXQ) * MAXS), ("lost_ke", C.c_double * MAXS),
-                ("ionized_n", (C.c_uint64 * MAXN) * MAXS), ("elastic", (C.c_uint64 * MAXQ) * MAXS)]
+                ("ionized_n", (C.c_uint64 * MAXN) * MAXS), ("elastic", (C.c_uint64 * MAXQ) * MAXS),
+                ("cx_unmatched", C.c_uint64 * MAXS)]
 
 
 class StateView(C.Structure):
@@ -136,7 +137,7 @@ def make_params(p, events=False, split=False):
     P.deposit_mask = p["deposit_mask"]
     P.flags = (FLAG_EVENTS if events else 0) | (FLAG_SPLIT if split else 0) | \
         (FLAG_SELF_NE if p.get("self_ne") else 0) | (FLAG_HEAT_ISOTROPIC if p.get("heat_isotropic") else 0) | \
-        (FLAG_SELF_N0 if p.get("self_n0") else 0)
+        (FLAG_SELF_N0 if p.get("self_n0") else 0) | (FLAG_CX_PARTNER if p.get("cx_partner") else 0)
     P.sort_every = p["sort_every"]
     P.seed = p["seed"]
     P.n_particles = p["n"]
@@ -201,7 +202,8 @@ def tallies_to_dict(t):
                 anomalies=int(t.anomalies), steps=int(t.steps), coul_dp=np.array(t.coul_dp[:]),
                 coul_de=float(t.coul_de), coul_e=float(t.coul_e), fpt_n=g(t.fpt_n), fpt_sum=g(t.fpt_sum),
                 fpt_hist=g(t.fpt_hist), extracted_r=d(t.extracted_r), lost_ke=np.array(t.lost_ke[:]),
-                ionized_n=g(t.ionized_n), elastic=g(t.elastic))
+                ionized_n=g(t.ionized_n), elastic=g(t.elastic),
+                cx_unmatched=np.array(t.cx_unmatched[:], dtype=np.uint64))
 
 
 class Run:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libecrpic.so")
-SOURCES = ["runtime.hip", "k_particles.hip", "k_coulomb.hip", "k_sort.hip"]
+SOURCES = ["runtime.hip", "k_particles.hip", "k_coulomb.hip", "k_sort.hip", "k_partner.hip"]
 ARCH = os.environ.get("ECR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

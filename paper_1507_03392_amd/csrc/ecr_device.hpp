@@ -24,7 +24,7 @@ constexpr double kWallEps = 1e-9;            // re-emission offset from a wall, 
 // Philox stream ids (counter word 2); word 0 = particle id, word 1 = step,
 // word 3 = call index within the stream.
 enum : uint32_t { S_INIT = 0, S_STEP = 1, S_COUL = 2, S_BND = 3, S_CX = 4, S_HEAT = 5, S_EL = 6 };
-enum : uint8_t { EV_NONE = 0, EV_IONIZE = 1, EV_CX = 2, EV_WALL = 3, EV_EXTRACT = 4, EV_ELASTIC = 5 };
+enum : uint8_t { EV_NONE = 0, EV_IONIZE = 1, EV_CX = 2, EV_WALL = 3, EV_EXTRACT = 4, EV_ELASTIC = 5, EV_CX_PARTNER = 6 };
 enum : uint32_t { P_PUSH = 1, P_IONIZE = 2, P_CX = 4, P_COULOMB = 8, P_DEPOSIT = 16, P_HEAT = 32, P_ELASTIC = 64 };
 
 // Nanbu A(s) table: ln A at s = 2^e (1 + j/K), e in [kAeLo, kAeHi], j in [0, K)
@@ -50,6 +50,10 @@ struct KParams {
   // 2.38e-6 sqrt(T_e) (the electron Larmor radius times |B|)
   double ne_zone[2], rl_zone[2];
   const double *bmap;  // device [3][nnode] node magnetic field (T), or null: the analytic field
+  // exchange partners (ECR_FLAG_CX_PARTNER): the exchanges of the step per
+  // species and collision cell [s][cell], and each slot's collision cell
+  uint32_t *cxreq;
+  const uint32_t *cellid;
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
   double cel[kMaxS];     // n0 sigma_el1 dt (elastic ion-atom scattering)
   double sdt_cx[kMaxS], sdt_el[kMaxS];  // sigma1 dt, sigma_el1 dt: neutrals from the tracked atoms

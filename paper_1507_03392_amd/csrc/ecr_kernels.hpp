@@ -17,7 +17,7 @@ constexpr int kCoulMaxE = 1024;
 static_assert(kBirthNone == ECR_BIRTH_NONE, "birth sentinel");
 
 // Error bits raised by kernels (read back with the tallies).
-enum : uint32_t { ERR_COUL_OVERFLOW = 1 };
+enum : uint32_t { ERR_COUL_OVERFLOW = 1, ERR_PARTNER_OVERFLOW = 2 };
 
 struct DevAccum {
   ecr_tallies t;           // steps field unused on the device
@@ -44,6 +44,14 @@ template <typename R>
 void launch_push(const KParams &P, const Tables *T, Soa<R> S, const double *ef, uint8_t *evlog,
                  DevAccum *acc, double *dens, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next,
                  hipStream_t st);
+
+// exchange partners (ECR_FLAG_CX_PARTNER): per Coulomb chunk, the atoms of
+// each requesting collision cell become ions in (key, id) order; chg is the
+// next step's cell grids, updated for the new charges; the requests are
+// cleared
+template <typename R>
+void launch_cx_partner(const KParams &P, Soa<R> S, const uint32_t *chunk_lo, uint32_t *chg, uint8_t *evlog,
+                       DevAccum *acc, StepArg step, hipStream_t st);
 
 // ion charge per cell of the current state, added into chg (zeroed before)
 template <typename R>

@@ -187,7 +187,10 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
       } else {
         atomicAdd((unsigned long long *)&acc->t.wall[s][Q], 1ull);
       }
-      if (Q >= 1) birth[j] = kBirthNone;  // now an atom
+      // now an atom; with exchange partners an atom's birth is the step it
+      // became one, so that it is no partner in this step
+      if (EXT && (P.flags & ECR_FLAG_CX_PARTNER)) birth[j] = step;
+      else if (Q >= 1) birth[j] = kBirthNone;
       Q = 0;
     }
   }
@@ -280,13 +283,25 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
       ev = EV_IONIZE;
     } else if (u < pt) {
       atomicAdd((unsigned long long *)&acc->t.cx[s][Q], 1ull);
-      if (Q == 1) birth[j] = step;  // resonant exchange: the ion is the former neutral
-      cx_outcome<R>(P, id, step, s, Q, vx, vy, vz);
-      if (Q >= 2) {
-        Q = Q - 1;
-        atomicAdd((unsigned long long *)&acc->t.cx_products[s], 1ull);
-      }
       ev = EV_CX;
+      if (P.flags & ECR_FLAG_CX_PARTNER) {
+        // the electron comes from a tracked atom of the collision cell,
+        // picked at the end of the step; a Q = 1 ion is an atom from now
+        // on and keeps its velocity
+        atomicAdd(&P.cxreq[(uint32_t)s * P.ncell + P.cellid[j]], 1u);
+        if (Q == 1) {
+          birth[j] = step;
+          Q = 0;
+        }
+      }
+      if (Q >= 1) {
+        if (Q == 1) birth[j] = step;  // resonant exchange: the ion is the former neutral
+        cx_outcome<R>(P, id, step, s, Q, vx, vy, vz);
+        if (Q >= 2) {
+          Q = Q - 1;
+          atomicAdd((unsigned long long *)&acc->t.cx_products[s], 1ull);
+        }
+      }
     } else if (u < pall) {
       atomicAdd((unsigned long long *)&acc->t.elastic[s][Q], 1ull);
       elastic_outcome<R>(P, id, step, s, vx, vy, vz);

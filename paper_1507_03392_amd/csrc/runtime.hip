@@ -33,6 +33,7 @@ struct Layout {
   size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, bfield,
       evlog;
   size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
+  size_t cxreq;   // exchanges per species and collision cell (ECR_FLAG_CX_PARTNER)
   size_t total;
 };
 
@@ -95,6 +96,8 @@ Layout make_layout(const ecr_params *p) {
     if (p->flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0))
       o = align_up(o + 4 * (size_t)ncells(p) * (size_t)(1 + p->n_species));
   }
+  L.cxreq = o;
+  if (p->flags & ECR_FLAG_CX_PARTNER) o = align_up(o + 4 * (size_t)ncells(p) * (size_t)p->n_species);
   L.total = o + kAlign;  // slack so the arena base may be realigned
   return L;
 }
@@ -275,7 +278,9 @@ std::string validate(const ecr_params *p) {
     return "negative weight, Coulomb logarithm or temperature";
   if (p->ne_in_m3 < 0.0 || p->ne_out_m3 < 0.0) return "negative electron density";
   if (p->process_mask >= 128u) return "process_mask has unknown bits";
-  if (p->flags >= 32u) return "flags has unknown bits";
+  if (p->flags >= 64u) return "flags has unknown bits";
+  if ((p->flags & ECR_FLAG_CX_PARTNER) && !(p->flags & ECR_FLAG_SELF_N0))
+    return "ECR_FLAG_CX_PARTNER needs ECR_FLAG_SELF_N0 (the partners are the tracked atoms)";
   if ((p->flags & ECR_FLAG_SELF_N0) && (int64_t)ncells(p) * (1 + p->n_species) >= (1LL << 32) - 1)
     return "mesh too large for the per-species atom grids";
   if ((p->process_mask & ECR_P_HEAT) &&
@@ -537,6 +542,14 @@ void do_step(ecr_run *r, StepArg stepw) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit_pressure<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
   }
+  if (r->kp.cxreq) {
+    // exchange partners, after the deposit; chg_par now names the grids of
+    // the next step, which the partners' new charges update
+    launch_cx_partner<R>(r->kp, soa<R>(r, r->cur), at<uint32_t>(r, r->L.chunks),
+                         at<uint32_t>(r, r->L.chg[r->chg_par]),
+                         (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc, stepw,
+                         r->stream);
+  }
   if (dep) r->dens_steps++;
   r->step++;
   r->steps++;
@@ -557,6 +570,7 @@ void zero_accumulators(ecr_run *r) {
   launch_fill_f64(at<double>(r, r->L.dens), 0.0, (int64_t)ECR_N_FIELDS * r->nnode, r->stream);
   launch_fill_u32(at<uint32_t>(r, r->L.acc), 0u, (int64_t)(sizeof(DevAccum) / 4), r->stream);
   launch_fill_f64(at<double>(r, r->L.moments), 0.0, 5 * coul_moment_slots(r->kp.n > 0 ? r->kp.n : 1), r->stream);
+  if (r->kp.cxreq) launch_fill_u32(r->kp.cxreq, 0u, r->ncell * r->p.n_species, r->stream);
   r->steps = 0;
   r->dens_steps = 0;
 }
@@ -698,6 +712,8 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   r->p.efield_nodes = params->efield_nodes ? (const double *)1 : nullptr;  // only its presence is kept
   r->p.bfield_nodes = nullptr;  // the kernels read the arena copy through kp.bmap
   r->kp.bmap = params->bfield_nodes ? at<double>(r, L.bfield) : nullptr;
+  r->kp.cellid = at<uint32_t>(r, L.cellid);
+  r->kp.cxreq = (params->flags & ECR_FLAG_CX_PARTNER) ? at<uint32_t>(r, L.cxreq) : nullptr;
   zero_accumulators(r);
   *out = r;
   return ECR_OK;
@@ -829,6 +845,10 @@ ecr_status ecr_read_tallies(ecr_run *r, ecr_tallies *out) {
   out->steps = r->steps;
   if (h.err & ERR_COUL_OVERFLOW) {
     r->err = "a Coulomb chunk exceeded the LDS capacity; its cells were skipped";
+    out->anomalies += 1;
+  }
+  if (h.err & ERR_PARTNER_OVERFLOW) {
+    r->err = "an exchange-partner chunk exceeded the LDS capacity; its exchanges found no partner";
     out->anomalies += 1;
   }
   if (out->anomalies > 0) return fail(r, ECR_ENUMERIC, r->err.empty() ? "anomalies counted" : r->err);

@@ -27,7 +27,7 @@ def _same(a, b, what):
     assert sa["step"] == sb["step"]
     assert np.array_equal(a.events(), b.events()), what
     ta, tb = a.tallies(), b.tallies()
-    for k in ("extracted", "wall", "ionized", "cx", "cx_products"):
+    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "cx_unmatched"):
         assert np.array_equal(ta[k], tb[k]), f"{what}: {k}"
     for k in ("recycled", "anomalies", "steps"):
         assert ta[k] == tb[k], f"{what}: {k}"
@@ -96,11 +96,13 @@ def test_graph_self_consistent_electrons_odd_period(heat):
         _same(a, b, f"after {a.get_state()['step']} steps")
 
 
-def test_graph_tracked_neutrals_odd_period():
-    # the cell grids (ion charge and atoms) alternate buffers every step
+@pytest.mark.parametrize("partner", [False, True])
+def test_graph_tracked_neutrals_odd_period(partner):
+    # the cell grids (ion charge and atoms) alternate buffers every step;
+    # with exchange partners a kernel after the push edits the next grid
     import torch
     params = W.with_(W.base_params(20_011, 16, 16, 32, seed=7), sort_every=15, self_n0=True, self_ne=True,
-                     process_mask=W.P_ALL | W.P_ELASTIC, weight=1e12, dt=2e-9)
+                     process_mask=W.P_ALL | W.P_ELASTIC, weight=1e12, dt=2e-9, cx_partner=partner)
     params["species"] = [W.with_extended_mcc(dict(params["species"][0], n0=2e19))]
     st = W.random_state(params, seed=70, q_max=8, v_ev=40.0, frac_atoms=0.5)
     stream = torch.cuda.Stream()

@@ -44,7 +44,8 @@ def assert_state_close(a, b, params, ids=None, what="", tol=XTOL):
 
 
 def assert_tallies_equal(tg, to, what=""):
-    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "fpt_n", "fpt_sum", "fpt_hist", "ionized_n", "elastic"):
+    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "fpt_n", "fpt_sum", "fpt_hist", "ionized_n", "elastic",
+              "cx_unmatched"):
         assert np.array_equal(tg[k], to[k]), f"{what}: tally {k} differs"
     for k in ("recycled", "anomalies", "steps"):
         assert tg[k] == to[k], f"{what}: {k} {tg[k]} vs {to[k]}"
@@ -138,6 +139,11 @@ CASES = {
     "cx_self_n0": dict(mask=W.P_CX | W.P_ELASTIC, v_ev=50.0, self_n0=True, weight=1e13, ext=True, fa=0.5),
     "all_self_n0_ne": dict(mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True,
                            self_n0=True, weight=4e12, ext=True, n0=5e18),
+    # every exchange ionises a tracked atom of the ion's collision cell
+    "cx_partner": dict(mask=W.P_CX | W.P_ELASTIC, v_ev=50.0, self_n0=True, weight=1e13, ext=True, fa=0.5,
+                       cx_partner=True),
+    "all_cx_partner_ne": dict(mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True,
+                              self_n0=True, weight=4e12, ext=True, n0=5e18, fa=0.5, cx_partner=True),
     # every process with a magnetic field map (the kick reads |B| at cell centres from it)
     "map_all_heat_self_ne": dict(mask=W.P_ALL | W.P_HEAT, v_ev=200.0, dt=5e-9, rf=0.9995, self_ne=True, weight=4e12,
                                  bmap=True),
@@ -151,7 +157,7 @@ def test_single_step_parity(case, seed):
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=seed), n0=c.get("n0", 2e19))
     params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=c.get("dm", 15), weight=c.get("weight", 4e9),
                   self_ne=c.get("self_ne", False), heat_isotropic=c.get("heat_isotropic", False),
-                  self_n0=c.get("self_n0", False))
+                  self_n0=c.get("self_n0", False), cx_partner=c.get("cx_partner", False))
     # a large zone with a dense electron background so ionisation fires in one step
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     if c.get("ext"):
@@ -178,8 +184,11 @@ def test_single_step_parity(case, seed):
         assert to["ionized_n"][0][1:].sum() > 0 and (ev == W.EV_IONIZE).sum() > 5
     if case in ("elastic", "all_extended", "extended_self_ne", "cx_self_n0", "all_self_n0_ne"):
         assert (ev == W.EV_ELASTIC).sum() > 10
-    if case == "cx_self_n0":
+    if case in ("cx_self_n0", "cx_partner"):
         assert (ev == W.EV_CX).sum() > 10
+    if case in ("cx_partner", "all_cx_partner_ne"):
+        assert (ev == W.EV_CX_PARTNER).sum() > 5
+        assert (ev == W.EV_WALL).sum() > 20 or case == "cx_partner"
     if case in ("heat", "heat_self_ne", "heat_iso_self_ne"):
         kicked = (b["vx"] != st["vx"]).sum()
         assert kicked > 2000, kicked
@@ -332,6 +341,31 @@ def test_multi_step_c1_extended_mcc():
     tg, to = g.tallies(), o.tallies()
     assert_tallies_equal(tg, to, "c1 extended")
     assert to["elastic"].sum() > 15 and to["ionized_n"][0][1:].sum() > 5
+
+
+def test_multi_step_exchange_partners():
+    # tracked exchange partners over 60 steps and three sorts, with every
+    # process on: partners, unmatched exchanges and births bit for bit
+    params = boosted(W.base_params(20_011, 16, 16, 32, seed=8))
+    params["species"] = [W.with_extended_mcc(params["species"][0])]
+    params.update(process_mask=W.P_ALL | W.P_ELASTIC | W.P_HEAT, self_ne=True, self_n0=True, cx_partner=True,
+                  weight=1e12, sort_every=20, dt=2e-9, zone_a=0.03, zone_c=0.14)
+    st = W.random_state(params, seed=81, q_max=8, v_ev=40.0, frac_atoms=0.5)
+    g = gpu_run(params, events=True)
+    g.set_state(st, step=0)
+    o = oracle(params)
+    o.set_state(st, step=0)
+    partners = 0
+    for chunk in (1, 29, 30):
+        g.step(chunk)
+        o.step(chunk)
+        a, b = g.get_state(), o.get_state()
+        assert np.array_equal(g.events(), o.events())
+        partners += int((o.events() == W.EV_CX_PARTNER).sum())
+        assert_state_close(a, b, params, what=f"exchange partners step {a['step']}", tol=1e-9)
+    to = o.tallies()
+    assert_tallies_equal(g.tallies(), to, "exchange partners")
+    assert to["cx"].sum() > 20 and partners > 0
 
 
 def test_multi_step_tracked_neutrals_and_electrons():

@@ -63,11 +63,15 @@ def test_footprint_and_parameter_checks():
     with pytest.raises(ecr.EcrError, match="process_mask"):
         ecr.footprint(W.with_(p, process_mask=128))
     P, _keep = ecr.make_params(p)
-    P.flags = 32
+    P.flags = 64
     import ctypes as C
     n = C.c_size_t()
     assert ecr.lib().ecr_footprint(C.byref(P), C.byref(n)) == -1
     assert b"flags" in ecr.lib().ecr_last_error(None)
+    # exchange partners are tracked atoms: the switch needs tracked neutrals
+    with pytest.raises(ecr.EcrError, match="SELF_N0"):
+        ecr.footprint(W.with_(p, cx_partner=True))
+    assert ecr.footprint(W.with_(p, cx_partner=True, self_n0=True)) > nb
     P, _keep = ecr.make_params(p)
     P.abi_version = 99
     import ctypes as C
