@@ -40,6 +40,8 @@ def describe(name, p):
         "fixed electron background"
     if p.get("self_n0"):
         ne += ", neutrals from the tracked atoms per cell"
+    if p.get("cx_partner"):
+        ne += ", each charge exchange ionises a tracked atom"
     return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, {ne}, "
             f"mesh {p['nx']}x{p['ny']}x{p['nz']}, dt {p['dt']:g} s, sort every {p['sort_every']}, "
             f"all processes on" + (", with the electron-ion heating kick" if p["process_mask"] & 32 else ""))
@@ -60,6 +62,9 @@ ALG_BYTES_FP64 = {
     "sort": (24 + 8) + (57 + 8) + (57 + 4),
     # push + deposit in one kernel: the deposit reads nothing more from HBM
     "push_deposit": 48 + 1 + 4 + 48 + 1,
+    # exchange partners: read each slot's collision cell, qs and birth (the
+    # requesting cells' atoms add a few bytes more)
+    "cx_partner": 4 + 1 + 4,
 }
 ALG_BYTES_FP32 = {
     "push": 24 + 1 + 4 + 24 + 1,
@@ -68,6 +73,7 @@ ALG_BYTES_FP32 = {
     "deposit": 12 + 1,
     "sort": (12 + 8) + (33 + 8) + (33 + 4),
     "push_deposit": 24 + 1 + 4 + 24 + 1,
+    "cx_partner": 4 + 1 + 4,
 }
 
 
@@ -196,6 +202,8 @@ def main():
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--self-ne", action="store_true",
                     help="electron density = ion charge density per cell (self-consistent electrons)")
+    ap.add_argument("--cx-partner", action="store_true",
+                    help="every charge exchange takes its electron from a tracked atom of the cell (implies --self-n0)")
     ap.add_argument("--self-n0", action="store_true",
                     help="neutral gas of charge exchange and elastic scattering from the tracked atoms per cell")
     ap.add_argument("--heat", action="store_true",
@@ -235,8 +243,10 @@ def main():
         params["self_ne"] = True
     if args.heat:
         params["process_mask"] |= ecr.P_HEAT
-    if args.self_n0:
+    if args.self_n0 or args.cx_partner:
         params["self_n0"] = True
+    if args.cx_partner:
+        params["cx_partner"] = True
     n = params["n"]
     fp32 = params.get("precision", 0) == ecr.FP32_MIXED
     log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")
@@ -277,7 +287,7 @@ def main():
     achieved = alg / avg_s / 1e9
     # the counters were taken on the default step (fixed electron background,
     # no optional physics, fused deposit): another configuration runs other code
-    default_step = not (args.self_ne or args.heat or args.split or args.self_n0)
+    default_step = not (args.self_ne or args.heat or args.split or args.self_n0 or args.cx_partner)
     traffic = measured_traffic(args.workload, dom) if default_step else None
 
     drift = None

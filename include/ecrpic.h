@@ -287,7 +287,8 @@ enum {
   ECR_K_DEPOSIT = 3,    /* deposit alone (ECR_FLAG_SPLIT) */
   ECR_K_FUSED = 4,      /* push + wall/aperture + ionisation/charge exchange + deposit in one kernel */
   ECR_K_COUL_PAIRS = 5, /* Coulomb scattering of the listed pairs */
-  ECR_N_KERNELS = 6
+  ECR_K_PARTNER = 6,    /* exchange partners (ECR_FLAG_CX_PARTNER) */
+  ECR_N_KERNELS = 7
 };
 ecr_status ecr_profile(ecr_run *run, int32_t enable);
 ecr_status ecr_kernel_times(ecr_run *run, double *ms_out, int64_t *launches_out);

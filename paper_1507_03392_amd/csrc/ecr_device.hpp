@@ -51,9 +51,10 @@ struct KParams {
   double ne_zone[2], rl_zone[2];
   const double *bmap;  // device [3][nnode] node magnetic field (T), or null: the analytic field
   // exchange partners (ECR_FLAG_CX_PARTNER): the exchanges of the step per
-  // species and collision cell [s][cell], and each slot's collision cell
-  uint32_t *cxreq;
-  const uint32_t *cellid;
+  // species and collision cell [s][cell], a flag per Coulomb chunk holding
+  // any, each slot's collision cell and each cell's first slot
+  uint32_t *cxreq, *cxchunk;
+  const uint32_t *cellid, *cell_off;
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
   double cel[kMaxS];     // n0 sigma_el1 dt (elastic ion-atom scattering)
   double sdt_cx[kMaxS], sdt_el[kMaxS];  // sigma1 dt, sigma_el1 dt: neutrals from the tracked atoms

@@ -288,7 +288,10 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
         // the electron comes from a tracked atom of the collision cell,
         // picked at the end of the step; a Q = 1 ion is an atom from now
         // on and keeps its velocity
-        atomicAdd(&P.cxreq[(uint32_t)s * P.ncell + P.cellid[j]], 1u);
+        const uint32_t cc = P.cellid[j];
+        atomicAdd(&P.cxreq[(uint32_t)s * P.ncell + cc], 1u);
+        // the chunk owning the cell: the one its first slot falls in
+        P.cxchunk[P.cell_off[cc] / (uint32_t)kCoulCap] = 1u;
         if (Q == 1) {
           birth[j] = step;
           Q = 0;

@@ -7,6 +7,8 @@
 // last sort).  One workgroup per Coulomb chunk (the cells whose first sorted
 // slot lies in [b*kCoulCap, (b+1)*kCoulCap)), so each cell has exactly one
 // owner:
+//  0. a chunk none of whose cells holds a request (the push flags the
+//     others) returns at once;
 //  1. every slot puts its cell in LDS; an atom that did not become one in
 //     this step (birth != step) and whose species has requests in its cell
 //     is a candidate and also puts (key, id) there, key = word 3 of its
@@ -46,7 +48,7 @@ __global__ void __launch_bounds__(kPB) k_cx_partner(KParams P, Soa<R> S, const u
   const int tid = threadIdx.x;
   const int64_t s_lo = chunk_lo[blockIdx.x];
   const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
-  if (ns <= 0) return;
+  if (ns <= 0 || P.cxchunk[blockIdx.x] == 0u) return;
   if (ns > kCoulMaxE) {
     if (tid == 0) atomicOr(&acc->err, ERR_PARTNER_OVERFLOW);
     return;
@@ -75,22 +77,33 @@ __global__ void __launch_bounds__(kPB) k_cx_partner(KParams P, Soa<R> S, const u
     }
   }
   __syncthreads();
-  // 2. the first slot of a cell settles the cell's requests
+  if (tid == 0) P.cxchunk[blockIdx.x] = 0u;  // every lane has read it
+  // 2. the first slot of a cell settles the cell's requests; it reads them
+  //    first and walks the cell only when there are any (requests are
+  //    rare, cells in the zone hold a hundred slots or more)
 #pragma unroll
   for (int k = 0; k < kPEPT; ++k) {
     const int i = tid + k * kPB;
     if (i < ns && (i == 0 || sh.cell[i - 1] != sh.cell[i])) {
       const uint32_t c = sh.cell[i];
-      int e = i + 1;
-      while (e < ns && sh.cell[e] == c) ++e;
-      for (int s = 0; s < P.nspecies; ++s) {
-        uint32_t *rq = &P.cxreq[(uint32_t)s * P.ncell + c];
-        const uint32_t r = *rq;
-        if (r == 0u) continue;
-        uint32_t m = 0u;
-        for (int t = i; t < e; ++t) m += sh.spc[t] == (uint8_t)s ? 1u : 0u;
-        if (r > m) atomicAdd((unsigned long long *)&acc->t.cx_unmatched[s], (unsigned long long)(r - m));
-        *rq = 0u;
+      uint32_t r[kMaxS];
+      bool any = false;
+#pragma unroll
+      for (int s = 0; s < kMaxS; ++s) {
+        r[s] = s < P.nspecies ? P.cxreq[(uint32_t)s * P.ncell + c] : 0u;
+        any = any || r[s] != 0u;
+      }
+      if (any) {
+        int e = i + 1;
+        while (e < ns && sh.cell[e] == c) ++e;
+#pragma unroll
+        for (int s = 0; s < kMaxS; ++s) {
+          if (r[s] == 0u) continue;
+          uint32_t m = 0u;
+          for (int t = i; t < e; ++t) m += sh.spc[t] == (uint8_t)s ? 1u : 0u;
+          if (r[s] > m) atomicAdd((unsigned long long *)&acc->t.cx_unmatched[s], (unsigned long long)(r[s] - m));
+          P.cxreq[(uint32_t)s * P.ncell + c] = 0u;
+        }
       }
     }
   }

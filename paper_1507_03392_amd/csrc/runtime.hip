@@ -34,6 +34,7 @@ struct Layout {
       evlog;
   size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
   size_t cxreq;   // exchanges per species and collision cell (ECR_FLAG_CX_PARTNER)
+  size_t cxchunk; // per Coulomb chunk: any of them in its cells
   size_t total;
 };
 
@@ -98,6 +99,8 @@ Layout make_layout(const ecr_params *p) {
   }
   L.cxreq = o;
   if (p->flags & ECR_FLAG_CX_PARTNER) o = align_up(o + 4 * (size_t)ncells(p) * (size_t)p->n_species);
+  L.cxchunk = o;
+  if (p->flags & ECR_FLAG_CX_PARTNER) o = align_up(o + 4 * (size_t)(coul_nchunks((int64_t)N) + 1));
   L.total = o + kAlign;  // slack so the arena base may be realigned
   return L;
 }
@@ -543,6 +546,7 @@ void do_step(ecr_run *r, StepArg stepw) {
     launch_deposit_pressure<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
   }
   if (r->kp.cxreq) {
+    ProfScope ps(r, ECR_K_PARTNER);
     // exchange partners, after the deposit; chg_par now names the grids of
     // the next step, which the partners' new charges update
     launch_cx_partner<R>(r->kp, soa<R>(r, r->cur), at<uint32_t>(r, r->L.chunks),
@@ -570,7 +574,10 @@ void zero_accumulators(ecr_run *r) {
   launch_fill_f64(at<double>(r, r->L.dens), 0.0, (int64_t)ECR_N_FIELDS * r->nnode, r->stream);
   launch_fill_u32(at<uint32_t>(r, r->L.acc), 0u, (int64_t)(sizeof(DevAccum) / 4), r->stream);
   launch_fill_f64(at<double>(r, r->L.moments), 0.0, 5 * coul_moment_slots(r->kp.n > 0 ? r->kp.n : 1), r->stream);
-  if (r->kp.cxreq) launch_fill_u32(r->kp.cxreq, 0u, r->ncell * r->p.n_species, r->stream);
+  if (r->kp.cxreq) {
+    launch_fill_u32(r->kp.cxreq, 0u, r->ncell * r->p.n_species, r->stream);
+    launch_fill_u32(r->kp.cxchunk, 0u, coul_nchunks(r->kp.n) + 1, r->stream);
+  }
   r->steps = 0;
   r->dens_steps = 0;
 }
@@ -714,6 +721,8 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   r->kp.bmap = params->bfield_nodes ? at<double>(r, L.bfield) : nullptr;
   r->kp.cellid = at<uint32_t>(r, L.cellid);
   r->kp.cxreq = (params->flags & ECR_FLAG_CX_PARTNER) ? at<uint32_t>(r, L.cxreq) : nullptr;
+  r->kp.cxchunk = (params->flags & ECR_FLAG_CX_PARTNER) ? at<uint32_t>(r, L.cxchunk) : nullptr;
+  r->kp.cell_off = at<uint32_t>(r, L.cell_off);
   zero_accumulators(r);
   *out = r;
   return ECR_OK;
