@@ -327,7 +327,7 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
 // kP*l .. kP*l+kP-1.  Consecutive slots share a cell almost always, so the
 // lane sums their weights in registers and flushes a run only when the cell
 // changes, into an LDS brick spanning the tile's nodes.  The lanes' last runs
-// go through a segmented sum over the wavefront, so only the first lane of
+// go through a segmented sum over the wavefront, so only the last lane of
 // each run of equal cells touches the brick; the brick goes to HBM with one
 // FP64 atomic per touched node.  A tile whose nodes do not fit the brick
 // (one spanning two planes of cells) sends the same wavefront sums to HBM.
@@ -441,19 +441,86 @@ __device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, N
   }
 }
 
-// segmented sum over the lanes of a wavefront: lanes are in slot order, so
+// Segmented sums over the lanes of a wavefront: lanes are in slot order, so
 // equal run nodes form contiguous lane segments (a lane's earlier runs were
-// flushed already); afterwards the first lane of every segment holds its total
-__device__ __forceinline__ void wave_segment_sum(int seg, double *v) {
+// flushed already).  Segmented inclusive sums over a wavefront with DPP lane moves, no LDS:
+// row_shr 1, 2, 4, 8 within each row of 16 lanes, then row_bcast 15 (the
+// last lane of rows 0 and 2 into rows 1 and 3) and row_bcast 31 (lane 31
+// into rows 2 and 3).  seg is a run id, equal exactly on runs of
+// consecutive lanes; a step adds the source lane's partial sum when the
+// source exists and lies in the same run, so after the six steps the last
+// lane of every run holds the run's total.  Called by all 64 lanes.
+struct SegSteps {
+  bool t[6];  // step i takes its source lane's partial sum
+};
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);  // disabled or missing source: old
+}
+
+__device__ __forceinline__ SegSteps seg_steps(int seg) {
+  SegSteps s;  // seg >= 0, so the -1 of a missing source never matches
+  s.t[0] = dpp_move<0x111, 0xf>(-1, seg) == seg;  // row_shr:1
+  s.t[1] = dpp_move<0x112, 0xf>(-1, seg) == seg;  // row_shr:2
+  s.t[2] = dpp_move<0x114, 0xf>(-1, seg) == seg;  // row_shr:4
+  s.t[3] = dpp_move<0x118, 0xf>(-1, seg) == seg;  // row_shr:8
+  s.t[4] = dpp_move<0x142, 0xa>(-1, seg) == seg;  // row_bcast:15 into rows 1, 3
+  s.t[5] = dpp_move<0x143, 0xc>(-1, seg) == seg;  // row_bcast:31 into rows 2, 3
+  return s;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move_d(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)dpp_move<CTRL, ROWS>(0, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)dpp_move<CTRL, ROWS>(0, (int)(uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double seg_scan(const SegSteps &s, double x) {
+  double o;
+  o = dpp_move_d<0x111, 0xf>(x);
+  x = s.t[0] ? x + o : x;
+  o = dpp_move_d<0x112, 0xf>(x);
+  x = s.t[1] ? x + o : x;
+  o = dpp_move_d<0x114, 0xf>(x);
+  x = s.t[2] ? x + o : x;
+  o = dpp_move_d<0x118, 0xf>(x);
+  x = s.t[3] ? x + o : x;
+  o = dpp_move_d<0x142, 0xa>(x);
+  x = s.t[4] ? x + o : x;
+  o = dpp_move_d<0x143, 0xc>(x);
+  x = s.t[5] ? x + o : x;
+  return x;
+}
+
+// (the moves run on every lane before the select: a move under a lane
+// condition would read the lanes the condition turns off as missing)
+__device__ __forceinline__ uint32_t seg_scan(const SegSteps &s, uint32_t x) {
+  uint32_t o;
+  o = (uint32_t)dpp_move<0x111, 0xf>(0, (int)x);
+  x += s.t[0] ? o : 0u;
+  o = (uint32_t)dpp_move<0x112, 0xf>(0, (int)x);
+  x += s.t[1] ? o : 0u;
+  o = (uint32_t)dpp_move<0x114, 0xf>(0, (int)x);
+  x += s.t[2] ? o : 0u;
+  o = (uint32_t)dpp_move<0x118, 0xf>(0, (int)x);
+  x += s.t[3] ? o : 0u;
+  o = (uint32_t)dpp_move<0x142, 0xa>(0, (int)x);
+  x += s.t[4] ? o : 0u;
+  o = (uint32_t)dpp_move<0x143, 0xc>(0, (int)x);
+  x += s.t[5] ? o : 0u;
+  return x;
+}
+
+// runs of equal keys over the wavefront: run ids, and whether this lane ends its run
+__device__ __forceinline__ void wave_runs(int64_t key, int &seg, bool &tail) {
   const int lane = threadIdx.x & 63;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int sn = __shfl_down(seg, off, 64);
-    const bool take = lane + off < 64 && sn == seg;
-    for (int k = 0; k < 8; ++k) {
-      const double o = __shfl_down(v[k], off, 64);
-      v[k] += take ? o : 0.0;
-    }
-  }
+  const int64_t kprev = __shfl_up(key, 1, 64);
+  const uint64_t heads = __ballot(lane == 0 || kprev != key);
+  seg = __popcll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+  tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
 }
 
 // stage the deposit input of tile slot i (lane = slot layout)
@@ -533,17 +600,19 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
   if (!any) return;
   const int64_t nodes = (int64_t)bx * by * bz;
   // the lanes' last runs: one segmented sum per wavefront, then only the
-  // first lane of each segment (usually 2-3 per wavefront) flushes
+  // last lane of each segment (usually 2-3 per wavefront) flushes
   auto flush_last = [&](DepRun &L, auto &&flush) {
-    const int lane = tid & 63;
     const int key = (int)L.node;
-    const int kprev = __shfl_up(key, 1, 64);
-    const bool head = lane == 0 || kprev != key;
-    const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
-    if (dm & 1u) wave_segment_sum(seg, L.a);
-    if (dm & 2u) wave_segment_sum(seg, L.b);
-    if (dm & 4u) wave_segment_sum(seg, L.c);
-    if (head && key >= 0)
+    int seg;
+    bool tail;
+    wave_runs(key, seg, tail);
+    const SegSteps st = seg_steps(seg);
+    for (int k = 0; k < 8; ++k) {
+      if (dm & 1u) L.a[k] = seg_scan(st, L.a[k]);
+      if (dm & 2u) L.b[k] = seg_scan(st, L.b[k]);
+      if (dm & 4u) L.c[k] = seg_scan(st, L.c[k]);
+    }
+    if (tail && key >= 0)
       for (int k = 0; k < 8; ++k) {
         if ((dm & 1u) && L.a[k] != 0.0) flush(key, 0, k, L.a[k]);
         if ((dm & 2u) && L.b[k] != 0.0) flush(key, 1, k, L.b[k]);
@@ -602,19 +671,14 @@ __device__ __forceinline__ void box_init(int *box) {
 // ---------------------------------------------------------------------------
 // a lane's contribution to the next step's cell grids (chg_next: the ion
 // charge Q in channel 0, or one atom in its species' channel): lanes hold
-// consecutive slots, mostly of one cell, so the first lane of each run of
+// consecutive slots, mostly of one cell, so the last lane of each run of
 // equal entries adds the run's sum with one atomic
 __device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t cell, uint32_t q) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t prev = __shfl_up(cell, 1, 64);
-  const bool head = lane == 0 || prev != cell;
-  const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
-  for (int off = 1; off < 64; off <<= 1) {
-    const int sn = __shfl_down(seg, off, 64);
-    const uint32_t o = __shfl_down(q, off, 64);
-    q += (lane + off < 64 && sn == seg) ? o : 0u;
-  }
-  if (head && cell != 0xffffffffu && q != 0u) atomicAdd(&chg[cell], q);
+  int seg;
+  bool tail;
+  wave_runs((int64_t)cell, seg, tail);
+  q = seg_scan(seg_steps(seg), q);
+  if (tail && cell != 0xffffffffu && q != 0u) atomicAdd(&chg[cell], q);
 }
 
 // DEP: 0 no deposit, 1 deposit with the run's mask, 2 deposit of exactly the
@@ -833,13 +897,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit_pressure(KParams P, Soa<R> S
       for (int dy = 0; dy < 2; ++dy)
         for (int dx = 0; dx < 2; ++dx, ++k) a[k] += (double)((wx[dx] * wy[dy]) * wz[dz]) * e[p];
   }
-  const int lane = tid & 63;
   const int64_t key = cur;
-  const int64_t kprev = __shfl_up(key, 1, 64);
-  const bool head = lane == 0 || kprev != key;
-  const int seg = __popcll(__ballot(head) & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
-  wave_segment_sum(seg, a);
-  if (head && key >= 0) flush(key, a);
+  int seg;
+  bool tail;
+  wave_runs(key, seg, tail);
+  const SegSteps st = seg_steps(seg);
+  for (int k = 0; k < 8; ++k) a[k] = seg_scan(st, a[k]);
+  if (tail && key >= 0) flush(key, a);
   if (!in_brick) return;
   __syncthreads();
   for (int li = tid; li < nb; li += kBlock) {

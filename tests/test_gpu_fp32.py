@@ -85,6 +85,9 @@ CASES = {
     "extended": dict(mask=W.P_ALL | W.P_ELASTIC, v_ev=20.0, n0=3e19, ext=True),
     "self_ne_heat": dict(mask=W.P_ALL | W.P_HEAT, v_ev=20.0, self_ne=True, weight=4e12),
     "bfield_map": dict(mask=W.P_ALL, v_ev=20.0, n0=1e20, bmap=True),
+    # exchange partners from the tracked atoms (half the particles atoms)
+    "cx_partner": dict(mask=W.P_CX | W.P_ELASTIC, v_ev=50.0, self_n0=True, cx_partner=True, weight=1e13, ext=True,
+                       fa=0.5),
 }
 
 
@@ -93,7 +96,8 @@ def test_fp32_single_step_against_oracle(case):
     c = CASES[case]
     params = boosted(W.base_params(20_011, 16, 16, 32, seed=3), n0=c.get("n0", 2e19))
     params.update(process_mask=c["mask"], dt=c.get("dt", 1e-9), deposit_mask=7, weight=c.get("weight", 4e9),
-                  self_ne=c.get("self_ne", False))
+                  self_ne=c.get("self_ne", False), self_n0=c.get("self_n0", False),
+                  cx_partner=c.get("cx_partner", False))
     params.update(zone_a=0.03, zone_c=0.14, ne_in=1e20)
     if c.get("ext"):
         params["species"] = [W.with_extended_mcc(params["species"][0])]
@@ -102,7 +106,8 @@ def test_fp32_single_step_against_oracle(case):
         m = np.random.default_rng(6).normal(size=(3, nn)) * 0.05
         m[2] += 0.5
         params["bfield"] = m
-    st = to_f32_exact(W.random_state(params, seed=300, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95)))
+    st = to_f32_exact(W.random_state(params, seed=300, q_max=12, v_ev=c["v_ev"], radius_frac=c.get("rf", 0.95),
+                                     frac_atoms=c.get("fa", 0.1)))
     g = gpu_run(fp32(params), events=True)
     g.set_state(st, step=11)
     g.step(1)
@@ -112,13 +117,15 @@ def test_fp32_single_step_against_oracle(case):
     assert np.array_equal(g.events(), o.events()), "events differ"
     assert_close32(g.get_state(), o.get_state(), params, what=case)
     tg, to = g.tallies(), o.tallies()
-    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "ionized_n", "elastic"):
+    for k in ("extracted", "wall", "ionized", "cx", "cx_products", "ionized_n", "elastic", "cx_unmatched"):
         assert np.array_equal(tg[k], to[k]), k
     ev = o.events()
     if case == "extended":
         assert (ev == W.EV_ELASTIC).sum() > 5 and to["ionized_n"][0][1:].sum() > 0
     if case == "self_ne_heat":
         assert (ev == W.EV_IONIZE).sum() > 20
+    if case == "cx_partner":
+        assert (ev == W.EV_CX_PARTNER).sum() > 10
     if case == "push_walls":
         assert (ev == W.EV_WALL).sum() > 20
     if case == "cx":

@@ -493,6 +493,24 @@ def test_edge_sizes_zero_one_and_tiny_grid():
             assert_tallies_equal(t, o.tallies())
 
 
+def test_edge_sizes_with_exchange_partners():
+    # tracked neutrals and exchange partners with 0-3 particles in one cell
+    for n in (0, 1, 2, 3):
+        params = W.base_params(n, 1, 1, 1)
+        params.update(process_mask=W.P_ALL, self_n0=True, cx_partner=True)
+        g = gpu_run(params, events=True)
+        g.init_ions()
+        g.step(5)
+        t = g.tallies()
+        assert t["steps"] == 5
+        if n:
+            o = oracle(params)
+            o.init_ions()
+            o.step(5)
+            assert_state_close(g.get_state(), o.get_state(), params, what=f"partners n={n}")
+            assert_tallies_equal(t, o.tallies())
+
+
 def test_edt_rejected_and_bad_state():
     import paper_1507_03392_amd as ecr
     params = boosted(W.base_params(100, 8, 8, 16), n0=1e23)
