@@ -607,17 +607,21 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
     bool tail;
     wave_runs(key, seg, tail);
     const SegSteps st = seg_steps(seg);
+    const bool out = tail && key >= 0;
     for (int k = 0; k < 8; ++k) {
-      if (dm & 1u) L.a[k] = seg_scan(st, L.a[k]);
-      if (dm & 2u) L.b[k] = seg_scan(st, L.b[k]);
-      if (dm & 4u) L.c[k] = seg_scan(st, L.c[k]);
-    }
-    if (tail && key >= 0)
-      for (int k = 0; k < 8; ++k) {
-        if ((dm & 1u) && L.a[k] != 0.0) flush(key, 0, k, L.a[k]);
-        if ((dm & 2u) && L.b[k] != 0.0) flush(key, 1, k, L.b[k]);
-        if ((dm & 4u) && L.c[k] != 0.0) flush(key, 2, k, L.c[k]);
+      if (dm & 1u) {
+        const double v = seg_scan(st, L.a[k]);
+        if (out && v != 0.0) flush(key, 0, k, v);
       }
+      if (dm & 2u) {
+        const double v = seg_scan(st, L.b[k]);
+        if (out && v != 0.0) flush(key, 1, k, v);
+      }
+      if (dm & 4u) {
+        const double v = seg_scan(st, L.c[k]);
+        if (out && v != 0.0) flush(key, 2, k, v);
+      }
+    }
   };
   if (nodes <= kDepBrick / kFields) {
     const int nb = (int)nodes;
