@@ -117,6 +117,44 @@ struct CoulShared {
   uint32_t wsum[kCB / 64];
 };
 
+// Inclusive sums over a wavefront with DPP lane moves, no LDS: row_shr 1,
+// 2, 4, 8 within each row of 16 lanes, then row_bcast 15 (the last lane of
+// rows 0 and 2 into rows 1 and 3) and row_bcast 31 (lane 31 into rows 2
+// and 3); a missing source adds zero.  Called by all 64 lanes; lane 63 ends
+// with the wavefront's total.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  x += dpp_u32<0x111, 0xf>(x);
+  x += dpp_u32<0x112, 0xf>(x);
+  x += dpp_u32<0x114, 0xf>(x);
+  x += dpp_u32<0x118, 0xf>(x);
+  x += dpp_u32<0x142, 0xa>(x);
+  x += dpp_u32<0x143, 0xc>(x);
+  return x;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = dpp_u32<CTRL, ROWS>((uint32_t)u), hi = dpp_u32<CTRL, ROWS>((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// the wavefront's total, in lane 63
+__device__ __forceinline__ double wave_sum_last(double x) {
+  x += dpp_f64<0x111, 0xf>(x);
+  x += dpp_f64<0x112, 0xf>(x);
+  x += dpp_f64<0x114, 0xf>(x);
+  x += dpp_f64<0x118, 0xf>(x);
+  x += dpp_f64<0x142, 0xa>(x);
+  x += dpp_f64<0x143, 0xc>(x);
+  return x;
+}
+
 // in-place exclusive scan of a[0..L) by the workgroup; returns the total
 __device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum) {
   const int tid = threadIdx.x;
@@ -125,11 +163,7 @@ __device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum
   uint32_t s = 0;
   for (int i = b; i < e; ++i) s += a[i];
   const int lane = tid & 63, w = tid >> 6;
-  uint32_t x = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  const uint32_t x = wave_incl_scan(s);
   if (lane == 63) wsum[w] = x;
   __syncthreads();
   uint32_t woff = 0, tot = 0;
@@ -320,18 +354,15 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
   // slot order; pairs and triplets side by side in one word (each at most
   // kCoulItems, so the low half never carries into the high one)
   constexpr int kLead = kEPT * (kCB / 64);
+  static_assert(kLead <= 64, "leader counts fit one wavefront");
   const uint32_t c = lane < nk * (kCB / 64) ? sh.lead[lane] : 0u;
-  uint32_t incl = c;
-#pragma unroll
-  for (int o = 1; o < kLead; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t tot = __shfl(incl, kLead - 1, 64);
+  const uint32_t incl = wave_incl_scan(c), excl = incl - c;
+  const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kLead - 1);
   const int np = (int)(tot & 0xffffu);
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);  // uniform over the wavefront
   uint32_t before[kEPT];
 #pragma unroll
-  for (int k = 0; k < kEPT; ++k) before[k] = __shfl(incl - c, k * (kCB / 64) + wv, 64);
+  for (int k = 0; k < kEPT; ++k) before[k] = (uint32_t)__builtin_amdgcn_readlane((int)excl, k * (kCB / 64) + wvu);
   CoulItem *out = items + (int64_t)blockIdx.x * kCoulItems;
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
@@ -391,18 +422,16 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
         nt = c.y;
       }
     }
-    uint32_t my_incl = nt;
-    for (int off = 1; off < kTriChunks; off <<= 1) {
-      const uint32_t t = __shfl_up(my_incl, off, 64);
-      if (lane >= off) my_incl += t;
-    }
-    const int total = (int)__shfl(my_incl, kTriChunks - 1, 64);
+    static_assert(kTriChunks <= 64, "a group's chunks fit one wavefront");
+    const uint32_t my_incl = wave_incl_scan(nt);  // lanes >= kTriChunks hold nt = 0
+    const int total = __builtin_amdgcn_readlane((int)my_incl, kTriChunks - 1);
     if (kw * 64 >= total) return;
     const double h = 0.5 * P.dt;
     for (int q0 = kw * 64; q0 < total; q0 += 64 * nw) {
       const int q = q0 + lane;
       int c = 0;  // the lane's triplet is number q - incl[c-1] of chunk b + c
-      for (int j = 0; j < kTriChunks; ++j) c += (int)__shfl(my_incl, j, 64) <= q ? 1 : 0;
+#pragma unroll
+      for (int j = 0; j < kTriChunks; ++j) c += __builtin_amdgcn_readlane((int)my_incl, j) <= q ? 1 : 0;
       const int cc = c < kTriChunks ? c : kTriChunks - 1;  // c < kTriChunks when q < total
       const uint32_t prev = __shfl(my_incl, cc > 0 ? cc - 1 : 0, 64);
       const uint32_t lo = __shfl(my_lo, cc, 64), np = __shfl(my_np, cc, 64);
@@ -418,9 +447,8 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
     // each triplet wave owns the triplet slot of the chunk its column names
     double *slot = moments + ((int64_t)blockIdx.x * kMomentSlotsPerChunk + kMomentSlotsPerChunk - 1) * 5;
     for (int k = 0; k < 5; ++k) {
-      double v = acc[k];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0 && v != 0.0) slot[k] += v;
+      const double v = wave_sum_last(acc[k]);
+      if (lane == 63 && v != 0.0) slot[k] += v;
     }
     return;
   }
@@ -443,9 +471,8 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
   // tallies are read)
   double *slot = moments + (b * kMomentSlotsPerChunk + y) * 5;
   for (int k = 0; k < 5; ++k) {
-    double v = acc[k];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0 && v != 0.0) slot[k] += v;
+    const double v = wave_sum_last(acc[k]);
+    if (lane == 63 && v != 0.0) slot[k] += v;
   }
 }
 
