@@ -514,6 +514,26 @@ __device__ __forceinline__ uint32_t seg_scan(const SegSteps &s, uint32_t x) {
   return x;
 }
 
+// the wavefront's cell-index bounding box (minima and maxima of three
+// indices) by the same DPP moves, in lane 63; called by all 64 lanes
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void box_step(int mn[3], int mx[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const int a = dpp_move<CTRL, ROWS>(0x7fffffff, mn[d]), b = dpp_move<CTRL, ROWS>(-0x7fffffff - 1, mx[d]);
+    mn[d] = min(mn[d], a);
+    mx[d] = max(mx[d], b);
+  }
+}
+
+__device__ __forceinline__ void wave_box_last(int mn[3], int mx[3]) {
+  box_step<0x111, 0xf>(mn, mx);
+  box_step<0x112, 0xf>(mn, mx);
+  box_step<0x114, 0xf>(mn, mx);
+  box_step<0x118, 0xf>(mn, mx);
+  box_step<0x142, 0xa>(mn, mx);
+  box_step<0x143, 0xc>(mn, mx);
+}
+
 // runs of equal keys over the wavefront: run ids, and whether this lane ends its run
 __device__ __forceinline__ void wave_runs(int64_t key, int &seg, bool &tail) {
   const int lane = threadIdx.x & 63;
@@ -561,12 +581,8 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
   const int tid = threadIdx.x;
   const uint32_t dm = NQ ? 3u : P.dmask;
   constexpr int kFields = NQ ? 2 : 3;  // brick fields
-  for (int off = 32; off > 0; off >>= 1)
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
-      mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
-    }
-  if ((tid & 63) == 0)
+  wave_box_last(mn, mx);
+  if ((tid & 63) == 63)
     for (int d = 0; d < 3; ++d) {
       atomicMin(&box[d], mn[d]);
       atomicMax(&box[3 + d], mx[d]);
@@ -831,12 +847,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_pressure(KParams P, Soa<R> S
       }
     }
   }
-  for (int off = 32; off > 0; off >>= 1)
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
-      mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
-    }
-  if ((tid & 63) == 0)
+  wave_box_last(mn, mx);
+  if ((tid & 63) == 63)
     for (int d = 0; d < 3; ++d) {
       atomicMin(&box[d], mn[d]);
       atomicMax(&box[3 + d], mx[d]);
