@@ -73,10 +73,13 @@ void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_
 // pairing (k_coul_order) then collisions (k_coul_pairs); items holds
 // kCoulItems entries per chunk, counts one (pairs, triplets) per chunk
 // moments: coul_moment_slots(n) x 5 doubles of per-wavefront momentum /
-// energy sums, reduced into the tallies by launch_sum_moments
+// energy sums, reduced into the tallies by launch_sum_moments.  The ordering
+// kernel also clears zero[0..zero_n) (the next step's cell grids) when zero
+// is given; it does nothing at all for n <= 1
 template <typename R>
 void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo, DevAccum *acc,
-                       CoulItem *items, uint2 *counts, StepArg step, hipStream_t st);
+                       CoulItem *items, uint2 *counts, StepArg step, uint32_t *zero, int64_t zero_n,
+                       hipStream_t st);
 template <typename R>
 void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *chunk_lo, const CoulItem *items,
                        const uint2 *counts, double *moments, StepArg step, hipStream_t st);

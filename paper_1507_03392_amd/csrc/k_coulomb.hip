@@ -202,10 +202,18 @@ template <typename R>
 __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const uint32_t *__restrict__ cellid,
                                                     const uint32_t *__restrict__ chunk_lo,
                                                     DevAccum *__restrict__ accum, CoulItem *__restrict__ items,
-                                                    uint2 *__restrict__ counts, StepArg sa) {
+                                                    uint2 *__restrict__ counts, StepArg sa,
+                                                    uint32_t *__restrict__ zero, int64_t zero_n) {
   __shared__ CoulShared sh;
   const uint32_t step = sa.get();
   const int tid = threadIdx.x;
+  if (zero) {
+    // the next step's cell grids, cleared here, a slice per workgroup,
+    // instead of by a kernel of their own (the push fills them afterwards)
+    const int64_t per = (zero_n + gridDim.x - 1) / gridDim.x;
+    const int64_t z0 = (int64_t)blockIdx.x * per, z1 = min(z0 + per, zero_n);
+    for (int64_t t = z0 + tid; t < z1; t += kCB) zero[t] = 0u;
+  }
   const int64_t s_lo = chunk_lo[blockIdx.x];
   const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
   if (ns <= 1) return;
@@ -516,10 +524,11 @@ void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_
 
 template <typename R>
 void launch_coul_order(const KParams &P, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo, DevAccum *acc,
-                       CoulItem *items, uint2 *counts, StepArg step, hipStream_t st) {
+                       CoulItem *items, uint2 *counts, StepArg step, uint32_t *zero, int64_t zero_n,
+                       hipStream_t st) {
   if (P.n <= 1) return;
   hipLaunchKernelGGL(k_coul_order<R>, dim3((unsigned)coul_nchunks(P.n)), dim3(kCB), 0, st, P, S, cellid, chunk_lo, acc,
-                     items, counts, step);
+                     items, counts, step, zero, zero_n);
 }
 
 template <typename R>
@@ -532,9 +541,9 @@ void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32
 }
 
 template void launch_coul_order<double>(const KParams &, Soa<double>, const uint32_t *, const uint32_t *, DevAccum *,
-                                        CoulItem *, uint2 *, StepArg, hipStream_t);
+                                        CoulItem *, uint2 *, StepArg, uint32_t *, int64_t, hipStream_t);
 template void launch_coul_order<float>(const KParams &, Soa<float>, const uint32_t *, const uint32_t *, DevAccum *,
-                                       CoulItem *, uint2 *, StepArg, hipStream_t);
+                                       CoulItem *, uint2 *, StepArg, uint32_t *, int64_t, hipStream_t);
 template void launch_coul_pairs<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *,
                                         const CoulItem *, const uint2 *, double *, StepArg, hipStream_t);
 template void launch_coul_pairs<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const CoulItem *,

@@ -514,11 +514,18 @@ void do_step(ecr_run *r, StepArg stepw) {
   }
   DevAccum *acc = at<DevAccum>(r, r->L.acc);
   const Tables *T = at<Tables>(r, r->L.tables);
+  const bool grids = (r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0)) != 0;
+  uint32_t *chg_cur = grids ? at<uint32_t>(r, r->L.chg[r->chg_par]) : nullptr;
+  uint32_t *chg_next = grids ? at<uint32_t>(r, r->L.chg[1 - r->chg_par]) : nullptr;
+  const int64_t chg_words = r->ncell * (1 + r->p.n_species);
+  // the ordering kernel clears the next step's grids when it runs
+  const bool fold = grids && (pm & ECR_P_COULOMB) && r->kp.n > 1;
   if (pm & ECR_P_COULOMB) {
     {
       ProfScope ps(r, ECR_K_COULOMB);
       launch_coul_order<R>(r->kp, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.chunks), acc,
-                           at<CoulItem>(r, r->L.pairs), at<uint2>(r, r->L.tris), stepw, r->stream);
+                           at<CoulItem>(r, r->L.pairs), at<uint2>(r, r->L.tris), stepw, fold ? chg_next : nullptr,
+                           fold ? chg_words : 0, r->stream);
     }
     ProfScope ps(r, ECR_K_COUL_PAIRS);
     launch_coul_pairs<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.chunks), at<CoulItem>(r, r->L.pairs),
@@ -526,10 +533,7 @@ void do_step(ecr_run *r, StepArg stepw) {
   }
   const bool dep = (pm & ECR_P_DEPOSIT) != 0;
   const bool split = (r->p.flags & ECR_FLAG_SPLIT) != 0;
-  const bool grids = (r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0)) != 0;
-  uint32_t *chg_cur = grids ? at<uint32_t>(r, r->L.chg[r->chg_par]) : nullptr;
-  uint32_t *chg_next = grids ? at<uint32_t>(r, r->L.chg[1 - r->chg_par]) : nullptr;
-  if (grids) launch_fill_u32(chg_next, 0u, r->ncell * (1 + r->p.n_species), r->stream);
+  if (grids && !fold) launch_fill_u32(chg_next, 0u, chg_words, r->stream);
   {
     ProfScope ps(r, (dep && !split) ? ECR_K_FUSED : ECR_K_PUSH);
     launch_push<R>(r->kp, T, soa<R>(r, r->cur), r->p.efield_nodes ? at<double>(r, r->L.efield) : nullptr,
