@@ -109,9 +109,7 @@ struct CoulShared {
   uint64_t skey[kCoulMaxE];         // (key << 32) | id, in slot order
   uint32_t r1[kCoulMaxE + 2];       // cell flags and scan scratch, then the bucket histogram
   uint16_t hd[kCoulMaxE];           // cell (head) index of each slot of the chunk
-  uint16_t hstart[kCoulMaxE + 1];   // first slot of each cell
-  uint16_t hbase[kCoulMaxE + 1];    // first bucket of each cell
-  uint8_t hlog[kCoulMaxE];          // log2 of the cell's bucket count
+  uint16_t hcell[kCoulMaxE + 1];    // first slot of each cell (steps 2-3), then its first bucket
   uint16_t ord[kCoulMaxE];          // members bucket by bucket
   uint32_t lead[kEPT * (kCB / 64)];  // leaders per (pass, wavefront): pairs | triplets << 16
   uint32_t wsum[kCB / 64];
@@ -222,6 +220,10 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     return;
   }
   uint32_t *flags = sh.r1;
+  // one array serves twice: the cells' first slots are last read in step 3,
+  // before the scan after which their first buckets are written (20 KB of
+  // LDS in all, so eight workgroups share a CU)
+  uint16_t *const hstart = sh.hcell, *const hbase = sh.hcell;
   // 1. coalesced loads: cell, pool flag, pairing key
   bool pool[kEPT];
   uint32_t key[kEPT];
@@ -255,23 +257,22 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     if (i < ns) {
       const int h = (int)(flags[i] + fl[k]) - 1;
       sh.hd[i] = (uint16_t)h;
-      if (fl[k]) sh.hstart[h] = (uint16_t)i;
+      if (fl[k]) hstart[h] = (uint16_t)i;
     }
   }
-  if (tid == 0) sh.hstart[nheads] = (uint16_t)ns;
+  if (tid == 0) hstart[nheads] = (uint16_t)ns;
   __syncthreads();
   // 3. buckets per cell: B = 2^floor(log2(slots of the cell)), so at most
   //    one bucket per slot of the chunk
   for (int h = tid; h < nheads; h += kCB) {
-    const int m = sh.hstart[h + 1] - sh.hstart[h];
+    const int m = hstart[h + 1] - hstart[h];
     const int lg = m <= 1 ? 0 : 31 - __clz(m);
-    sh.hlog[h] = (uint8_t)lg;
     sh.r1[h] = 1u << lg;
   }
   __syncthreads();
   const int nbuckets = (int)wg_exscan(sh.r1, nheads, sh.wsum);
-  for (int h = tid; h < nheads; h += kCB) sh.hbase[h] = (uint16_t)sh.r1[h];
-  if (tid == 0) sh.hbase[nheads] = (uint16_t)nbuckets;
+  for (int h = tid; h < nheads; h += kCB) hbase[h] = (uint16_t)sh.r1[h];
+  if (tid == 0) hbase[nheads] = (uint16_t)nbuckets;
   __syncthreads();
   // 4-5. histogram of the pool members over their cell's buckets
   uint32_t *hist = sh.r1;
@@ -285,8 +286,8 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     arr[k] = 0;
     if (i < ns && pool[k]) {
       const int h = sh.hd[i];
-      const int lg = sh.hlog[h];
-      bk[k] = sh.hbase[h] + (lg ? (int)(key[k] >> (32 - lg)) : 0);
+      const int lg = 31 - __clz(hbase[h + 1] - hbase[h]);  // the cell's 2^lg buckets
+      bk[k] = hbase[h] + (lg ? (int)(key[k] >> (32 - lg)) : 0);
       arr[k] = (int)atomicAdd(&hist[bk[k]], 1u);
     }
   }
@@ -314,8 +315,8 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
       for (int t = b0; t < b1; ++t) rib += sh.skey[sh.ord[t]] < me ? 1 : 0;
       pos[k] = b0 + rib;
       const int h = sh.hd[i];
-      const int pstart = (int)hist[sh.hbase[h]];
-      const int pend = (int)hist[sh.hbase[h] + (1 << sh.hlog[h])];
+      const int pstart = (int)hist[hbase[h]];
+      const int pend = (int)hist[hbase[h + 1]];
       mm[k] = pend - pstart;
       rr[k] = pos[k] - pstart;
     }
