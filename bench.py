@@ -8,8 +8,8 @@ on the GPU before the timed region.
 
 Prints one JSON line: throughput in particle-steps/s, the roofline of the
 dominant kernel (algorithmic bytes per launch / its mean launch time, timed
-with HIP events on the run's stream around each of its launches in the timed
-region; the kernel is picked by a short all-kernel timing pass before it),
+with HIP events on the run's stream around one in ten of its launches in the
+timed region; the kernel is picked by a short all-kernel timing pass before it),
 the HBM traffic the committed rocprofv3 counters give for that kernel, and
 the CPU oracle timed on a bounded sample of the same workload.
 """
@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=200,
                     help="steps of the all-kernel timing pass (after warm-up) that picks the dominant kernel")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--event-stride", type=int, default=10,
+                    help="time one launch of the dominant kernel in this many with HIP events (1: every launch)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--self-ne", action="store_true",
@@ -269,8 +271,10 @@ def main():
                    "share": round(tot[k] / max(1e-12, sum(tot.values())), 3)} for k in tot if per[k][1]}
     log(f"bench: kernels {json.dumps(kernels)}")
 
-    # ... which is then timed with events over the timed region itself
-    run.profile(True, kinds=[dom])
+    # ... which is then timed with events over the timed region itself, on
+    # one launch in --event-stride (the event packets around a launch hold
+    # up the queue, so timing every launch would slow the step it measures)
+    run.profile(True, kinds=[dom], stride=args.event_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run.step(args.steps)
@@ -340,7 +344,8 @@ def main():
                    "sort_every": params["sort_every"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6, "timed_launches": launches},
+                     "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6, "timed_launches": launches,
+                     "event_stride": args.event_stride},
         "kernels": kernels,
         "tallies": {"ionized": int(tal["ionized"].sum()), "wall": int(tal["wall"].sum()),
                     "extracted": int(tal["extracted"].sum()), "cx": int(tal["cx"].sum()),

@@ -292,6 +292,10 @@ enum {
 };
 ecr_status ecr_profile(ecr_run *run, int32_t enable);
 ecr_status ecr_kernel_times(ecr_run *run, double *ms_out, int64_t *launches_out);
+/* Bracket only one launch in `stride` (>= 1, default 1) of each timed kind,
+ * counted from the next ecr_profile call: sampled timing that leaves the
+ * other launches without event packets.  ECR_EINVAL for stride < 1. */
+ecr_status ecr_profile_stride(ecr_run *run, int32_t stride);
 
 /* Message of the last error on this run (NULL run: of the calling thread). */
 const char *ecr_last_error(const ecr_run *run);

@@ -31,7 +31,7 @@ STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}
 
 EXPORTS = ["ecr_footprint", "ecr_create", "ecr_init_ions", "ecr_step", "ecr_step_graph", "ecr_step_batch",
-           "ecr_read_tallies", "ecr_read_density", "ecr_get_state", "ecr_set_state", "ecr_event_log", "ecr_weight", "ecr_profile",
+           "ecr_read_tallies", "ecr_read_density", "ecr_get_state", "ecr_set_state", "ecr_event_log", "ecr_weight", "ecr_profile", "ecr_profile_stride",
            "ecr_kernel_times", "ecr_last_error", "ecr_destroy", "ecr_selftest_philox", "ecr_selftest_divsqrt"]
 
 
@@ -108,7 +108,7 @@ def lib():
             "ecr_read_density": [vp, u32, vp, C.POINTER(i64)],
             "ecr_get_state": [vp, C.POINTER(StateView)], "ecr_set_state": [vp, C.POINTER(StateView)],
             "ecr_event_log": [vp, vp], "ecr_weight": [vp, C.POINTER(C.c_double)],
-            "ecr_profile": [vp, i32], "ecr_kernel_times": [vp, vp, vp], "ecr_destroy": [vp],
+            "ecr_profile": [vp, i32], "ecr_profile_stride": [vp, i32], "ecr_kernel_times": [vp, vp, vp], "ecr_destroy": [vp],
             "ecr_selftest_philox": [u64, u32, u32, u32, u32, i64, vp, vp],
             "ecr_selftest_divsqrt": [vp, vp, i64, vp, vp, vp],
         }
@@ -297,12 +297,14 @@ class Run:
         _check(lib().ecr_weight(self.h, C.byref(w)), self.h)
         return w.value
 
-    def profile(self, enable=True, kinds=None):
+    def profile(self, enable=True, kinds=None, stride=1):
         """Time launches with HIP events: every kernel kind, or only `kinds`
-        (names from KERNEL_NAMES); enable=False turns timing off."""
+        (names from KERNEL_NAMES), one launch in `stride` of each; enable=False
+        turns timing off."""
         mask = 0
         if enable:
             mask = -1 if kinds is None else sum(1 << KERNEL_NAMES.index(k) for k in kinds)
+        _check(lib().ecr_profile_stride(self.h, stride), self.h)
         _check(lib().ecr_profile(self.h, mask), self.h)
 
     def kernel_times(self):

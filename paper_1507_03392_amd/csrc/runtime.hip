@@ -213,6 +213,8 @@ struct ecr_run {
   std::string err;
   // profiling: bit k set = launches of kernel kind k are bracketed by events
   uint32_t prof;
+  int32_t prof_stride = 1;           // bracket one launch in prof_stride of each kind
+  int64_t prof_seen[ECR_N_KERNELS];  // launches of each kind since ecr_profile
   double ms[ECR_N_KERNELS];
   int64_t launches[ECR_N_KERNELS];
   std::vector<hipEvent_t> free_events;
@@ -475,14 +477,14 @@ struct ProfScope {
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(ecr_run *r_, int k) : r(r_), kind(k) {
-    if ((r->prof >> kind) & 1u) {
+    if ((r->prof >> kind) & 1u && r->prof_seen[kind]++ % r->prof_stride == 0) {
       a = get_event(r);
       b = get_event(r);
       (void)hipEventRecord(a, r->stream);
     }
   }
   ~ProfScope() {
-    if ((r->prof >> kind) & 1u) {
+    if (a) {
       (void)hipEventRecord(b, r->stream);
       r->pending.push_back({kind, a, b});
       if (r->pending.size() >= 4096) harvest(r);
@@ -703,6 +705,7 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   r->cur = 0;
   r->need_sort = true;
   r->prof = 0u;
+  for (int k = 0; k < ECR_N_KERNELS; ++k) r->prof_seen[k] = 0;
   for (int k = 0; k < ECR_N_KERNELS; ++k) {
     r->ms[k] = 0.0;
     r->launches[k] = 0;
@@ -940,7 +943,15 @@ ecr_status ecr_profile(ecr_run *r, int32_t enable) {
   for (int k = 0; k < ECR_N_KERNELS; ++k) {
     r->ms[k] = 0.0;
     r->launches[k] = 0;
+    r->prof_seen[k] = 0;
   }
+  return ECR_OK;
+}
+
+ecr_status ecr_profile_stride(ecr_run *r, int32_t stride) {
+  if (!r) return fail(nullptr, ECR_EINVAL, "run is NULL");
+  if (stride < 1) return fail(r, ECR_EINVAL, "stride must be >= 1");
+  r->prof_stride = stride;
   return ECR_OK;
 }
 

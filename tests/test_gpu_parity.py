@@ -566,3 +566,29 @@ def test_full_size_c2_sampled_cells():
     lost = int((zz * (t["extracted"][0] + t["wall"][0])).sum())
     assert int(after["q"].astype(np.int64).sum()) + lost + int(t["cx_products"][0]) == \
         params["n"] + int(t["ionized"][0].sum())
+
+
+def test_kernel_timing_every_launch_and_sampled():
+    # ecr_profile brackets launches with events; ecr_profile_stride keeps
+    # one launch in stride of each kind; timing leaves the results unchanged
+    params = W.with_(W.config("c1")[0], sort_every=10)
+    a, b = gpu_run(params), gpu_run(params)
+    a.init_ions()
+    b.init_ions()
+    a.profile(True)
+    a.step(20)
+    kt = a.kernel_times()
+    assert kt["push_deposit"][1] == 20 and kt["coul_order"][1] == 20 and kt["sort"][1] == 2
+    assert all(ms > 0 for ms, c in kt.values() if c)
+    a.profile(True, kinds=["push_deposit"], stride=6)
+    a.step(20)
+    kt = a.kernel_times()
+    assert kt["push_deposit"][1] == 4 and kt["coul_order"][1] == 0  # launches 0, 6, 12, 18
+    a.profile(False)
+    b.step(40)
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("x", "vx", "q"):
+        assert np.array_equal(sa[k], sb[k])
+    import paper_1507_03392_amd as ecr
+    with pytest.raises(ecr.EcrError):
+        a.profile(True, stride=0)
