@@ -537,7 +537,10 @@ __device__ __forceinline__ void wave_box_last(int mn[3], int mx[3]) {
 // runs of equal keys over the wavefront: run ids, and whether this lane ends its run
 __device__ __forceinline__ void wave_runs(int64_t key, int &seg, bool &tail) {
   const int lane = threadIdx.x & 63;
-  const int64_t kprev = __shfl_up(key, 1, 64);
+  // the previous lane's key by wave_shr:1 (lane 0 has none and heads a run)
+  const uint32_t plo = (uint32_t)dpp_move<0x138, 0xf>(0, (int)(uint32_t)(uint64_t)key);
+  const uint32_t phi = (uint32_t)dpp_move<0x138, 0xf>(0, (int)(uint32_t)((uint64_t)key >> 32));
+  const int64_t kprev = (int64_t)(((uint64_t)phi << 32) | plo);
   const uint64_t heads = __ballot(lane == 0 || kprev != key);
   seg = __popcll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
   tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
