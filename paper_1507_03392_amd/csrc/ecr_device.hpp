@@ -55,6 +55,8 @@ struct KParams {
   // any, each slot's collision cell and each cell's first slot
   uint32_t *cxreq, *cxchunk;
   const uint32_t *cellid, *cell_off;
+  // heating kick with self-consistent electrons: |B| x hx at each cell centre
+  const double *bden;
   double mass[kMaxS], sig_w[kMaxS], sig_n[kMaxS], sig_i[kMaxS], decx[kMaxS], ccx[kMaxS];
   double cel[kMaxS];     // n0 sigma_el1 dt (elastic ion-atom scattering)
   double sdt_cx[kMaxS], sdt_el[kMaxS];  // sigma1 dt, sigma_el1 dt: neutrals from the tracked atoms

@@ -53,6 +53,9 @@ template <typename R>
 void launch_cx_partner(const KParams &P, Soa<R> S, const uint32_t *chunk_lo, uint32_t *chg, uint8_t *evlog,
                        DevAccum *acc, StepArg step, hipStream_t st);
 
+// |B| at every cell centre times hx, into bden[ncell] (once, at create)
+void launch_cell_bden(const KParams &P, double *bden, hipStream_t st);
+
 // ion charge per cell of the current state, added into chg (zeroed before)
 template <typename R>
 void launch_charge_grid(const KParams &P, Soa<R> S, uint32_t *chg, hipStream_t st);

@@ -96,21 +96,11 @@ __device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__rest
     };
     ne = nat(ix, iy);
     if (!(ne > 0.0)) return;
-    double bx, by, bz;
-    const double xc = -P.R0 + ((double)ix + 0.5) * P.hx, yc = -P.R0 + ((double)iy + 0.5) * P.hy;
-    const double zc = -P.hL + ((double)iz + 0.5) * P.hz;
-    if (P.bmap) {
-      double B[3];
-      gather_E<double>(P, P.bmap, xc, yc, zc, B);
-      bx = B[0];
-      by = B[1];
-      bz = B[2];
-    } else {
-      field_B<double>(P, xc, yc, zc, bx, by, bz);
-    }
-    const double bmag = sqrt((bx * bx + by * by) + bz * bz);
-    if (bmag > 0.0 && !(P.flags & ECR_FLAG_HEAT_ISOTROPIC)) {
-      const double rl = P.rl_zone[zone] / (bmag * P.hx);
+    // |B| at the cell centre times the cell size, tabulated per cell when
+    // the run is created (cell_bden)
+    const double den = P.bden[plane + (uint32_t)ix + (uint32_t)P.nx * (uint32_t)iy];
+    if (den > 0.0 && !(P.flags & ECR_FLAG_HEAT_ISOTROPIC)) {
+      const double rl = P.rl_zone[zone] / den;
       const double nmm = nat(ix - 1, iy - 1), nzm = nat(ix, iy - 1), npm = nat(ix + 1, iy - 1);
       const double nmz = nat(ix - 1, iy), npz = nat(ix + 1, iy);
       const double nmp = nat(ix - 1, iy + 1), nzp = nat(ix, iy + 1), npp = nat(ix + 1, iy + 1);
@@ -1008,6 +998,34 @@ void launch_charge_grid(const KParams &P, Soa<R> S, uint32_t *chg, hipStream_t s
 
 template void launch_charge_grid<double>(const KParams &, Soa<double>, uint32_t *, hipStream_t);
 template void launch_charge_grid<float>(const KParams &, Soa<float>, uint32_t *, hipStream_t);
+
+// |B| at each cell centre times the cell size hx (the heating kick's
+// electron Larmor radius divides by it): the analytic field, or the node
+// map interpolated at the centre
+__global__ void __launch_bounds__(256) k_cell_bden(KParams P, double *__restrict__ bden) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)P.ncell) return;
+  const int ix = (int)(c % P.nx), iy = (int)((c / P.nx) % P.ny), iz = (int)(c / ((int64_t)P.nx * P.ny));
+  const double xc = -P.R0 + ((double)ix + 0.5) * P.hx, yc = -P.R0 + ((double)iy + 0.5) * P.hy;
+  const double zc = -P.hL + ((double)iz + 0.5) * P.hz;
+  double bx, by, bz;
+  if (P.bmap) {
+    double B[3];
+    gather_E<double>(P, P.bmap, xc, yc, zc, B);
+    bx = B[0];
+    by = B[1];
+    bz = B[2];
+  } else {
+    field_B<double>(P, xc, yc, zc, bx, by, bz);
+  }
+  const double bmag = sqrt((bx * bx + by * by) + bz * bz);
+  bden[c] = bmag * P.hx;
+}
+
+void launch_cell_bden(const KParams &P, double *bden, hipStream_t st) {
+  if (P.ncell == 0u) return;
+  hipLaunchKernelGGL(k_cell_bden, dim3(grid_for((int64_t)P.ncell, 256)), dim3(256), 0, st, P, bden);
+}
 
 template <typename R>
 void launch_deposit(const KParams &P, Soa<R> S, double *dens, hipStream_t st) {

@@ -35,11 +35,16 @@ struct Layout {
   size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
   size_t cxreq;   // exchanges per species and collision cell (ECR_FLAG_CX_PARTNER)
   size_t cxchunk; // per Coulomb chunk: any of them in its cells
+  size_t bden;    // |B| hx per cell (heating kick with self-consistent electrons)
   size_t total;
 };
 
 int64_t ncells(const ecr_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
 int64_t nnodes(const ecr_params *p) { return (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1); }
+// the heating kick reads |B| hx per cell when n_e comes from the particles
+bool needs_bden(const ecr_params *p) {
+  return (p->process_mask & ECR_P_HEAT) && (p->flags & ECR_FLAG_SELF_NE);
+}
 
 Layout make_layout(const ecr_params *p) {
   Layout L{};
@@ -101,6 +106,8 @@ Layout make_layout(const ecr_params *p) {
   if (p->flags & ECR_FLAG_CX_PARTNER) o = align_up(o + 4 * (size_t)ncells(p) * (size_t)p->n_species);
   L.cxchunk = o;
   if (p->flags & ECR_FLAG_CX_PARTNER) o = align_up(o + 4 * (size_t)(coul_nchunks((int64_t)N) + 1));
+  L.bden = o;
+  if (needs_bden(p)) o = align_up(o + 8 * (size_t)ncells(p));
   L.total = o + kAlign;  // slack so the arena base may be realigned
   return L;
 }
@@ -730,6 +737,8 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   r->kp.cxreq = (params->flags & ECR_FLAG_CX_PARTNER) ? at<uint32_t>(r, L.cxreq) : nullptr;
   r->kp.cxchunk = (params->flags & ECR_FLAG_CX_PARTNER) ? at<uint32_t>(r, L.cxchunk) : nullptr;
   r->kp.cell_off = at<uint32_t>(r, L.cell_off);
+  r->kp.bden = needs_bden(params) ? at<double>(r, L.bden) : nullptr;
+  if (r->kp.bden) launch_cell_bden(r->kp, at<double>(r, L.bden), r->stream);
   zero_accumulators(r);
   *out = r;
   return ECR_OK;
