@@ -10,7 +10,8 @@
 namespace ecr {
 
 // Coulomb chunking: a workgroup owns the cells whose first sorted slot falls
-// in [b*kCoulCap, (b+1)*kCoulCap); it orders up to kCoulMaxE slots in LDS.
+// in [b*kCoulCap, (b+1)*kCoulCap); it orders up to kCoulMaxE pool members
+// (ions; atoms take no room) in LDS.
 constexpr int kCoulCap = 256;
 constexpr int kCoulMaxE = 1024;
 

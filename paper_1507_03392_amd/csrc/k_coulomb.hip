@@ -12,8 +12,9 @@
 // Two kernels per step:
 //  * k_coul_order: workgroup b owns the cells whose first slot lies in
 //    [b*kCoulCap, (b+1)*kCoulCap) (slot ranges tabulated once per sort by
-//    k_coul_chunks).  The chunk's slots are already grouped by cell, so the
-//    pool order is found per cell without a general sort: a cell of m slots
+//    k_coul_chunks).  It first compacts the chunk's pool members (ions) into
+//    LDS in slot order, so they are already grouped by cell, and the pool
+//    order is found per cell without a general sort: a cell of m members
 //    gets B = 2^floor(log2 m) buckets on the top bits of the uniform keys
 //    (one or two members per bucket); an LDS histogram and scan place the
 //    members bucket by bucket, and a member's exact position is its bucket
@@ -103,16 +104,17 @@ constexpr int kPairRows = 2;
 constexpr int kTriChunks = 32;
 
 constexpr int kCB = 256;               // lanes per ordering workgroup
-constexpr int kEPT = kCoulMaxE / kCB;  // slots per lane at most
+constexpr int kEPT = kCoulMaxE / kCB;  // pool members per lane at most
 
 struct CoulShared {
-  uint64_t skey[kCoulMaxE];         // (key << 32) | id, in slot order
-  uint32_t r1[kCoulMaxE + 2];       // cell flags and scan scratch, then the bucket histogram
-  uint16_t hd[kCoulMaxE];           // cell (head) index of each slot of the chunk
-  uint16_t hcell[kCoulMaxE + 1];    // first slot of each cell (steps 2-3), then its first bucket
+  uint64_t skey[kCoulMaxE];         // (key << 32) | slot of each pool member, in slot order
+  uint32_t r1[kCoulMaxE + 2];       // member cells, then cell flags and scan scratch, then the bucket histogram
+  uint16_t hd[kCoulMaxE];           // cell (head) index of each member
+  uint16_t hcell[kCoulMaxE + 1];    // first member of each cell (steps 2-3), then its first bucket
   uint16_t ord[kCoulMaxE];          // members bucket by bucket
   uint32_t lead[kEPT * (kCB / 64)];  // leaders per (pass, wavefront): pairs | triplets << 16
   uint32_t wsum[kCB / 64];
+  uint32_t grp[2][kEPT * (kCB / 64)];  // step 1's member counts per pass and wave, by group parity
 };
 
 // Inclusive sums over a wavefront with DPP lane moves, no LDS: row_shr 1,
@@ -196,74 +198,146 @@ __global__ void k_coul_chunks(const uint32_t *__restrict__ cellid, const uint32_
   chunk_lo[b] = st == (uint32_t)t ? (uint32_t)t : cell_off[c + 1];
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const uint32_t *__restrict__ cellid,
-                                                    const uint32_t *__restrict__ chunk_lo,
-                                                    DevAccum *__restrict__ accum, CoulItem *__restrict__ items,
-                                                    uint2 *__restrict__ counts, StepArg sa,
-                                                    uint32_t *__restrict__ zero, int64_t zero_n) {
-  __shared__ CoulShared sh;
-  const uint32_t step = sa.get();
+// the ordering of one chunk.  CMP: the chunk holds more than kCoulMaxE
+// slots, so only its pool members (ions) are staged, compacted in slot
+// order, with skey = (key << 32) | slot; else every slot is staged with
+// skey = (key << 32) | id, atoms as entries in no pool.  Both give the same
+// pool order and so the same work items.
+template <typename R, bool CMP>
+__device__ __forceinline__ void order_chunk(const KParams &P, Soa<R> S, const uint32_t *__restrict__ cellid,
+                                            DevAccum *__restrict__ accum, CoulItem *__restrict__ items,
+                                            uint2 *__restrict__ counts, uint32_t step, int64_t s_lo, int nsl,
+                                            CoulShared &sh) {
   const int tid = threadIdx.x;
-  if (zero) {
-    // the next step's cell grids, cleared here, a slice per workgroup,
-    // instead of by a kernel of their own (the push fills them afterwards)
-    const int64_t per = (zero_n + gridDim.x - 1) / gridDim.x;
-    const int64_t z0 = (int64_t)blockIdx.x * per, z1 = min(z0 + per, zero_n);
-    for (int64_t t = z0 + tid; t < z1; t += kCB) zero[t] = 0u;
+  const int lane = tid & 63, wv = tid >> 6;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // 1. the pool members (ions) of the chunk, compacted in slot order, with
+  //    their pairing keys: skey = (key << 32) | slot, and the cell in r1.
+  //    Atoms take no LDS, so a cell crowded with atoms (the gas inlet's,
+  //    where recycled particles return) cannot overflow it; the capacity
+  //    bounds the ions of a chunk
+  constexpr int kLead = kEPT * (kCB / 64);  // (pass, wavefront) entries of a group
+  static_assert(kLead <= 64, "per-wave counts fit one wavefront");
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);  // uniform over the wavefront
+  int ns;  // entries: pool members (CMP), or every slot of the chunk
+  bool pool[kEPT];
+  uint32_t key[kEPT], myslot[kEPT], myid[kEPT];
+  if constexpr (!CMP) {
+    // a chunk that fits: every slot is an entry, (key << 32) | id in skey,
+    // the cell in r1; atoms are entries that are in no pool
+    ns = nsl;
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+      const int i = tid + k * kCB;
+      pool[k] = false;
+      key[k] = myslot[k] = myid[k] = 0u;
+      if (i < ns) {
+        const int64_t j = s_lo + i;
+        const uint32_t id = S.pid[j];
+        sh.r1[i] = cellid[j];
+        pool[k] = q_of(S.qs[j]) >= 1;
+        if (pool[k]) key[k] = draw(P, id, step, S_STEP, 0).z;
+        sh.skey[i] = ((uint64_t)key[k] << 32) | id;
+      }
+    }
+    __syncthreads();
+  } else {
+  uint32_t nm = 0;  // members so far, uniform over the workgroup
+  // groups of kEPT passes of kCB slots (one group unless the chunk holds
+  // more than kCoulMaxE slots): ballots, one barrier, then each member's
+  // index from a scan of the per-wave counts
+  for (int g0 = 0; g0 < nsl; g0 += kEPT * kCB) {
+    uint32_t *gc = sh.grp[(g0 / (kEPT * kCB)) & 1];
+    bool pl[kEPT];
+    uint32_t cc[kEPT], kk[kEPT];
+    uint64_t bm[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+      const int i = g0 + tid + k * kCB;
+      pl[k] = false;
+      cc[k] = kk[k] = 0u;
+      if (i < nsl) {
+        // the three loads issued together (one round of memory latency)
+        const int64_t j = s_lo + i;
+        const uint8_t qs = S.qs[j];
+        const uint32_t id = S.pid[j];
+        cc[k] = cellid[j];
+        pl[k] = q_of(qs) >= 1;
+        if (pl[k]) kk[k] = draw(P, id, step, S_STEP, 0).z;
+      }
+      bm[k] = __ballot(pl[k]);
+      if (lane == 0) gc[k * (kCB / 64) + wv] = (uint32_t)__popcll(bm[k]);
+    }
+    __syncthreads();
+    const uint32_t c = lane < kLead ? gc[lane] : 0u;
+    const uint32_t incl = wave_incl_scan(c), excl = incl - c;
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+      const uint32_t m = nm + (uint32_t)__builtin_amdgcn_readlane((int)excl, k * (kCB / 64) + wvu) +
+                         (uint32_t)__popcll(bm[k] & below);
+      if (pl[k] && m < (uint32_t)kCoulMaxE) {
+        sh.skey[m] = ((uint64_t)kk[k] << 32) | (uint32_t)(g0 + tid + k * kCB);
+        sh.r1[m] = cc[k];
+      }
+    }
+    nm += (uint32_t)__builtin_amdgcn_readlane((int)incl, kLead - 1);
   }
-  const int64_t s_lo = chunk_lo[blockIdx.x];
-  const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
-  if (ns <= 1) return;
-  if (ns > kCoulMaxE) {
-    if (tid == 0) atomicOr(&accum->err, ERR_COUL_OVERFLOW);
+  if (nm <= 1u || nm > (uint32_t)kCoulMaxE) {
+    if (tid == 0) {
+      if (nm > (uint32_t)kCoulMaxE) atomicOr(&accum->err, ERR_COUL_OVERFLOW);
+      counts[blockIdx.x] = make_uint2(0u, 0u);
+    }
     return;
   }
-  uint32_t *flags = sh.r1;
-  // one array serves twice: the cells' first slots are last read in step 3,
-  // before the scan after which their first buckets are written (20 KB of
-  // LDS in all, so eight workgroups share a CU)
+  __syncthreads();  // the members are in LDS
+  // from here on an index i counts the chunk's pool members (in slot order)
+  ns = (int)nm;
+  // each lane's members: key, slot, and the particle id (loaded now, used
+  // by the work items at the end, so the load's latency is hidden)
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int i = tid + k * kCB;
+    pool[k] = i < ns;
+    const uint64_t sk = pool[k] ? sh.skey[i] : 0ull;
+    key[k] = (uint32_t)(sk >> 32);
+    myslot[k] = (uint32_t)sk;
+    myid[k] = pool[k] ? S.pid[s_lo + myslot[k]] : 0u;
+  }
+  }
+  // one array serves twice: the cells' first entries are last read in step
+  // 3, before the scan after which their first buckets are written (18.5 KB
+  // of LDS in all, so eight workgroups share a CU)
   uint16_t *const hstart = sh.hcell, *const hbase = sh.hcell;
-  // 1. coalesced loads: cell, pool flag, pairing key
-  bool pool[kEPT];
-  uint32_t key[kEPT];
-#pragma unroll
-  for (int k = 0; k < kEPT; ++k) {
-    const int i = tid + k * kCB;
-    pool[k] = false;
-    key[k] = 0;
-    if (i < ns) {
-      const int64_t j = s_lo + i;
-      const uint32_t id = S.pid[j];
-      pool[k] = q_of(S.qs[j]) >= 1;
-      if (pool[k]) key[k] = draw(P, id, step, S_STEP, 0).z;
-      sh.skey[i] = ((uint64_t)key[k] << 32) | id;
-    }
-  }
-  __syncthreads();
-  // 2. cells of the chunk: heads, cell index of every slot, first slot of every cell
+  // 2. cells of the members: heads (ballots per pass and wave, one
+  //    barrier, a scan of the counts), cell index of every member, first
+  //    member of every cell
   uint32_t fl[kEPT];
+  uint64_t hb[kEPT];
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int i = tid + k * kCB;
-    fl[k] = (i < ns && (i == 0 || cellid[s_lo + i] != cellid[s_lo + i - 1])) ? 1u : 0u;
-    if (i < ns) flags[i] = fl[k];
+    fl[k] = (i < ns && (i == 0 || sh.r1[i] != sh.r1[i - 1])) ? 1u : 0u;
+    hb[k] = __ballot(fl[k] != 0u);
+    if (lane == 0) sh.lead[k * (kCB / 64) + wv] = (uint32_t)__popcll(hb[k]);
   }
   __syncthreads();
-  const int nheads = (int)wg_exscan(flags, ns, sh.wsum);
+  const uint32_t hc = lane < kLead ? sh.lead[lane] : 0u;
+  const uint32_t hincl = wave_incl_scan(hc), hexcl = hincl - hc;
+  const int nheads = __builtin_amdgcn_readlane((int)hincl, kLead - 1);
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int i = tid + k * kCB;
     if (i < ns) {
-      const int h = (int)(flags[i] + fl[k]) - 1;
+      const int h = __builtin_amdgcn_readlane((int)hexcl, k * (kCB / 64) + wvu) + (int)__popcll(hb[k] & below) +
+                    (int)fl[k] - 1;
       sh.hd[i] = (uint16_t)h;
       if (fl[k]) hstart[h] = (uint16_t)i;
     }
   }
   if (tid == 0) hstart[nheads] = (uint16_t)ns;
   __syncthreads();
-  // 3. buckets per cell: B = 2^floor(log2(slots of the cell)), so at most
-  //    one bucket per slot of the chunk
+  // 3. buckets per cell: B = 2^floor(log2(members of the cell)), so at most
+  //    one bucket per member
   for (int h = tid; h < nheads; h += kCB) {
     const int m = hstart[h + 1] - hstart[h];
     const int lg = m <= 1 ? 0 : 31 - __clz(m);
@@ -302,7 +376,13 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     if (i < ns && pool[k]) sh.ord[hist[bk[k]] + arr[k]] = (uint16_t)i;
   }
   __syncthreads();
-  // 8. exact pool position: bucket offset + bucket mates with a smaller (key, id)
+  // 8. exact pool position: bucket offset + bucket mates with a smaller
+  //    (key, id); equal keys (rare) fetch the two ids
+  auto precedes = [&](uint64_t o, uint64_t me) -> int {
+    const uint32_t ko = (uint32_t)(o >> 32), km = (uint32_t)(me >> 32);
+    if (ko != km || o == me) return ko < km ? 1 : 0;  // (o == me: the member itself)
+    return S.pid[s_lo + (uint32_t)o] < S.pid[s_lo + (uint32_t)me] ? 1 : 0;
+  };
   int pos[kEPT], rr[kEPT], mm[kEPT];
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
@@ -312,7 +392,11 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
       const uint64_t me = sh.skey[i];
       const int b0 = (int)hist[bk[k]], b1 = (int)hist[bk[k] + 1];
       int rib = 0;
-      for (int t = b0; t < b1; ++t) rib += sh.skey[sh.ord[t]] < me ? 1 : 0;
+      if constexpr (CMP) {
+        for (int t = b0; t < b1; ++t) rib += precedes(sh.skey[sh.ord[t]], me);
+      } else {
+        for (int t = b0; t < b1; ++t) rib += sh.skey[sh.ord[t]] < me ? 1 : 0;
+      }
       pos[k] = b0 + rib;
       const int h = sh.hd[i];
       const int pstart = (int)hist[hbase[h]];
@@ -330,9 +414,7 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     const int i = tid + k * kCB;
     if (i < ns && pool[k]) sh.ord[pos[k]] = (uint16_t)i;
   }
-  const int lane = tid & 63, wv = tid >> 6;
-  const int nk = (ns + kCB - 1) / kCB;  // passes that hold slots of the chunk
-  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int nk = (ns + kCB - 1) / kCB;  // passes that hold members
   int lt[kEPT], li[kEPT];
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
@@ -362,13 +444,10 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
   // exclusive scan of the leader counts in (pass, wavefront) order, which is
   // slot order; pairs and triplets side by side in one word (each at most
   // kCoulItems, so the low half never carries into the high one)
-  constexpr int kLead = kEPT * (kCB / 64);
-  static_assert(kLead <= 64, "leader counts fit one wavefront");
   const uint32_t c = lane < nk * (kCB / 64) ? sh.lead[lane] : 0u;
   const uint32_t incl = wave_incl_scan(c), excl = incl - c;
   const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kLead - 1);
   const int np = (int)(tot & 0xffffu);
-  const int wvu = __builtin_amdgcn_readfirstlane(wv);  // uniform over the wavefront
   uint32_t before[kEPT];
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) before[k] = (uint32_t)__builtin_amdgcn_readlane((int)excl, k * (kCB / 64) + wvu);
@@ -378,15 +457,51 @@ __global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const u
     if (lt[k]) {
       const int p = pos[k];
       CoulItem e;
-      e.a = sh.ord[p];
-      e.b = sh.ord[p + 1];
-      e.c = lt[k] == 2 ? sh.ord[p + 2] : (uint16_t)0;
+      if constexpr (CMP) {
+        e.a = (uint16_t)myslot[k];  // the leader is the member at pool position p
+        e.b = (uint16_t)sh.skey[sh.ord[p + 1]];  // member -> its slot in the chunk
+        e.c = lt[k] == 2 ? (uint16_t)sh.skey[sh.ord[p + 2]] : (uint16_t)0;
+        e.id = myid[k];
+      } else {
+        e.a = sh.ord[p];
+        e.b = sh.ord[p + 1];
+        e.c = lt[k] == 2 ? sh.ord[p + 2] : (uint16_t)0;
+        e.id = (uint32_t)sh.skey[e.a];
+      }
       e.m = (uint16_t)mm[k];
-      e.id = (uint32_t)sh.skey[e.a];
       out[lt[k] == 1 ? (int)(before[k] & 0xffffu) + li[k] : np + (int)(before[k] >> 16) + li[k]] = e;
     }
   }
   if (tid == 0) counts[blockIdx.x] = make_uint2((uint32_t)np, tot >> 16);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kCB) k_coul_order(KParams P, Soa<R> S, const uint32_t *__restrict__ cellid,
+                                                    const uint32_t *__restrict__ chunk_lo,
+                                                    DevAccum *__restrict__ accum, CoulItem *__restrict__ items,
+                                                    uint2 *__restrict__ counts, StepArg sa,
+                                                    uint32_t *__restrict__ zero, int64_t zero_n) {
+  __shared__ CoulShared sh;
+  const uint32_t step = sa.get();
+  const int tid = threadIdx.x;
+  if (zero) {
+    // the next step's cell grids, cleared here, a slice per workgroup,
+    // instead of by a kernel of their own (the push fills them afterwards)
+    const int64_t per = (zero_n + gridDim.x - 1) / gridDim.x;
+    const int64_t z0 = (int64_t)blockIdx.x * per, z1 = min(z0 + per, zero_n);
+    for (int64_t t = z0 + tid; t < z1; t += kCB) zero[t] = 0u;
+  }
+  const int64_t s_lo = chunk_lo[blockIdx.x];
+  const int nsl = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);  // slots of the chunk
+  if (nsl <= 1 || nsl > 0xffff) {  // no pool, or slots past the items' 16-bit fields
+    if (tid == 0) {
+      if (nsl > 0xffff) atomicOr(&accum->err, ERR_COUL_OVERFLOW);
+      counts[blockIdx.x] = make_uint2(0u, 0u);
+    }
+    return;
+  }
+  if (nsl <= kCoulMaxE) order_chunk<R, false>(P, S, cellid, accum, items, counts, step, s_lo, nsl, sh);
+  else order_chunk<R, true>(P, S, cellid, accum, items, counts, step, s_lo, nsl, sh);
 }
 
 // collisions, one per lane, so that every collision of the step is in
@@ -425,7 +540,7 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
     if (lane < kTriChunks && b + lane < nchunks) {
       my_lo = chunk_lo[b + lane];
       const int ns = (int)(chunk_lo[b + lane + 1] - my_lo);
-      if (ns > 1 && ns <= kCoulMaxE) {  // else no pool, or skipped by the ordering (overflow flagged there)
+      if (ns > 1) {  // else no pool (an overflowing chunk has zero counts, flagged by the ordering)
         const uint2 c = counts[b + lane];
         my_np = c.x;
         nt = c.y;
@@ -465,7 +580,7 @@ k_coul_pairs(KParams P, const Tables *__restrict__ T, Soa<R> S,
   const int y = (int)blockIdx.y - 1;
   const int64_t s_lo = chunk_lo[b];
   const int ns = (int)((int64_t)chunk_lo[b + 1] - s_lo);
-  if (ns <= 1 || ns > kCoulMaxE) return;
+  if (ns <= 1) return;
   const int np = (int)counts[b].x;
   if (y * 64 >= np) return;
   // rows beyond kPairRows are folded onto these (rare: > 64 kPairRows pairs)

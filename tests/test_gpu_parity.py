@@ -592,3 +592,29 @@ def test_kernel_timing_every_launch_and_sampled():
     import paper_1507_03392_amd as ecr
     with pytest.raises(ecr.EcrError):
         a.profile(True, stride=0)
+
+
+def test_coulomb_in_a_cell_crowded_with_atoms():
+    # over a long run the gas inlet's cell fills with recycled atoms (more
+    # than a Coulomb chunk can stage): atoms take no room in the ordering,
+    # so a cell of 3000 atoms and 300 ions keeps its collisions, bit for bit
+    params = W.base_params(20_011, 16, 16, 32, seed=5)
+    params.update(process_mask=W.P_COULOMB, weight=4e9)
+    st = W.random_state(params, seed=55, q_max=8, v_ev=5.0, frac_atoms=0.1)
+    hx, hz = 2 * params["R0"] / 16, params["L"] / 32
+    rng = np.random.default_rng(56)
+    k = 3300
+    st["x"][:k] = -params["R0"] + (8.2 + 0.6 * rng.random(k)) * hx
+    st["y"][:k] = -params["R0"] + (8.2 + 0.6 * rng.random(k)) * hx
+    st["z"][:k] = -params["L"] / 2 + (1.2 + 0.6 * rng.random(k)) * hz
+    st["q"][:3000] = 0
+    st["q"][3000:k] = rng.integers(1, 9, k - 3000)
+    g, o = run_pair(params, st, 1, step0=3)
+    a, b = g.get_state(), o.get_state()
+    assert_state_close(a, b, params, what="crowded cell")
+    assert np.bincount(b["cell"].astype(np.int64)).max() >= k
+    tg, to = g.tallies(), o.tallies()
+    assert tg["anomalies"] == 0  # no chunk overflowed
+    assert tg["coul_e"] == pytest.approx(to["coul_e"], rel=1e-12)
+    moved = (a["vx"][3000:k] != st["vx"][3000:k]).mean()
+    assert moved > 0.9  # the crowded cell's ions did collide
