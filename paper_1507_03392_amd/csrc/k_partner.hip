@@ -28,13 +28,18 @@ namespace ecr {
 
 namespace {
 
-constexpr int kPB = 256;                // lanes per workgroup
-constexpr int kPEPT = kCoulMaxE / kPB;  // slots per lane at most
+constexpr int kPB = 256;  // lanes per workgroup
+// slots a chunk may hold: four times the Coulomb ordering's, since the
+// candidates are atoms and the gas inlet's cell gathers recycled atoms
+// (about 2000 at 2M ions after 50k steps); 53 KB of LDS, but a workgroup
+// without requests returns after one load
+constexpr int kPMaxE = 4 * kCoulMaxE;
+constexpr int kPEPT = kPMaxE / kPB;  // slots per lane at most
 
 struct PartnerShared {
-  uint64_t kv[kCoulMaxE];    // (key << 32) | id of a candidate
-  uint32_t cell[kCoulMaxE];  // collision cell of every slot of the chunk
-  uint8_t spc[kCoulMaxE];    // species of a candidate, 0xFF for any other slot
+  uint64_t kv[kPMaxE];    // (key << 32) | id of a candidate
+  uint32_t cell[kPMaxE];  // collision cell of every slot of the chunk
+  uint8_t spc[kPMaxE];    // species of a candidate, 0xFF for any other slot
 };
 
 }  // namespace
@@ -49,7 +54,7 @@ __global__ void __launch_bounds__(kPB) k_cx_partner(KParams P, Soa<R> S, const u
   const int64_t s_lo = chunk_lo[blockIdx.x];
   const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
   if (ns <= 0 || P.cxchunk[blockIdx.x] == 0u) return;
-  if (ns > kCoulMaxE) {
+  if (ns > kPMaxE) {
     if (tid == 0) atomicOr(&acc->err, ERR_PARTNER_OVERFLOW);
     return;
   }
