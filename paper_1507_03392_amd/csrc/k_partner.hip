@@ -22,6 +22,15 @@
 //     channel to the ion charge channel of the cell it is in.
 // The work is proportional to the requesting cells only; the default step
 // never launches it.
+//
+// A chunk of more slots than the LDS holds (the gas inlet's cell gathers
+// thousands of recycled atoms in long runs) takes the same decisions from
+// global memory instead: cell by cell, for each requesting species, the
+// workgroup picks the candidates of lowest (key, id) one at a time by
+// minimum reductions over the cell, each bounded below by the previous
+// pick.  The candidates of rank below the requests are the same ones, so
+// the result does not depend on the path; the cost is one pass over the
+// cell per request, and requests are rare.
 #include "ecr_kernels.hpp"
 
 namespace ecr {
@@ -42,6 +51,72 @@ struct PartnerShared {
   uint8_t spc[kPMaxE];    // species of a candidate, 0xFF for any other slot
 };
 
+// the smallest of the workgroup's 64-bit values (all lanes call it)
+__device__ __forceinline__ uint64_t wg_min_u64(uint64_t v, uint64_t *red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  __syncthreads();  // red may still be read by the previous call
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t m = red[0];
+  for (int w = 1; w < kPB / 64; ++w) m = red[w] < m ? red[w] : m;
+  return m;
+}
+
+// a chunk beyond the LDS capacity: every decision from global memory
+template <typename R>
+__device__ void partner_chunk_global(const KParams &P, Soa<R> S, int64_t s_lo, int64_t s_hi,
+                                     uint32_t *__restrict__ chg, uint8_t *__restrict__ evlog,
+                                     DevAccum *__restrict__ acc, uint32_t step, uint64_t *red) {
+  const int tid = threadIdx.x;
+  int64_t c_lo = s_lo;
+  while (c_lo < s_hi) {  // uniform: every lane walks the same cells
+    const uint32_t c = P.cellid[c_lo];
+    const int64_t c_hi = (int64_t)P.cell_off[c + 1];
+    for (int s = 0; s < P.nspecies; ++s) {
+      const uint32_t r = P.cxreq[(uint32_t)s * P.ncell + c];
+      if (r == 0u) continue;
+      uint32_t got = 0u;
+      uint64_t prev = 0ull;
+      bool first = true;
+      for (; got < r; ++got) {
+        // the smallest (key, id) above the previous pick among the cell's
+        // atoms of species s that did not become atoms in this step
+        uint64_t best = ~0ull;
+        for (int64_t j = c_lo + tid; j < c_hi; j += kPB) {
+          const uint8_t qs = S.qs[j];
+          if (q_of(qs) != 0 || sp_of(qs) != s || S.birth[j] == step) continue;
+          const uint32_t id = S.pid[j];
+          const uint64_t kv = ((uint64_t)draw(P, id, step, S_STEP, 0).w << 32) | id;
+          if ((first || kv > prev) && kv < best) best = kv;
+        }
+        const uint64_t m = wg_min_u64(best, red);
+        if (m == ~0ull) break;  // no candidate left (an id is below 2^31, so no real key is ~0)
+        prev = m;
+        first = false;
+        // the owner of the pick converts it
+        for (int64_t j = c_lo + tid; j < c_hi; j += kPB) {
+          if (S.pid[j] != (uint32_t)m) continue;
+          S.qs[j] = make_qs(1, s);
+          S.birth[j] = step;
+          if (evlog) evlog[j] = EV_CX_PARTNER;
+          const uint32_t cc = cell_of<R>(P, S.x[j], S.y[j], S.z[j]);
+          atomicAdd(&chg[cc], 1u);
+          atomicSub(&chg[(uint32_t)(1 + s) * P.ncell + cc], 1u);
+        }
+      }
+      __syncthreads();  // every lane has read the request before it is cleared
+      if (tid == 0) {
+        if (r > got) atomicAdd((unsigned long long *)&acc->t.cx_unmatched[s], (unsigned long long)(r - got));
+        P.cxreq[(uint32_t)s * P.ncell + c] = 0u;
+      }
+    }
+    c_lo = c_hi;
+  }
+}
+
 }  // namespace
 
 template <typename R>
@@ -55,7 +130,10 @@ __global__ void __launch_bounds__(kPB) k_cx_partner(KParams P, Soa<R> S, const u
   const int ns = (int)((int64_t)chunk_lo[blockIdx.x + 1] - s_lo);
   if (ns <= 0 || P.cxchunk[blockIdx.x] == 0u) return;
   if (ns > kPMaxE) {
-    if (tid == 0) atomicOr(&acc->err, ERR_PARTNER_OVERFLOW);
+    __shared__ uint64_t red[kPB / 64];
+    partner_chunk_global<R>(P, S, s_lo, s_lo + ns, chg, evlog, acc, step, red);
+    __syncthreads();
+    if (tid == 0) P.cxchunk[blockIdx.x] = 0u;
     return;
   }
   // 1. cells and candidates

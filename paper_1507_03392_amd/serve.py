@@ -18,7 +18,14 @@ state on the device from admission to retirement and works like this:
   admitted;
 * a request may ask for a warm-up: its first `warmup` steps are run, the
   tallies read at that point, and the result reports the tallies of the
-  remaining steps only (the stationary window the paper's outputs refer to).
+  remaining steps only (the stationary window the paper's outputs refer to);
+* a request may start from a given particle state (a checkpoint, as
+  ecr_set_state takes it) instead of the initial ions;
+* a run whose tallies report anomalies (a non-finite particle state, or a
+  per-step collision probability above the first-order limit) at any read is
+  answered with an error naming them, the tallies still attached; the
+  anomaly count in the result is the run's total, never a windowed
+  difference, so an anomaly of the warm-up is not hidden.
 
 Runs on different slots overlap on the device (their streams map to
 separate hardware queues); a run's result depends only on its own
@@ -43,6 +50,8 @@ class Request:
     params: dict
     steps: int
     warmup: int = 0     # leading steps left out of the reported tallies
+    state: dict | None = None  # initial particle state (Run.set_state) instead of init_ions
+    step0: int = 0      # step counter of that state
 
 
 @dataclasses.dataclass
@@ -72,6 +81,7 @@ class _Active:
     done: int = 0
     event: object = None
     base: dict | None = None  # tallies at the end of the warm-up
+    halt: bool = False        # retire at the next poll: the run failed
 
 
 class Server:
@@ -145,7 +155,10 @@ class Server:
                 slot = free.pop()
                 try:
                     run = Run(req.params, stream=self.streams[slot], device=self.device)
-                    run.init_ions()
+                    if req.state is not None:
+                        run.set_state(req.state, step=req.step0)
+                    else:
+                        run.init_ions()
                 except EcrError as e:
                     free.append(slot)
                     res.error, res.finished = str(e), now()
@@ -168,12 +181,18 @@ class Server:
                         a.base = a.run.tallies()
                     except EcrError as e:
                         a.res.error = str(e)
-                        a.done = a.req.steps
-                if a.done >= a.req.steps:
+                        a.halt = True
+                    else:
+                        if a.base["anomalies"] > 0:
+                            a.res.error = _anomaly_error(a.run, a.base, "warm-up")
+                            a.halt = True
+                if a.done >= a.req.steps or a.halt:
                     try:
                         t = a.run.tallies()
                         a.res.tallies = tallies_window(t, a.base) if a.base is not None else t
                         a.res.density = {f: a.run.density(f)[0] for f in self.fields}
+                        if t["anomalies"] > 0 and a.res.error is None:
+                            a.res.error = _anomaly_error(a.run, t, "run")
                     except EcrError as e:
                         a.res.error = str(e)
                     a.res.finished = now()
@@ -209,11 +228,20 @@ class Server:
 
 
 def tallies_window(t, base):
-    """Tallies accumulated between two reads of one run (t later than base)."""
+    """Tallies accumulated between two reads of one run (t later than base).
+    The anomaly count stays the run's total: anomalies are never windowed."""
     out = {}
     for k, v in t.items():
-        out[k] = v - base[k]
+        out[k] = v if k == "anomalies" else v - base[k]
     return out
+
+
+def _anomaly_error(run, t, where):
+    from . import lib
+    msg = lib().ecr_last_error(run.h)
+    detail = msg.decode() if msg else ""
+    return (f"ECR_ENUMERIC: {t['anomalies']} anomalies by the end of the {where} "
+            f"({detail or 'non-finite state or per-step collision probability above 0.1'})")
 
 
 def summary(results):

@@ -211,10 +211,18 @@ def test_fp32_two_species_c4_full_size_sampled_cells():
     # FP32-mixed; after 60 steps whole collision cells are stepped
     # once more by the FP64 oracle from the same (binary32) state
     from oracle.binding import OracleSim
+    from test_gpu_parity import host_cells
     params, _ = W.config("c4")
     g = gpu_run(params, events=True)
     g.init_ions()
-    g.step(60)
+    g.step(50)
+    # the sort at step 50 over 10M binary32 positions: floor-and-clamp in
+    # binary32 arithmetic gives every particle's collision cell
+    s50 = g.get_state()
+    g.step(1)
+    assert np.array_equal(g.get_state()["cell"], host_cells(params, s50, np.float32)), "c4 sort cells"
+    del s50
+    g.step(9)
     before = g.get_state()
     g.step(1)
     after = g.get_state()

@@ -85,12 +85,19 @@ def test_division_and_sqrt_correctly_rounded():
     import paper_1507_03392_amd as ecr
     rng = np.random.default_rng(0)
     n = 2_000_000
-    a = np.exp(rng.uniform(-700, 700, n)) * rng.choice([1.0], n)
-    b = np.exp(rng.uniform(-700, 700, n)) * rng.choice([-1.0, 1.0], n)
+    # operands within e^+-350, so that every quotient is a finite normal
+    # number (|ln q| <= 700 < 708): the rounding of the quotient is what is
+    # tested, not overflow to inf or underflow to 0
+    a = np.exp(rng.uniform(-350, 350, n))
+    b = np.exp(rng.uniform(-350, 350, n)) * rng.choice([-1.0, 1.0], n)
+    # a few ends of the range: zero, subnormal and largest operands
     a[:6] = [0.0, 1.0, 2.0, 5e-324, 1.7976931348623157e308, 2.2250738585072014e-308]
-    b[:6] = [3.0, 3.0, 7.0, 3.0, 0.7, 3.0]
+    b[:6] = [3.0, 3.0, 7.0, 3.0, 3.0, 3.0]
+    with np.errstate(over="raise", under="ignore"):
+        ref_q = a / b
+    assert np.isfinite(ref_q).all()
     q, r = ecr.selftest_divsqrt(a, b)
-    assert np.array_equal(q.view(np.uint64), (a / b).view(np.uint64))
+    assert np.array_equal(q.view(np.uint64), ref_q.view(np.uint64))
     assert np.array_equal(r.view(np.uint64), np.sqrt(a).view(np.uint64))
 
 
@@ -533,6 +540,23 @@ def test_edt_rejected_and_bad_state():
     assert e.value.status == -5
 
 
+def host_cells(params, st, dtype=np.float64):
+    """Collision cell of each particle by floor-and-clamp of its position, in
+    the arithmetic of the state's precision (binary64, or binary32 for the
+    FP32-mixed state): i = clamp(floor((x + R0) * nx / (2 R0)), 0, nx - 1),
+    likewise for y, and for z with (z + L/2) * nz / L."""
+    R0, hL = params["R0"], 0.5 * params["L"]
+    idx = params["nx"] / (2.0 * R0)
+    idy = params["ny"] / (2.0 * R0)
+    idz = params["nz"] / params["L"]
+    t = dtype
+    with np.errstate(invalid="ignore"):
+        ix = np.clip(np.floor((st["x"].astype(t) + t(R0)) * t(idx)), 0, params["nx"] - 1).astype(np.int64)
+        iy = np.clip(np.floor((st["y"].astype(t) + t(R0)) * t(idy)), 0, params["ny"] - 1).astype(np.int64)
+        iz = np.clip(np.floor((st["z"].astype(t) + t(hL)) * t(idz)), 0, params["nz"] - 1).astype(np.int64)
+    return (ix + params["nx"] * (iy + params["ny"] * iz)).astype(np.uint32)
+
+
 def test_full_size_c2_sampled_cells():
     # 2M ions on the 64x64x128 grid, the benchmark's launch configuration:
     # after 60 steps, whole collision cells are stepped once more by the oracle
@@ -540,7 +564,13 @@ def test_full_size_c2_sampled_cells():
     params, _ = W.config("c2")
     g = gpu_run(params, events=True)
     g.init_ions()
-    g.step(60)
+    g.step(50)
+    # the sort at step 50 at full size: every particle's collision cell is
+    # floor-and-clamp of its position at the start of that step
+    s50 = g.get_state()
+    g.step(1)
+    assert np.array_equal(g.get_state()["cell"], host_cells(params, s50)), "c2 sort cells"
+    g.step(9)
     before = g.get_state()
     g.step(1)
     after = g.get_state()
@@ -592,6 +622,65 @@ def test_kernel_timing_every_launch_and_sampled():
     import paper_1507_03392_amd as ecr
     with pytest.raises(ecr.EcrError):
         a.profile(True, stride=0)
+
+
+def test_step_batch_matches_separate_steps():
+    # ecr_step_batch advances several runs that share a stream: the same
+    # state, events and tallies bit for bit as each run stepped alone
+    import torch
+
+    import paper_1507_03392_amd as ecr
+    stream = torch.cuda.Stream()
+    cases = []
+    for i, (n, q) in enumerate(((3_001, 3), (20_011, 8), (700, 1))):
+        p = boosted(W.base_params(n, 16, 16, 32, seed=40 + i))
+        p.update(process_mask=W.P_ALL, sort_every=7)
+        cases.append((p, W.random_state(p, seed=90 + i, q_max=q, v_ev=30.0)))
+    runs = []
+    for p, st in cases:
+        r = gpu_run(p, events=True, stream=stream)
+        r.set_state(st, step=5)
+        runs.append(r)
+    ecr.step_batch(runs, 11, stream)
+    ecr.step_batch(runs, 9, stream)
+    stream.synchronize()
+    for (p, st), r in zip(cases, runs):
+        alone = gpu_run(p, events=True)
+        alone.set_state(st, step=5)
+        alone.step(20)
+        a, b = r.get_state(), alone.get_state()
+        for k in ("x", "y", "z", "vx", "vy", "vz", "q", "cell", "birth"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["step"] == b["step"] == 25
+        assert np.array_equal(r.events(), alone.events())
+        assert_tallies_equal(r.tallies(), alone.tallies(), "batch vs alone")
+
+
+def test_exchange_partners_in_a_chunk_beyond_the_lds():
+    # a cell of 5000 atoms (more slots than the exchange-partner kernel
+    # stages in LDS) whose ions exchange charge: the partners are picked
+    # from global memory, bit for bit with the oracle
+    params = boosted(W.base_params(20_011, 16, 16, 32, seed=9), n0=3e19)
+    params.update(process_mask=W.P_CX | W.P_PUSH, self_n0=True, cx_partner=True, weight=4e10)
+    st = W.random_state(params, seed=57, q_max=4, v_ev=20.0, frac_atoms=0.2)
+    hx, hz = 2 * params["R0"] / 16, params["L"] / 32
+    rng = np.random.default_rng(58)
+    k = 5600
+    st["x"][:k] = -params["R0"] + (8.3 + 0.4 * rng.random(k)) * hx
+    st["y"][:k] = -params["R0"] + (8.3 + 0.4 * rng.random(k)) * hx
+    st["z"][:k] = -params["L"] / 2 + (1.3 + 0.4 * rng.random(k)) * hz
+    st["q"][:5000] = 0
+    st["q"][5000:k] = rng.integers(1, 5, k - 5000)
+    g, o = run_pair(params, st, 2, step0=3)  # the oracle takes 7 partners in the crowded cell
+    a, b = g.get_state(), o.get_state()
+    assert np.array_equal(g.events(), o.events())
+    assert_state_close(a, b, params, what="partners beyond the LDS")
+    tg, to = g.tallies(), o.tallies()
+    assert_tallies_equal(tg, to, "partners beyond the LDS")
+    assert tg["anomalies"] == 0
+    crowded = np.bincount(o.get_state()["cell"].astype(np.int64)).max()
+    assert crowded >= 5000
+    assert int((o.events()[:k] == W.EV_CX_PARTNER).sum()) > 0  # partners were taken in the crowded cell
 
 
 def test_coulomb_in_a_cell_crowded_with_atoms():

@@ -86,3 +86,25 @@ def test_admission_by_footprint_and_errors():
     assert out[6].error
     for r in out[:5]:
         assert r.error is None and r.tallies["steps"] == 60
+
+
+def test_anomalies_are_reported_not_windowed():
+    """A run whose state goes non-finite is answered with an error, both
+    when it happens inside the warm-up and after it; the anomaly count of
+    the result is the run's total, not the warm-up-subtracted window."""
+    from paper_1507_03392_amd.serve import Request, Server
+    good = _scan(n_req=1, steps=60)[0]
+    p = W.base_params(4_000, 16, 16, 32, seed=11)
+    st = W.random_state(p, seed=3, q_max=3, v_ev=1.0)
+    st["vx"] = st["vx"].copy()
+    st["vx"][17] = float("nan")
+    reqs = [good,
+            Request(rid=1, arrival=0.0, params=p, steps=60, warmup=20, state=st),
+            Request(rid=2, arrival=0.0, params=p, steps=60, state=st)]
+    out = Server(hbm_budget=1 << 34, max_active=3).serve(reqs)
+    assert out[0].error is None
+    for r in out[1:]:
+        assert r.error is not None and "ECR_ENUMERIC" in r.error, r.error
+        assert r.tallies is None or r.tallies["anomalies"] > 0
+    # the run without warm-up carries its tallies, anomalies included
+    assert out[2].tallies is not None and out[2].tallies["anomalies"] > 0

@@ -4,11 +4,18 @@ Philox (Salmon et al., SC'11) is not in the paper; it is the counter-based
 generator both sides draw from.  The oracle builds its 4x32 and 4x64
 instances from one round macro; the 4x64 instance is checked bit-for-bit
 against numpy's independent Philox4x64-10, which pins the round structure
-(word permutation, xor placement, key schedule).  The 4x32 instance is then
-pinned by its Weyl constants (derived here from the golden ratio and sqrt 3)
-and by statistics.
+(word permutation, xor placement, key schedule).  The 4x32 instance, the one
+both sides draw from, is checked bit-for-bit against PyTorch's header-only
+at::Philox4_32 engine (an independent implementation, compiled here with
+g++) over 120 000+ counters and keys, including the all-ones counter and key:
+that pins its multipliers 0xD2511F53 / 0xCD9E8D57 as well as the round
+structure.  The Weyl constants are also derived from the golden ratio and
+sqrt 3, and the output bytes are checked for uniformity.
 """
 import math
+import os
+import shutil
+import subprocess
 from decimal import Decimal, getcontext
 
 import numpy as np
@@ -75,3 +82,51 @@ def test_u53_range_and_resolution():
         u = B.u53(int(a), int(b))
         assert 0.0 <= u < 1.0
         assert math.ldexp(u, 53) == int(math.ldexp(u, 53))  # a multiple of 2^-53
+
+
+def _torch_philox_driver(tmp_path):
+    """Build the at::Philox4_32 driver with g++ against torch's headers."""
+    torch = pytest.importorskip("torch")
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    hdr = os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")
+    if not os.path.exists(hdr):
+        pytest.skip("torch headers not installed")
+    src = os.path.join(os.path.dirname(__file__), "golden", "philox_torch_driver.cpp")
+    exe = str(tmp_path / "philox_torch")
+    subprocess.run([gxx, "-O1", "-std=c++17", "-I", inc, src, "-o", exe], check=True, capture_output=True)
+    return exe
+
+
+def test_philox4x32_matches_torch_engine(tmp_path):
+    exe = _torch_philox_driver(tmp_path)
+    rng = np.random.default_rng(2024)
+    ones = 0xFFFFFFFF
+    rows = [(0, 0, 0, 0, 0, 0), (ones, ones, ones, ones, ones, ones), (ones, 0, ones, 0, 0, ones),
+            (1, 2, 3, 4, 5, 6)]
+    rows += [tuple(int(v) for v in r) for r in rng.integers(0, 2**32, size=(2000, 6), dtype=np.uint64)]
+    # runs of consecutive counters in the layout the method uses (particle id,
+    # step, stream, call) under several seeds, one wrapping past 2^32 - 1
+    runs = [(0, 0, 1, 0, 0), (0x123456789ABCDEF, 7, 2, 0, 40_000), ((1 << 64) - 1, 0xFFFFFFFF, 4, 3, 2**32 - 20_000),
+            (3, 100, 5, 1, 123_456_789)]
+    fills = []
+    for seed, c1, c2, c3, c0 in runs:
+        n = 30_000
+        fills.append(((seed, c0, c1, c2, c3), B.philox_fill(seed, c0, c1, c2, c3, n)))
+        rows += [((c0 + i) & ones, c1, c2, c3, seed & ones, seed >> 32) for i in range(n)]
+    assert len(rows) >= 120_000
+    inp = "\n".join(" ".join(str(v) for v in r) for r in rows) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    ref = np.array(out, dtype=np.uint64).astype(np.uint32).reshape(-1, 4)
+    assert ref.shape[0] == len(rows)
+    nrand = len(rows) - sum(f.shape[0] for _, f in fills)
+    for r, want in zip(rows[:nrand], ref[:nrand]):
+        assert B.philox4x32(list(r[:4]), list(r[4:])) == [int(w) for w in want], r
+    # counter 0, key 0: 6627e8d5 e169c58d bc57ac4c 9b00dbd8
+    assert [int(w) for w in ref[0]] == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    off = nrand
+    for _, f in fills:
+        assert np.array_equal(f, ref[off:off + f.shape[0]])
+        off += f.shape[0]
