@@ -231,6 +231,26 @@ ecr_status ecr_footprint(const ecr_params *params, size_t *device_bytes);
 ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena_bytes,
                       void *hip_stream, ecr_run **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run as ecr_create, with the arena replaced by a static workspace of
+ * 64 MiB that the library holds in device memory, one per GPU it runs on,
+ * from the first call on that GPU until the process ends.  The call itself
+ * allocates no device memory (no hipMalloc, no allocating library routine).
+ * It binds the run to the current device's workspace and to hip_stream
+ * (NULL: the null stream) and returns that device's one static handle.
+ * A run whose ecr_footprint() exceeds the workspace is rejected with
+ * ECR_ENOMEM and a message giving both sizes.  The workspace keeps the last
+ * run's contents: the run is set up exactly as on an uninitialised arena
+ * (tables uploaded, tallies and density zeroed; the particle state comes
+ * from ecr_init_ions or ecr_set_state).  One static run per device at a
+ * time: a second call while one is live returns ECR_ESTATE; ecr_destroy
+ * releases the workspace for the next call (it waits for the run's stream).
+ * Runs on one device that overlap in time would race on the workspace,
+ * which is why the second call is refused.  Every other call takes the
+ * handle as it takes one of ecr_create. */
+ecr_status ecr_create_static(const ecr_params *params, void *hip_stream, ecr_run **out);
+
 /* Initial ions: uniform in the ECR-zone ellipsoid, Maxwellian at Ti0, Q = 1
  * (Sec. II); zeroes tallies and density; step counter 0. */
 ecr_status ecr_init_ions(ecr_run *run);

@@ -30,7 +30,7 @@ KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_p
 STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4: "ECR_ESTATE",
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}
 
-EXPORTS = ["ecr_footprint", "ecr_create", "ecr_init_ions", "ecr_step", "ecr_step_graph", "ecr_step_batch",
+EXPORTS = ["ecr_footprint", "ecr_create", "ecr_create_static", "ecr_init_ions", "ecr_step", "ecr_step_graph", "ecr_step_batch",
            "ecr_read_tallies", "ecr_read_density", "ecr_get_state", "ecr_set_state", "ecr_event_log", "ecr_weight", "ecr_profile", "ecr_profile_stride",
            "ecr_kernel_times", "ecr_last_error", "ecr_destroy", "ecr_selftest_philox", "ecr_selftest_divsqrt"]
 
@@ -103,6 +103,7 @@ def lib():
         sig = {
             "ecr_footprint": [C.POINTER(Params), C.POINTER(C.c_size_t)],
             "ecr_create": [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)],
+            "ecr_create_static": [C.POINTER(Params), vp, C.POINTER(vp)],
             "ecr_init_ions": [vp], "ecr_step": [vp, i64], "ecr_step_graph": [vp, i64], "ecr_step_batch": [C.POINTER(vp), i32, i64, vp],
             "ecr_read_tallies": [vp, C.POINTER(Tallies)],
             "ecr_read_density": [vp, u32, vp, C.POINTER(i64)],
@@ -209,7 +210,10 @@ def tallies_to_dict(t):
 class Run:
     """One simulation run on the GPU: arena and stream from torch, all compute in libecrpic."""
 
-    def __init__(self, params, events=False, split=False, device=None, stream=None, arena=None):
+    def __init__(self, params, events=False, split=False, device=None, stream=None, arena=None, static=False):
+        """static=True: the run lives in the library's static device
+        workspace (ecr_create_static, no device allocation); else in an arena
+        from torch (or the given one)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the ion step runs only in the HIP library")
@@ -222,11 +226,16 @@ class Run:
         _check(lib().ecr_footprint(C.byref(P), C.byref(nbytes)))
         self.nbytes = nbytes.value
         dev = torch.device(device or "cuda")
-        self.arena = arena if arena is not None else torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         h = C.c_void_p()
-        _check(lib().ecr_create(C.byref(P), C.c_void_p(self.arena.data_ptr()), self.nbytes,
-                                C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        if static:
+            self.arena = None
+            with torch.cuda.device(dev):
+                _check(lib().ecr_create_static(C.byref(P), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        else:
+            self.arena = arena if arena is not None else torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+            _check(lib().ecr_create(C.byref(P), C.c_void_p(self.arena.data_ptr()), self.nbytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         del keep
         self.h = h
 

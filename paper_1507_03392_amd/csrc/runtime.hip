@@ -13,6 +13,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -234,6 +235,10 @@ struct ecr_run {
   // HIP graph, one per SoA buffer the period starts from
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [SoA buffer][charge grid]
   int chg_par = 0;  // charge grid of the current step (ECR_FLAG_SELF_NE)
+  // a run of ecr_create_static: it lives in the library's static workspace
+  // and handle of its device; ecr_destroy releases them instead of freeing
+  bool is_static = false;
+  bool live = false;
 };
 
 namespace {
@@ -684,22 +689,26 @@ ecr_status ecr_footprint(const ecr_params *params, size_t *device_bytes) {
   return ECR_OK;
 }
 
-ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena_bytes, void *hip_stream,
-                      ecr_run **out) {
-  if (!out) return fail(nullptr, ECR_EINVAL, "out is NULL");
-  *out = nullptr;
-  const std::string v = validate(params);
-  if (!v.empty()) return fail(nullptr, params && params->abi_version != ECR_ABI_VERSION ? ECR_EABI : ECR_EINVAL, v);
-  const Layout L = make_layout(params);
-  if (!device_arena) return fail(nullptr, ECR_EINVAL, "device_arena is NULL");
-  if (arena_bytes < L.total) return fail(nullptr, ECR_ENOMEM, "arena smaller than ecr_footprint()");
-  KParams K;
-  Tables T;
-  double w;
-  derive(params, K, T, w);
-  if (max_probability(params, K, T) >= 0.1)
-    return fail(nullptr, ECR_EDT, "per-step ionisation + charge-exchange probability can reach 0.1: reduce dt_s");
-  ecr_run *r = new ecr_run();
+}  // extern "C"
+
+namespace {
+
+// release what a run holds besides its arena: events and captured graphs
+void release_run(ecr_run *r) {
+  harvest(r);
+  for (auto e : r->free_events) (void)hipEventDestroy(e);
+  r->free_events.clear();
+  for (auto &row : r->gexec)
+    for (auto &g : row) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// bind run r (fresh) to the arena at device_arena and upload its tables;
+// params were validated and the arena checked by the caller
+ecr_status init_run(ecr_run *r, const ecr_params *params, const Layout &L, const KParams &K, const Tables &T,
+                    double w, void *device_arena, void *hip_stream) {
   r->p = *params;
   r->kp = K;
   r->stream = (hipStream_t)hip_stream;
@@ -727,7 +736,6 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
   if (e != hipSuccess) {
     g_thread_err = std::string("upload failed: ") + hipGetErrorString(e);
-    delete r;
     return ECR_EDEVICE;
   }
   r->p.efield_nodes = params->efield_nodes ? (const double *)1 : nullptr;  // only its presence is kept
@@ -740,6 +748,98 @@ ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena
   r->kp.bden = needs_bden(params) ? at<double>(r, L.bden) : nullptr;
   if (r->kp.bden) launch_cell_bden(r->kp, at<double>(r, L.bden), r->stream);
   zero_accumulators(r);
+  return ECR_OK;
+}
+
+// checks shared by ecr_create and ecr_create_static: the parameters, and the
+// derived constants and tables
+ecr_status prepare(const ecr_params *params, Layout &L, KParams &K, Tables &T, double &w) {
+  const std::string v = validate(params);
+  if (!v.empty()) return fail(nullptr, params && params->abi_version != ECR_ABI_VERSION ? ECR_EABI : ECR_EINVAL, v);
+  L = make_layout(params);
+  derive(params, K, T, w);
+  if (max_probability(params, K, T) >= 0.1)
+    return fail(nullptr, ECR_EDT, "per-step ionisation + charge-exchange probability can reach 0.1: reduce dt_s");
+  return ECR_OK;
+}
+
+// The static workspace of ecr_create_static: one array per GPU the library
+// runs on (each device holds its own copy until the process ends), and one
+// run handle per device.  In host code `scratch` only names the symbol; its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticArenaBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_base[kMaxDevices];
+ecr_run g_static_run[kMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticArenaBytes];
+
+extern "C" {
+
+ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena_bytes, void *hip_stream,
+                      ecr_run **out) {
+  if (!out) return fail(nullptr, ECR_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  KParams K;
+  Tables T;
+  double w;
+  // the arena is checked before the tables, so that a missing arena is
+  // EINVAL whatever the parameters' probabilities
+  {
+    const std::string v = validate(params);
+    if (!v.empty()) return fail(nullptr, params && params->abi_version != ECR_ABI_VERSION ? ECR_EABI : ECR_EINVAL, v);
+    if (!device_arena) return fail(nullptr, ECR_EINVAL, "device_arena is NULL");
+    if (arena_bytes < make_layout(params).total) return fail(nullptr, ECR_ENOMEM, "arena smaller than ecr_footprint()");
+  }
+  const ecr_status st = prepare(params, L, K, T, w);
+  if (st != ECR_OK) return st;
+  ecr_run *r = new ecr_run();
+  const ecr_status si = init_run(r, params, L, K, T, w, device_arena, hip_stream);
+  if (si != ECR_OK) {
+    delete r;
+    return si;
+  }
+  r->live = true;
+  *out = r;
+  return ECR_OK;
+}
+
+ecr_status ecr_create_static(const ecr_params *params, void *hip_stream, ecr_run **out) {
+  if (!out) return fail(nullptr, ECR_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  KParams K;
+  Tables T;
+  double w;
+  const ecr_status st = prepare(params, L, K, T, w);
+  if (st != ECR_OK) return st;
+  if (L.total > kStaticArenaBytes)
+    return fail(nullptr, ECR_ENOMEM,
+                "run needs " + std::to_string(L.total) + " bytes of device memory; the static workspace holds " +
+                    std::to_string(kStaticArenaBytes) + " (create the run with ecr_create and an arena instead)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, ECR_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, ECR_EDEVICE, "device index beyond the static workspaces");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_base[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, ECR_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_static_base[dev] = p;
+  }
+  ecr_run *r = &g_static_run[dev];
+  if (r->live) return fail(nullptr, ECR_ESTATE, "the static workspace of this device holds a run: ecr_destroy it first");
+  *r = ecr_run();
+  r->is_static = true;
+  const ecr_status si = init_run(r, params, L, K, T, w, g_static_base[dev], hip_stream);
+  if (si != ECR_OK) return si;
+  r->live = true;
   *out = r;
   return ECR_OK;
 }
@@ -978,11 +1078,16 @@ const char *ecr_last_error(const ecr_run *r) { return r ? r->err.c_str() : g_thr
 
 ecr_status ecr_destroy(ecr_run *r) {
   if (!r) return ECR_OK;
-  harvest(r);
-  for (auto e : r->free_events) (void)hipEventDestroy(e);
-  for (auto &row : r->gexec)
-    for (auto &g : row)
-      if (g) (void)hipGraphExecDestroy(g);
+  if (r->is_static) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (r->live) {
+      (void)hipStreamSynchronize(r->stream);  // nothing may still use the workspace
+      release_run(r);
+      r->live = false;
+    }
+    return ECR_OK;
+  }
+  release_run(r);
   delete r;
   return ECR_OK;
 }
