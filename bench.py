@@ -6,12 +6,21 @@ path: sort (every 50th step), Coulomb collisions, push + wall/aperture loss +
 ionisation/charge exchange, and the density deposit.  The ions are created
 on the GPU before the timed region.
 
+Order: init; a fixed settling run (50 000 steps by default, whatever
+--warmup is) so that the timed state has ions reaching the walls and the
+aperture and atoms recycled at the gas inlet; --warmup steps; a short pass
+with HIP events around every launch that picks the dominant kernel; steps up
+to the next sort; then the timed window: --steps rounded up to whole sort
+periods, starting with a sort, bracketed by device synchronisations.
+
 Prints one JSON line: throughput in particle-steps/s, the roofline of the
 dominant kernel (algorithmic bytes per launch / its mean launch time, timed
-with HIP events on the run's stream around one in ten of its launches in the
-timed region; the kernel is picked by a short all-kernel timing pass before it),
+with HIP events on the run's stream around one in `stride` of its launches
+in the timed window, at least ten of them) and of the whole step (the fused
+step's algorithmic bytes plus the sort's share, over the mean step time),
 the HBM traffic the committed rocprofv3 counters give for that kernel, and
-the CPU oracle timed on a bounded sample of the same workload.
+the CPU oracle timed on a bounded sample of the same workload, alone on one
+core and as one copy per usable core at once.
 """
 from __future__ import annotations
 
@@ -50,6 +59,9 @@ def describe(name, p):
 # x y z vx vy vz 8 B each, qs 1 B, pid 4 B, birth step 4 B (moved by the sort
 # only), collision cell 4 B)
 ALG_BYTES_FP64 = {
+    # the fused step (Coulomb pairing and collisions, push, loss, MCC,
+    # deposit): read x, v, qs, pid and the collision cell; write x, v, qs
+    "step": 48 + 1 + 4 + 4 + 48 + 1,
     # read x, v, qs, pid; write x, v, qs
     "push": 48 + 1 + 4 + 48 + 1,
     # read qs, pid, cell; write one 12-byte work item per pair (half a particle)
@@ -67,6 +79,7 @@ ALG_BYTES_FP64 = {
     "cx_partner": 4 + 1 + 4,
 }
 ALG_BYTES_FP32 = {
+    "step": 24 + 1 + 4 + 4 + 24 + 1,
     "push": 24 + 1 + 4 + 24 + 1,
     "coul_order": 1 + 4 + 4 + 6,
     "coul_pairs": 6 + 12 + 1 + 12,
@@ -108,17 +121,74 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(params, steps):
+def oracle_sample(workload, steps):
+    """The oracle on a bounded sample of the workload: init, one step (the
+    first sort), then `steps` timed steps.  Run in a child process that
+    never touches the GPU; prints one JSON line."""
+    import workloads as W
     from oracle.binding import OracleSim
+    params, _ = W.config(workload)
     o = OracleSim(params)
     o.init_ions()
-    o.step(1)  # includes the first sort
+    o.step(1)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    return dict(value=params["n"] * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+    print(json.dumps({"seconds": dt, "steps": steps, "n": params["n"]}), flush=True)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    use = min(avail, int(cap)) if cap and cap.isdigit() and int(cap) > 0 else avail
+    return model, os.cpu_count() or avail, avail, max(1, use)
+
+
+def cpu_baseline(workload, params, steps):
+    """The oracle as it stands (single-threaded C, FP64) timed on the host:
+    one process alone (1 core), then one process per usable core, each on
+    its own copy of the same sample, all at once; the all-core figure is
+    their summed throughput (independent runs, as a scan would use the
+    cores)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-sample", workload, "--cpu-steps", str(steps)]
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+
+    def run_many(k):
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, env=env, text=True) for _ in range(k)]
+        outs = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
+        if any(p.returncode != 0 for p in procs):
+            raise RuntimeError("oracle sample failed")
+        return outs, time.perf_counter() - t0
+
+    model, ncpu, avail, use = host_cpu()
+    one, _ = run_many(1)
+    v1 = one[0]["n"] * one[0]["steps"] / one[0]["seconds"]
+    log(f"bench: oracle 1 core {v1:.3e} particle-steps/s; now {use} processes at once")
+    many, wall = run_many(use)
+    # the timed windows overlap (same work after the same set-up): summed
+    # work over the slowest window
+    slowest = max(o["seconds"] for o in many)
+    vall = sum(o["n"] * o["steps"] for o in many) / slowest
+    return dict(value=vall, unit="particle-steps/s", cores=use, kind="oracle",
                 sample=f"{params['n']} ions, {params['nx']}x{params['ny']}x{params['nz']} mesh, steps 1..{steps} "
-                       f"after init (one sort), single-threaded FP64 C oracle, {dt:.1f} s")
+                       f"after init (one sort); single-threaded FP64 C oracle, {use} independent copies at once "
+                       f"(all usable cores), slowest timed window {slowest:.1f} s",
+                value_1core=v1, seconds_1core=one[0]["seconds"], cpu_model=model, nproc=ncpu,
+                usable_cpus=avail)
 
 
 def serve_bench(args):
@@ -198,8 +268,9 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=200,
                     help="steps of the all-kernel timing pass (after warm-up) that picks the dominant kernel")
     ap.add_argument("--cpu-steps", type=int, default=20)
-    ap.add_argument("--event-stride", type=int, default=10,
-                    help="time one launch of the dominant kernel in this many with HIP events (1: every launch)")
+    ap.add_argument("--event-stride", type=int, default=0,
+                    help="time one launch of the dominant kernel in this many with HIP events (1: every launch; "
+                         "default: 10, fewer when the window has under 100 steps, for ten timed launches)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drift", action="store_true", help="FP32-mixed workloads: skip the FP64 comparison run")
     ap.add_argument("--self-ne", action="store_true",
@@ -216,7 +287,14 @@ def main():
                     help="run push and deposit as two kernels (per-kernel timing; the default fuses them)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--settle", type=int, default=None,
+                    help="steps run after init and before warm-up, fixed whatever --warmup is, so that the timed "
+                         "state has its losses and recycling going (default: 50000; c4: 20000)")
+    ap.add_argument("--oracle-sample", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_sample:
+        oracle_sample(args.oracle_sample, args.cpu_steps)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the ion step is not "
               "sharded across GPUs", file=sys.stderr)
@@ -252,8 +330,18 @@ def main():
     n = params["n"]
     fp32 = params.get("precision", 0) == ecr.FP32_MIXED
     log(f"bench: workload {args.workload}, {n} ions, grid {params['nx']}x{params['ny']}x{params['nz']}")
+    period = params["sort_every"]
+    settle = args.settle if args.settle is not None else (20_000 if args.workload == "c4" else 50_000)
     run = ecr.Run(params, split=args.split)
     run.init_ions()
+    t_s = time.perf_counter()
+    done = 0
+    while done < settle:
+        k = min(10_000, settle - done)
+        run.step_graph(k)
+        torch.cuda.synchronize()
+        done += k
+        log(f"bench: settled {done}/{settle} steps ({time.perf_counter() - t_s:.1f} s)")
     run.step(args.warmup)
     torch.cuda.synchronize()
     log(f"bench: warmup {args.warmup} steps done")
@@ -271,24 +359,39 @@ def main():
                    "share": round(tot[k] / max(1e-12, sum(tot.values())), 3)} for k in tot if per[k][1]}
     log(f"bench: kernels {json.dumps(kernels)}")
 
-    # ... which is then timed with events over the timed region itself, on
-    # one launch in --event-stride (the event packets around a launch hold
-    # up the queue, so timing every launch would slow the step it measures)
-    run.profile(True, kinds=[dom], stride=args.event_stride)
+    # the timed window starts at a sort and holds whole sort periods, so it
+    # carries its share of sorts whatever --steps is (rounded up)
+    step_now = settle + args.warmup + args.prof_steps
+    pad = (-step_now) % period
+    if pad:
+        run.step(pad)
+    steps = -(-args.steps // period) * period
+    # ... the dominant kernel is then timed with events over the timed region
+    # itself, on one launch in `stride` (the event packets around a launch
+    # hold up the queue, so timing every launch would slow the step it
+    # measures), with at least ten timed launches
+    stride = args.event_stride if args.event_stride else min(10, max(1, steps // 10))
+    run.profile(True, kinds=[dom], stride=stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run.step(args.steps)
+    run.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, launches = run.kernel_times()[dom]
     run.profile(False)
     elapsed = t1 - t0
-    value = n * args.steps / elapsed
-    log(f"bench: timed {args.steps} steps in {elapsed:.3f} s ({value:.3e} particle-steps/s)")
+    value = n * steps / elapsed
+    log(f"bench: timed {steps} steps (from step {step_now + pad}, {steps // period} sorts) in {elapsed:.3f} s "
+        f"({value:.3e} particle-steps/s)")
     tal = run.tallies()
-    alg = (ALG_BYTES_FP32 if fp32 else ALG_BYTES_FP64)[dom] * n
+    table = ALG_BYTES_FP32 if fp32 else ALG_BYTES_FP64
+    alg = table[dom] * n
     avg_s = ms * 1e-3 / max(1, launches)
     achieved = alg / avg_s / 1e9
+    # the whole step against the roofline: the fused step's bytes plus the
+    # sort's amortised over its period
+    step_bytes = (table["step"] + table["sort"] / period) * n
+    step_frac = step_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS
     # the counters were taken on the default step (fixed electron background,
     # no optional physics, fused deposit): another configuration runs other code
     default_step = not (args.self_ne or args.heat or args.split or args.self_n0 or args.cx_partner)
@@ -298,10 +401,10 @@ def main():
     if fp32 and not args.no_drift:
         # the FP32-mixed run against the same workload in FP64 on the same
         # GPU (the FP64 path matches the oracle to 1e-12), same steps from init
-        done = args.warmup + args.prof_steps + args.steps
+        done = step_now + pad + steps
         ref = ecr.Run(W.with_(params, precision=0))
         ref.init_ions()
-        ref.step(done)
+        ref.step_graph(done)
         tr = ref.tallies()
         t32 = run.tallies()
         a32, a64 = run.get_state(), ref.get_state()
@@ -324,16 +427,16 @@ def main():
     cpu = None
     if not args.no_cpu:
         log(f"bench: CPU oracle sample, {args.cpu_steps} steps of the same workload")
-        cpu = cpu_baseline(params, args.cpu_steps)
+        cpu = cpu_baseline(args.workload, params, args.cpu_steps)
 
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": elapsed / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -341,11 +444,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(args.workload, params),
                    "n_particles": n, "mesh": [params["nx"], params["ny"], params["nz"]],
-                   "sort_every": params["sort_every"]},
+                   "sort_every": period, "steps_requested": args.steps,
+                   "timed_window": [step_now + pad, step_now + pad + steps], "settle_steps": settle},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6, "timed_launches": launches,
-                     "event_stride": args.event_stride},
+                     "event_stride": stride, "step_alg_bytes": step_bytes, "step_frac": step_frac},
         "kernels": kernels,
         "tallies": {"ionized": int(tal["ionized"].sum()), "wall": int(tal["wall"].sum()),
                     "extracted": int(tal["extracted"].sum()), "cx": int(tal["cx"].sum()),
