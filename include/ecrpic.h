@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ECR_ABI_VERSION 6u
+#define ECR_ABI_VERSION 7u
 #define ECR_MAX_SPECIES 4
 #define ECR_MAX_Q 32          /* charge-state slots per species: Q = 0..31 */
 #define ECR_MAX_NION 4        /* electrons one ionisation may remove: Q -> Q+n, n = 1..4 */
@@ -92,7 +92,12 @@ enum {
 /* run flags */
 enum {
   ECR_FLAG_EVENTS = 1, /* record each particle's event code of the last step */
-  ECR_FLAG_SPLIT = 2,  /* deposit in its own kernel instead of inside the push kernel (per-kernel timing) */
+  ECR_FLAG_SPLIT = 2,  /* the step as separate kernels (Coulomb pairing order, Coulomb collisions, push + loss +
+                          MCC, deposit) instead of one kernel for the whole step, for per-kernel timing; the
+                          results are the same (the density and the FP64 sums within atomic rounding).  Runs with
+                          an electric field grid or a magnetic field map always run the separate kernels.  In
+                          this form a Coulomb chunk of more than 1024 ions skips its collisions for the step and
+                          the read calls report it (ECR_ENUMERIC); the one-kernel step has no such limit */
   ECR_FLAG_SELF_NE = 4, /* electron density = ion charge density of the particle's cell at the start of the
                           step (Sec. II: charge neutrality) instead of the fixed ne_in/ne_out background;
                           the zone still picks the rate table (warm inside, cold outside), and the
@@ -308,7 +313,8 @@ enum {
   ECR_K_FUSED = 4,      /* push + wall/aperture + ionisation/charge exchange + deposit in one kernel */
   ECR_K_COUL_PAIRS = 5, /* Coulomb scattering of the listed pairs */
   ECR_K_PARTNER = 6,    /* exchange partners (ECR_FLAG_CX_PARTNER) */
-  ECR_N_KERNELS = 7
+  ECR_K_STEP = 7,       /* the whole step in one kernel: Coulomb pairing and collisions, push, loss, MCC, deposit */
+  ECR_N_KERNELS = 8
 };
 ecr_status ecr_profile(ecr_run *run, int32_t enable);
 ecr_status ecr_kernel_times(ecr_run *run, double *ms_out, int64_t *launches_out);

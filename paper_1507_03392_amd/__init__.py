@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libecrpic.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 MAXS, MAXQ = 4, 32
 MAXN = 4  # electrons one ionisation may remove
 FPT_BINS = 32
@@ -24,8 +24,8 @@ FP64, FP32_MIXED = 0, 1
 P_PUSH, P_IONIZE, P_CX, P_COULOMB, P_DEPOSIT, P_ALL, P_HEAT, P_ELASTIC = 1, 2, 4, 8, 16, 31, 32, 64
 F_ION_N, F_ION_Q, F_ATOM_N, F_ION_P, N_FIELDS = 0, 1, 2, 3, 4
 FLAG_EVENTS, FLAG_SPLIT, FLAG_SELF_NE, FLAG_HEAT_ISOTROPIC, FLAG_SELF_N0, FLAG_CX_PARTNER = 1, 2, 4, 8, 16, 32
-K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, K_PARTNER, N_KERNELS = 0, 1, 2, 3, 4, 5, 6, 7
-KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_pairs", "cx_partner"]
+K_SORT, K_COULOMB, K_PUSH, K_DEPOSIT, K_FUSED, K_COUL_PAIRS, K_PARTNER, K_STEP, N_KERNELS = 0, 1, 2, 3, 4, 5, 6, 7, 8
+KERNEL_NAMES = ["sort", "coul_order", "push", "deposit", "push_deposit", "coul_pairs", "cx_partner", "step"]
 
 STATUS = {0: "ECR_OK", -1: "ECR_EINVAL", -2: "ECR_ENOMEM", -3: "ECR_EDEVICE", -4: "ECR_ESTATE",
           -5: "ECR_ENUMERIC", -6: "ECR_EDT", -7: "ECR_EABI"}

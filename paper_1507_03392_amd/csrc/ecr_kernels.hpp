@@ -14,6 +14,10 @@ namespace ecr {
 // (ions; atoms take no room) in LDS.
 constexpr int kCoulCap = 256;
 constexpr int kCoulMaxE = 1024;
+// the fused step kernel's chunks: the cells whose first sorted slot falls in
+// [b*kFCap, (b+1)*kFCap); a chunk of at most 1024 slots is stepped by its
+// own workgroup, a larger one by a handler workgroup
+constexpr int kFCap = 768;
 
 static_assert(kBirthNone == ECR_BIRTH_NONE, "birth sentinel");
 
@@ -71,7 +75,7 @@ void launch_deposit_pressure(const KParams &P, Soa<R> S, double *dens, hipStream
 // Coulomb chunk table: chunk b covers slots [chunk_lo[b], chunk_lo[b+1]),
 // nchunks+1 entries, rebuilt after every sort
 int64_t coul_nchunks(int64_t n);
-void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_t n, uint32_t *chunk_lo,
+void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_t n, uint32_t *chunk_lo, int64_t cap,
                         hipStream_t st);
 
 // pairing (k_coul_order) then collisions (k_coul_pairs); items holds
@@ -89,6 +93,19 @@ void launch_coul_pairs(const KParams &P, const Tables *T, Soa<R> S, const uint32
                        const uint2 *counts, double *moments, StepArg step, hipStream_t st);
 int64_t coul_moment_slots(int64_t n);
 void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hipStream_t st);
+
+// the whole step in one kernel (Coulomb pairing and collisions, push,
+// wall/aperture loss, MCC, deposit) over the chunks of the fused table
+// (chunk_lo, step_nchunks(n) + 1 entries; big: the oversized chunks, made by
+// launch_big_list at the sort); moments as for the Coulomb kernels;
+// scratch64: n 64-bit words of sort space for pools beyond the LDS.  With
+// chg_next, it must have been zeroed before.
+int64_t step_nchunks(int64_t n);
+void launch_big_list(const uint32_t *chunk_lo, int64_t n, uint32_t *big, hipStream_t st);
+template <typename R>
+void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
+                 const uint32_t *big, uint8_t *evlog, DevAccum *acc, double *dens, double *moments,
+                 uint64_t *scratch64, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, hipStream_t st);
 
 // sort by cell: keys either from positions or (given != nullptr) from given[pid]
 template <typename R>

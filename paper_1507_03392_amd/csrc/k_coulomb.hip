@@ -29,71 +29,11 @@
 //    collisions are all in flight at once.  Pairs are disjoint, so no two
 //    lanes touch one particle, and the item order does not change any
 //    particle (it only regroups the FP64 momentum and energy sums).
+#include "ecr_coll.hpp"
 #include "ecr_kernels.hpp"
+#include "ecr_wave.hpp"
 
 namespace ecr {
-
-// one binary collision of slots ia, ib with time step dtp and pool density
-// nc; acc gathers the momentum / energy change and the energy of the pool
-// before (count_e0_*: count this member's energy)
-template <typename R>
-__device__ __forceinline__ void collide(const KParams &P, const double *__restrict__ lnA, Soa<R> S, uint32_t ia,
-                                        uint32_t ib, uint32_t id_a, double nc, double dtp, uint32_t step,
-                                        double acc[5], bool count_e0_a, bool count_e0_b) {
-  const uint4 W = draw(P, id_a, step, S_COUL, 0);
-  const double u = u53(W.x, W.y), u2 = u53(W.z, W.w);
-  const R vax = S.vx[ia], vay = S.vy[ia], vaz = S.vz[ia];
-  const R vbx = S.vx[ib], vby = S.vy[ib], vbz = S.vz[ib];
-  const uint8_t qa = S.qs[ia], qb = S.qs[ib];
-  const int sa = sp_of(qa), sb = sp_of(qb);
-  const double ma = P.mass[sa], mb = P.mass[sb];
-  const double ea = 0.5 * ma * (double)((vax * vax + vay * vay) + vaz * vaz);
-  const double eb = 0.5 * mb * (double)((vbx * vbx + vby * vby) + vbz * vbz);
-  if (count_e0_a) acc[4] += ea;
-  if (count_e0_b) acc[4] += eb;
-  const R ux = vax - vbx, uy = vay - vby, uz = vaz - vbz;
-  const R g2 = (ux * ux + uy * uy) + uz * uz;
-  if (g2 == (R)0) return;
-  const R g = sqrt(g2);
-  const double mu = P.mu[sa][sb];  // (ma mb) / (ma + mb), tabulated on the host
-  const double qq = (double)q_of(qa) * (double)q_of(qb);
-  const double num = ((P.Cs * (qq * qq)) * nc) * dtp;
-  const double den = (mu * mu) * ((double)g2 * (double)g);
-  const double sv = num / den;
-  const R omc = (R)nanbu_omc(lnA, sv, u);
-  const R sinchi = sqrt(omc * ((R)2 - omc));
-  R sp, cp;
-  sincospi_r((R)(2.0 * u2), &sp, &cp);  // phi = 2 pi u2
-  const R ca = sinchi * cp, cb = sinchi * sp;
-  const R uperp = sqrt(ux * ux + uy * uy);
-  R dux, duy, duz;
-  if (uperp > (R)0) {
-    const R iu = (R)1 / uperp;
-    const R cx = ux * iu, cy = uy * iu;  // within an ulp of ux/uperp, uy/uperp
-    dux = ((cx * uz) * ca - (cy * g) * cb) - ux * omc;
-    duy = ((cy * uz) * ca + (cx * g) * cb) - uy * omc;
-    duz = -(uperp * ca) - uz * omc;
-  } else {
-    dux = g * ca;
-    duy = g * cb;
-    duz = -(g * omc);
-  }
-  const R ra = (R)P.mra[sa][sb], rb = (R)P.mrb[sa][sb];  // mu / ma, mu / mb
-  const R nax = vax + ra * dux, nay = vay + ra * duy, naz = vaz + ra * duz;
-  const R nbx = vbx - rb * dux, nby = vby - rb * duy, nbz = vbz - rb * duz;
-  S.vx[ia] = nax;
-  S.vy[ia] = nay;
-  S.vz[ia] = naz;
-  S.vx[ib] = nbx;
-  S.vy[ib] = nby;
-  S.vz[ib] = nbz;
-  acc[0] += ma * (double)(nax - vax) + mb * (double)(nbx - vbx);
-  acc[1] += ma * (double)(nay - vay) + mb * (double)(nby - vby);
-  acc[2] += ma * (double)(naz - vaz) + mb * (double)(nbz - vbz);
-  const double ea1 = 0.5 * ma * (double)((nax * nax + nay * nay) + naz * naz);
-  const double eb1 = 0.5 * mb * (double)((nbx * nbx + nby * nby) + nbz * nbz);
-  acc[3] += (ea1 - ea) + (eb1 - eb);
-}
 
 // moment slots of a chunk: one per pair wavefront, one for triplets
 constexpr int kMomentSlotsPerChunk = kCoulItems / 64 + 1;
@@ -117,78 +57,14 @@ struct CoulShared {
   uint32_t grp[2][kEPT * (kCB / 64)];  // step 1's member counts per pass and wave, by group parity
 };
 
-// Inclusive sums over a wavefront with DPP lane moves, no LDS: row_shr 1,
-// 2, 4, 8 within each row of 16 lanes, then row_bcast 15 (the last lane of
-// rows 0 and 2 into rows 1 and 3) and row_bcast 31 (lane 31 into rows 2
-// and 3); a missing source adds zero.  Called by all 64 lanes; lane 63 ends
-// with the wavefront's total.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  x += dpp_u32<0x111, 0xf>(x);
-  x += dpp_u32<0x112, 0xf>(x);
-  x += dpp_u32<0x114, 0xf>(x);
-  x += dpp_u32<0x118, 0xf>(x);
-  x += dpp_u32<0x142, 0xa>(x);
-  x += dpp_u32<0x143, 0xc>(x);
-  return x;
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = dpp_u32<CTRL, ROWS>((uint32_t)u), hi = dpp_u32<CTRL, ROWS>((uint32_t)(u >> 32));
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// the wavefront's total, in lane 63
-__device__ __forceinline__ double wave_sum_last(double x) {
-  x += dpp_f64<0x111, 0xf>(x);
-  x += dpp_f64<0x112, 0xf>(x);
-  x += dpp_f64<0x114, 0xf>(x);
-  x += dpp_f64<0x118, 0xf>(x);
-  x += dpp_f64<0x142, 0xa>(x);
-  x += dpp_f64<0x143, 0xc>(x);
-  return x;
-}
-
-// in-place exclusive scan of a[0..L) by the workgroup; returns the total
-__device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum) {
-  const int tid = threadIdx.x;
-  const int per = (L + kCB - 1) / kCB;
-  const int b = tid * per, e = min(b + per, L);
-  uint32_t s = 0;
-  for (int i = b; i < e; ++i) s += a[i];
-  const int lane = tid & 63, w = tid >> 6;
-  const uint32_t x = wave_incl_scan(s);
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  uint32_t woff = 0, tot = 0;
-  for (int q = 0; q < kCB / 64; ++q) {
-    if (q < w) woff += wsum[q];
-    tot += wsum[q];
-  }
-  uint32_t run = woff + x - s;
-  for (int i = b; i < e; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
-  __syncthreads();
-  return tot;
-}
-
 // slot range of every chunk: the first slot of the first cell starting at or
-// after b*kCoulCap (the cell holding that slot if it starts there, else the
-// next one)
+// after b*cap (the cell holding that slot if it starts there, else the next
+// one)
 __global__ void k_coul_chunks(const uint32_t *__restrict__ cellid, const uint32_t *__restrict__ cell_off, int64_t n,
-                              int64_t nchunks, uint32_t *__restrict__ chunk_lo) {
+                              int64_t nchunks, int64_t cap, uint32_t *__restrict__ chunk_lo) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nchunks) return;
-  const int64_t t = b * kCoulCap;
+  const int64_t t = b * cap;
   if (t >= n) {
     chunk_lo[b] = (uint32_t)n;
     return;
@@ -344,7 +220,7 @@ __device__ __forceinline__ void order_chunk(const KParams &P, Soa<R> S, const ui
     sh.r1[h] = 1u << lg;
   }
   __syncthreads();
-  const int nbuckets = (int)wg_exscan(sh.r1, nheads, sh.wsum);
+  const int nbuckets = (int)wg_exscan<kCB>(sh.r1, nheads, sh.wsum);
   for (int h = tid; h < nheads; h += kCB) hbase[h] = (uint16_t)sh.r1[h];
   if (tid == 0) hbase[nheads] = (uint16_t)nbuckets;
   __syncthreads();
@@ -367,7 +243,7 @@ __device__ __forceinline__ void order_chunk(const KParams &P, Soa<R> S, const ui
   }
   __syncthreads();
   // 6-7. bucket offsets, members listed bucket by bucket
-  const int npool = (int)wg_exscan(hist, nbuckets, sh.wsum);
+  const int npool = (int)wg_exscan<kCB>(hist, nbuckets, sh.wsum);
   if (tid == 0) hist[nbuckets] = (uint32_t)npool;
   __syncthreads();
 #pragma unroll
@@ -631,11 +507,11 @@ void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hi
 
 int64_t coul_nchunks(int64_t n) { return (n + kCoulCap - 1) / kCoulCap; }
 
-void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_t n, uint32_t *chunk_lo,
+void launch_coul_chunks(const uint32_t *cellid, const uint32_t *cell_off, int64_t n, uint32_t *chunk_lo, int64_t cap,
                         hipStream_t st) {
-  const int64_t nc = coul_nchunks(n);
+  const int64_t nc = (n + cap - 1) / cap;
   hipLaunchKernelGGL(k_coul_chunks, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, cellid, cell_off, n, nc,
-                     chunk_lo);
+                     cap, chunk_lo);
 }
 
 template <typename R>

@@ -11,13 +11,10 @@
 #include <type_traits>
 
 #include "ecr_kernels.hpp"
+#include "ecr_push.hpp"
 
 namespace ecr {
 
-constexpr int kP = 4;                // consecutive slots per lane
-constexpr int kBlock = 256;          // lanes per workgroup
-constexpr int kTile = kBlock * kP;   // slots per workgroup
-constexpr int kBrickNodes = 1536;    // LDS brick capacity in nodes (x 3 fields)
 
 // ---------------------------------------------------------------------------
 // Initial ions: uniform in the ECR-zone ellipsoid by rejection sampling in
@@ -66,635 +63,8 @@ __global__ void __launch_bounds__(256) k_init(KParams P, Soa<R> S) {
 }
 
 // ---------------------------------------------------------------------------
-// Electron-ion heating and diffusion (Sec. II): dV = D (R + delta) |R| /
-// |R + delta| with D^2 = n_e x dheat[s][zone][Q] and R uniform in the cube
-// [-1/2, 1/2]^3 (three words of one draw of the heating stream).  With the
-// cell charge grid (self-consistent electrons) n_e is the ion's cell's and
-// delta the electron diamagnetic bias: the 9-point stencil of the cell
-// density in the ion's z plane (cells beyond the mesh count as empty) times
-// -R_L / n_e(cell), R_L = 2.38e-6 sqrt(T_e) / (|B(cell centre)| hx); a cell
-// without charge gives no kick.  With the fixed background, n_e is the
-// zone's and, the background being uniform, delta = 0; ECR_FLAG_HEAT_ISOTROPIC
-// also sets delta = 0 (the isotropic-heating ablation).  The kick is
-// evaluated in binary64 whatever R; the neighbours' loads hit the cache
-// lines the lanes of a cell share (slots are in cell order).
-// ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void heat_kick(const KParams &P, const Tables *__restrict__ T, uint32_t id, uint32_t step,
-                                          int s, int Q, R x, R y, R z, R &vx, R &vy, R &vz,
-                                          const uint32_t *__restrict__ chg) {
-  const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
-  double ne, dlx = 0.0, dly = 0.0;
-  if (P.flags & ECR_FLAG_SELF_NE) {
-    const int ix = clampi((int)floor((x + (R)P.R0) * (R)P.idx), 0, P.nx - 1);
-    const int iy = clampi((int)floor((y + (R)P.R0) * (R)P.idy), 0, P.ny - 1);
-    const int iz = clampi((int)floor((z + (R)P.hL) * (R)P.idz), 0, P.nz - 1);
-    const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny * (uint32_t)iz;
-    auto nat = [&](int jx, int jy) -> double {
-      if (jx < 0 || jx >= P.nx || jy < 0 || jy >= P.ny) return 0.0;
-      return P.nfac * (double)chg[plane + (uint32_t)jx + (uint32_t)P.nx * (uint32_t)jy];
-    };
-    ne = nat(ix, iy);
-    if (!(ne > 0.0)) return;
-    // |B| at the cell centre times the cell size, tabulated per cell when
-    // the run is created (cell_bden)
-    const double den = P.bden[plane + (uint32_t)ix + (uint32_t)P.nx * (uint32_t)iy];
-    if (den > 0.0 && !(P.flags & ECR_FLAG_HEAT_ISOTROPIC)) {
-      const double rl = P.rl_zone[zone] / den;
-      const double nmm = nat(ix - 1, iy - 1), nzm = nat(ix, iy - 1), npm = nat(ix + 1, iy - 1);
-      const double nmz = nat(ix - 1, iy), npz = nat(ix + 1, iy);
-      const double nmp = nat(ix - 1, iy + 1), nzp = nat(ix, iy + 1), npp = nat(ix + 1, iy + 1);
-      const double gy = (-nzp + nzm) + 0.5 * (((-nmp - npp) + npm) + nmm);
-      const double gx = (-nmz + npz) + 0.5 * (((-nmp + npp) + npm) - nmm);
-      dlx = -(rl / ne) * gy;
-      dly = -(rl / ne) * gx;
-    }
-  } else {
-    ne = P.ne_zone[zone];
-    if (!(ne > 0.0)) return;
-  }
-  const double D = sqrt(ne * T->dheat[s][zone][Q]);
-  const uint4 W = draw(P, id, step, S_HEAT, 0);
-  constexpr double k2m32 = 2.3283064365386962890625e-10;  // 2^-32
-  const double rx = ((double)W.x + 0.5) * k2m32 - 0.5;
-  const double ry = ((double)W.y + 0.5) * k2m32 - 0.5;
-  const double rz = ((double)W.z + 0.5) * k2m32 - 0.5;
-  const double sx = rx + dlx, sy = ry + dly, sz = rz;
-  const double nr = sqrt((rx * rx + ry * ry) + rz * rz);
-  const double ns = sqrt((sx * sx + sy * sy) + sz * sz);
-  if (!(ns > 0.0)) return;
-  const double f = (D * nr) / ns;
-  vx = (R)((double)vx + f * sx);
-  vy = (R)((double)vy + f * sy);
-  vz = (R)((double)vz + f * sz);
-}
-
-// ---------------------------------------------------------------------------
-// One particle: push -> wall/aperture -> heating kick -> ionisation (Q -> Q+n)
-// / charge exchange / elastic ion-atom scattering.
-// Tallies are rare events (~1e-4 per particle-step) and go straight to
-// 64-bit global atomics; so do the loss diagnostics (first-passage times,
-// crossing radius, lost kinetic energy), and the particle's birth step
-// (birth[j]) is read or written only on such events.  Returns the event code.
-// ---------------------------------------------------------------------------
-// EXT: the kernel variant with the optional physics (self-consistent
-// electrons, heating kick, multiple ionisation, elastic scattering); the
-// default step runs the lean variant, which leaves those paths out of the
-// code altogether
-template <typename R, int FLD, bool EXT>
-__device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
-                                           const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
-                                           uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz,
-                                           uint32_t *__restrict__ birth, int64_t j,
-                                           const uint32_t *__restrict__ chg) {
-  uint8_t ev = EV_NONE;
-  if (P.pmask & P_PUSH) {
-    const R x0 = x, y0 = y, z0 = z;
-    const R h = (R)T->qmh[s][Q];
-    R E[3] = {(R)0, (R)0, (R)0};
-    if (FLD & 1) gather_E<R>(P, ef, x, y, z, E);
-    boris<R, FLD>(P, h, E, x, y, z, vx, vy, vz);
-    R f;
-    const int kind = segment_exit<R>(P, x0, y0, z0, x, y, z, f);
-    if (kind != X_NONE) {
-      if (Q >= 1) {
-        const double ke = 0.5 * P.mass[s] * (double)((vx * vx + vy * vy) + vz * vz);
-        unsafeAtomicAdd(&acc->t.lost_ke[s], ke);
-      }
-      R rc2 = (R)0;
-      ev = wall_event<R>(P, id, step, s, kind, f, x0, y0, z0, x, y, z, vx, vy, vz, rc2);
-      if (ev == EV_EXTRACT) {
-        atomicAdd((unsigned long long *)&acc->t.extracted[s][Q], 1ull);
-        atomicAdd((unsigned long long *)&acc->t.recycled, 1ull);
-        unsafeAtomicAdd(&acc->t.extracted_r[s][Q], (double)sqrt(rc2));
-        const uint32_t b = birth[j];
-        if (Q >= 1 && b != kBirthNone) {
-          const uint32_t t = step - b;
-          atomicAdd((unsigned long long *)&acc->t.fpt_n[s][Q], 1ull);
-          atomicAdd((unsigned long long *)&acc->t.fpt_sum[s][Q], (unsigned long long)t);
-          atomicAdd((unsigned long long *)&acc->t.fpt_hist[s][fpt_bin(t)], 1ull);
-        }
-      } else {
-        atomicAdd((unsigned long long *)&acc->t.wall[s][Q], 1ull);
-      }
-      // now an atom; with exchange partners an atom's birth is the step it
-      // became one, so that it is no partner in this step
-      if (EXT && (P.flags & ECR_FLAG_CX_PARTNER)) birth[j] = step;
-      else if (Q >= 1) birth[j] = kBirthNone;
-      Q = 0;
-    }
-  }
-  if (EXT && ev == EV_NONE && (P.pmask & P_HEAT) && Q >= 1)
-    heat_kick<R>(P, T, id, step, s, Q, x, y, z, vx, vy, vz, chg);
-  if (!EXT && ev == EV_NONE && (P.pmask & (P_IONIZE | P_CX))) {
-    const uint4 W = draw(P, id, step, S_STEP, 0);
-    const double u = u53(W.x, W.y);
-    const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
-    // single ionisation with the fixed background, then charge exchange
-    const double pi = (P.pmask & P_IONIZE) ? T->pion[s][zone][Q] : 0.0;
-    double pc = 0.0;
-    if ((P.pmask & P_CX) && ((P.cxok[s] >> Q) & 1u)) {
-      const R sp2 = (vx * vx + vy * vy) + vz * vz;
-      pc = (P.ccx[s] * (double)Q) * (double)sqrt(sp2);
-    }
-    const double pt = pi + pc;
-    if (pt > 0.1) atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
-    if (u < pi) {
-      atomicAdd((unsigned long long *)&acc->t.ionized[s][Q], 1ull);
-      atomicAdd((unsigned long long *)&acc->t.ionized_n[s][0], 1ull);
-      if (Q == 0) birth[j] = step;  // an ion is made from an atom
-      Q = Q + 1;
-      ev = EV_IONIZE;
-    } else if (u < pt) {
-      atomicAdd((unsigned long long *)&acc->t.cx[s][Q], 1ull);
-      if (Q == 1) birth[j] = step;  // resonant exchange: the ion is the former neutral
-      cx_outcome<R>(P, id, step, s, Q, vx, vy, vz);
-      if (Q >= 2) {
-        Q = Q - 1;
-        atomicAdd((unsigned long long *)&acc->t.cx_products[s], 1ull);
-      }
-      ev = EV_CX;
-    }
-  }
-  if (EXT && ev == EV_NONE && (P.pmask & (P_IONIZE | P_CX | P_ELASTIC))) {
-    const uint4 W = draw(P, id, step, S_STEP, 0);
-    const double u = u53(W.x, W.y);
-    const int zone = (((x * x) * (R)P.ia2 + (y * y) * (R)P.ia2) + (z * z) * (R)P.ic2) < (R)1;
-    // ionisation channels Q -> Q+n: the fixed background's tabulated
-    // probabilities, or with ECR_FLAG_SELF_NE n_e k dt, n_e = weight x (ion
-    // charge of the cell at the start of the step) / cell volume.  One
-    // uniform picks the channel by running sums: ionisation n = 1..4, then
-    // charge exchange, then elastic scattering.
-    const bool self_ne = (P.flags & ECR_FLAG_SELF_NE) != 0;
-    double pi = 0.0, ne = 0.0;
-    if (P.pmask & P_IONIZE) {
-      if (self_ne) {
-        ne = P.nfac * (double)chg[cell_of<R>(P, x, y, z)];
-        pi = ne * T->kdt[s][zone][Q];
-      } else {
-        pi = T->pion[s][zone][Q];
-      }
-    }
-    double c2 = pi, c3 = pi, c4 = pi;  // running sums through n = 2, 3, 4
-    if ((P.pmask & P_IONIZE) && P.nion > 1) {
-      const double p2 = self_ne ? ne * T->kmul[s][zone][0][Q] : T->pmul[s][zone][0][Q];
-      const double p3 = self_ne ? ne * T->kmul[s][zone][1][Q] : T->pmul[s][zone][1][Q];
-      const double p4 = self_ne ? ne * T->kmul[s][zone][2][Q] : T->pmul[s][zone][2][Q];
-      c2 = pi + p2;
-      c3 = c2 + p3;
-      c4 = c3 + p4;
-    }
-    const bool cxon = (P.pmask & P_CX) && ((P.cxok[s] >> Q) & 1u);
-    const bool elon = (P.pmask & P_ELASTIC) != 0;
-    double speed = 0.0;
-    if (cxon || elon) {
-      const R sp2 = (vx * vx + vy * vy) + vz * vz;
-      speed = (double)sqrt(sp2);
-    }
-    // neutral partners: the species' uniform n0, or with ECR_FLAG_SELF_N0
-    // weight x (atoms of the species in the cell at the start of the step) / cell volume
-    double ccx = P.ccx[s], cel = P.cel[s];
-    if ((P.flags & ECR_FLAG_SELF_N0) && (cxon || elon)) {
-      const double n0c = P.nfac * (double)chg[(uint32_t)(1 + s) * P.ncell + cell_of<R>(P, x, y, z)];
-      ccx = n0c * P.sdt_cx[s];
-      cel = n0c * P.sdt_el[s];
-    }
-    double pc = 0.0;
-    if (cxon) pc = (ccx * (double)Q) * speed;
-    const double pt = c4 + pc;
-    const double pall = elon ? pt + (cel * (double)Q) * speed : pt;
-    if (pall > 0.1) atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
-    if (u < c4) {
-      const int n = u < pi ? 1 : (u < c2 ? 2 : (u < c3 ? 3 : 4));
-      atomicAdd((unsigned long long *)&acc->t.ionized[s][Q], 1ull);
-      atomicAdd((unsigned long long *)&acc->t.ionized_n[s][n - 1], 1ull);
-      if (Q == 0) birth[j] = step;  // an ion is made from an atom
-      Q = Q + n;
-      ev = EV_IONIZE;
-    } else if (u < pt) {
-      atomicAdd((unsigned long long *)&acc->t.cx[s][Q], 1ull);
-      ev = EV_CX;
-      if (P.flags & ECR_FLAG_CX_PARTNER) {
-        // the electron comes from a tracked atom of the collision cell,
-        // picked at the end of the step; a Q = 1 ion is an atom from now
-        // on and keeps its velocity
-        const uint32_t cc = P.cellid[j];
-        atomicAdd(&P.cxreq[(uint32_t)s * P.ncell + cc], 1u);
-        // the chunk owning the cell: the one its first slot falls in
-        P.cxchunk[P.cell_off[cc] / (uint32_t)kCoulCap] = 1u;
-        if (Q == 1) {
-          birth[j] = step;
-          Q = 0;
-        }
-      }
-      if (Q >= 1) {
-        if (Q == 1) birth[j] = step;  // resonant exchange: the ion is the former neutral
-        cx_outcome<R>(P, id, step, s, Q, vx, vy, vz);
-        if (Q >= 2) {
-          Q = Q - 1;
-          atomicAdd((unsigned long long *)&acc->t.cx_products[s], 1ull);
-        }
-      }
-    } else if (u < pall) {
-      atomicAdd((unsigned long long *)&acc->t.elastic[s][Q], 1ull);
-      elastic_outcome<R>(P, id, step, s, vx, vy, vz);
-      ev = EV_ELASTIC;
-    }
-  }
-  if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) && isfinite(vz)))
-    atomicAdd((unsigned long long *)&acc->t.anomalies, 1ull);
-  return ev;
-}
-
-// ---------------------------------------------------------------------------
-// Cloud-in-cell deposit of a tile onto the (nx+1)(ny+1)(nz+1) node grid:
-// fields ion number (Q >= 1), ion charge (Q x weight) and atom number
-// (Q = 0), as enabled by the deposit mask.
-//
-// The push works on coalesced slots (lane = slot, kP rounds of 256).  Its
-// deposit inputs (lower node, fractional offsets, charge) are staged in LDS
-// and read back transposed, so that lane l owns the kP consecutive slots
-// kP*l .. kP*l+kP-1.  Consecutive slots share a cell almost always, so the
-// lane sums their weights in registers and flushes a run only when the cell
-// changes, into an LDS brick spanning the tile's nodes.  The lanes' last runs
-// go through a segmented sum over the wavefront, so only the last lane of
-// each run of equal cells touches the brick; the brick goes to HBM with one
-// FP64 atomic per touched node.  A tile whose nodes do not fit the brick
-// (one spanning two planes of cells) sends the same wavefront sums to HBM.
-// ---------------------------------------------------------------------------
-constexpr int kPad(int i) { return i + (i >> 2); }  // one pad slot every 4: fewer LDS bank conflicts
-constexpr int kStage = kPad(kTile);
-
-// unpadded: the push writes one slot per lane (consecutive addresses), and
-// lane l reads its kP consecutive slots back with wide loads, both free of
-// bank conflicts; 31 KB in binary64, so that five workgroups share a CU
-template <typename R>
-struct alignas(16) DepStage {
-  R t[3][kTile];
-  uint16_t c[3][kTile];
-  uint8_t q[kTile];  // charge, or 0xFF: nothing to deposit
-};
-
-// the brick reuses the staging memory: as many doubles as binary64 staging holds
-constexpr int kDepBrick = (int)(sizeof(DepStage<double>) / sizeof(double));
-
-template <typename R>
-union DepShared {
-  DepStage<R> st;
-  double brick[kDepBrick];
-};
-
-// kP consecutive staged values of lane l (16-byte aligned: kP = 4)
-__device__ __forceinline__ void lds_load4(const double *p, double o[4]) {
-  const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
-  o[0] = a.x;
-  o[1] = a.y;
-  o[2] = b.x;
-  o[3] = b.y;
-}
-__device__ __forceinline__ void lds_load4(const float *p, float o[4]) {
-  const float4 a = *reinterpret_cast<const float4 *>(p);
-  o[0] = a.x;
-  o[1] = a.y;
-  o[2] = a.z;
-  o[3] = a.w;
-}
-
-template <typename R>
-struct DepIn {
-  int ix[kP], iy[kP], iz[kP], q[kP];
-  R tx[kP], ty[kP], tz[kP];
-  bool on[kP];
-};
-
-// sum the runs of equal base node held by this lane; flush(node, field, corner, value)
-// the last run of a lane, handed to the wavefront reduction (node -1: none)
-struct DepRun {
-  int64_t node;
-  double a[8], b[8], c[8];
-};
-
-// CARRY: the lane's last run is returned in `last` instead of flushed
-template <typename R, bool CARRY, typename NodeOf, typename Flush>
-__device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, NodeOf nodeof, Flush flush,
-                                               DepRun &last) {
-  double a[8], b[8], c[8];
-  int64_t cur = -1;
-  bool has_ion = false, has_atom = false;
-  for (int k = 0; k < 8; ++k) a[k] = b[k] = c[k] = 0.0;
-  auto emit = [&]() {
-    if (cur < 0) return;
-    for (int k = 0; k < 8; ++k) {
-      if (has_ion && (dm & 1u)) flush(cur, 0, k, a[k]);
-      if (has_ion && (dm & 2u)) flush(cur, 1, k, b[k]);
-      if (has_atom && (dm & 4u)) flush(cur, 2, k, c[k]);
-    }
-  };
-#pragma unroll
-  for (int p = 0; p < kP; ++p) {
-    if (!D.on[p]) continue;
-    const int64_t node = nodeof(D.ix[p], D.iy[p], D.iz[p]);
-    if (node != cur) {
-      emit();
-      cur = node;
-      has_ion = has_atom = false;
-      for (int k = 0; k < 8; ++k) a[k] = b[k] = c[k] = 0.0;
-    }
-    const R wx[2] = {(R)1 - D.tx[p], D.tx[p]}, wy[2] = {(R)1 - D.ty[p], D.ty[p]};
-    const R wz[2] = {(R)1 - D.tz[p], D.tz[p]};
-    const bool ion = D.q[p] >= 1;
-    const double qd = (double)D.q[p];
-    int k = 0;
-    for (int dz = 0; dz < 2; ++dz)
-      for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx, ++k) {
-          const double w = (double)((wx[dx] * wy[dy]) * wz[dz]);
-          if (ion) {
-            a[k] += w;
-            b[k] += qd * w;
-          } else {
-            c[k] += w;
-          }
-        }
-    has_ion |= ion;
-    has_atom |= !ion;
-  }
-  if (CARRY) {
-    last.node = cur;
-    for (int k = 0; k < 8; ++k) {
-      last.a[k] = a[k];
-      last.b[k] = b[k];
-      last.c[k] = c[k];
-    }
-  } else {
-    emit();
-  }
-}
-
-// Segmented sums over the lanes of a wavefront: lanes are in slot order, so
-// equal run nodes form contiguous lane segments (a lane's earlier runs were
-// flushed already).  Segmented inclusive sums over a wavefront with DPP lane moves, no LDS:
-// row_shr 1, 2, 4, 8 within each row of 16 lanes, then row_bcast 15 (the
-// last lane of rows 0 and 2 into rows 1 and 3) and row_bcast 31 (lane 31
-// into rows 2 and 3).  seg is a run id, equal exactly on runs of
-// consecutive lanes; a step adds the source lane's partial sum when the
-// source exists and lies in the same run, so after the six steps the last
-// lane of every run holds the run's total.  Called by all 64 lanes.
-struct SegSteps {
-  bool t[6];  // step i takes its source lane's partial sum
-};
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_move(int old, int v) {
-  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);  // disabled or missing source: old
-}
-
-__device__ __forceinline__ SegSteps seg_steps(int seg) {
-  SegSteps s;  // seg >= 0, so the -1 of a missing source never matches
-  s.t[0] = dpp_move<0x111, 0xf>(-1, seg) == seg;  // row_shr:1
-  s.t[1] = dpp_move<0x112, 0xf>(-1, seg) == seg;  // row_shr:2
-  s.t[2] = dpp_move<0x114, 0xf>(-1, seg) == seg;  // row_shr:4
-  s.t[3] = dpp_move<0x118, 0xf>(-1, seg) == seg;  // row_shr:8
-  s.t[4] = dpp_move<0x142, 0xa>(-1, seg) == seg;  // row_bcast:15 into rows 1, 3
-  s.t[5] = dpp_move<0x143, 0xc>(-1, seg) == seg;  // row_bcast:31 into rows 2, 3
-  return s;
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move_d(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)dpp_move<CTRL, ROWS>(0, (int)(uint32_t)u);
-  const uint32_t hi = (uint32_t)dpp_move<CTRL, ROWS>(0, (int)(uint32_t)(u >> 32));
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-__device__ __forceinline__ double seg_scan(const SegSteps &s, double x) {
-  double o;
-  o = dpp_move_d<0x111, 0xf>(x);
-  x = s.t[0] ? x + o : x;
-  o = dpp_move_d<0x112, 0xf>(x);
-  x = s.t[1] ? x + o : x;
-  o = dpp_move_d<0x114, 0xf>(x);
-  x = s.t[2] ? x + o : x;
-  o = dpp_move_d<0x118, 0xf>(x);
-  x = s.t[3] ? x + o : x;
-  o = dpp_move_d<0x142, 0xa>(x);
-  x = s.t[4] ? x + o : x;
-  o = dpp_move_d<0x143, 0xc>(x);
-  x = s.t[5] ? x + o : x;
-  return x;
-}
-
-// (the moves run on every lane before the select: a move under a lane
-// condition would read the lanes the condition turns off as missing)
-__device__ __forceinline__ uint32_t seg_scan(const SegSteps &s, uint32_t x) {
-  uint32_t o;
-  o = (uint32_t)dpp_move<0x111, 0xf>(0, (int)x);
-  x += s.t[0] ? o : 0u;
-  o = (uint32_t)dpp_move<0x112, 0xf>(0, (int)x);
-  x += s.t[1] ? o : 0u;
-  o = (uint32_t)dpp_move<0x114, 0xf>(0, (int)x);
-  x += s.t[2] ? o : 0u;
-  o = (uint32_t)dpp_move<0x118, 0xf>(0, (int)x);
-  x += s.t[3] ? o : 0u;
-  o = (uint32_t)dpp_move<0x142, 0xa>(0, (int)x);
-  x += s.t[4] ? o : 0u;
-  o = (uint32_t)dpp_move<0x143, 0xc>(0, (int)x);
-  x += s.t[5] ? o : 0u;
-  return x;
-}
-
-// the wavefront's cell-index bounding box (minima and maxima of three
-// indices) by the same DPP moves, in lane 63; called by all 64 lanes
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void box_step(int mn[3], int mx[3]) {
-  for (int d = 0; d < 3; ++d) {
-    const int a = dpp_move<CTRL, ROWS>(0x7fffffff, mn[d]), b = dpp_move<CTRL, ROWS>(-0x7fffffff - 1, mx[d]);
-    mn[d] = min(mn[d], a);
-    mx[d] = max(mx[d], b);
-  }
-}
-
-__device__ __forceinline__ void wave_box_last(int mn[3], int mx[3]) {
-  box_step<0x111, 0xf>(mn, mx);
-  box_step<0x112, 0xf>(mn, mx);
-  box_step<0x114, 0xf>(mn, mx);
-  box_step<0x118, 0xf>(mn, mx);
-  box_step<0x142, 0xa>(mn, mx);
-  box_step<0x143, 0xc>(mn, mx);
-}
-
-// runs of equal keys over the wavefront: run ids, and whether this lane ends its run
-__device__ __forceinline__ void wave_runs(int64_t key, int &seg, bool &tail) {
-  const int lane = threadIdx.x & 63;
-  // the previous lane's key by wave_shr:1 (lane 0 has none and heads a run)
-  const uint32_t plo = (uint32_t)dpp_move<0x138, 0xf>(0, (int)(uint32_t)(uint64_t)key);
-  const uint32_t phi = (uint32_t)dpp_move<0x138, 0xf>(0, (int)(uint32_t)((uint64_t)key >> 32));
-  const int64_t kprev = (int64_t)(((uint64_t)phi << 32) | plo);
-  const uint64_t heads = __ballot(lane == 0 || kprev != key);
-  seg = __popcll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
-  tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
-}
-
-// stage the deposit input of tile slot i (lane = slot layout)
-// NQ: the deposit mask is known to hold exactly the ion number and ion
-// charge fields (the default); the atom-field paths then compile away
-template <typename R, bool NQ>
-__device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int i, R x, R y, R z, int q, int mn[3],
-                                          int mx[3]) {
-  int ix, iy, iz;
-  R tx, ty, tz;
-  cic_axis<R>(x, (R)P.R0, (R)P.idx, P.nx, ix, tx);
-  cic_axis<R>(y, (R)P.R0, (R)P.idy, P.ny, iy, ty);
-  cic_axis<R>(z, (R)P.hL, (R)P.idz, P.nz, iz, tz);
-  const uint32_t dm = NQ ? 3u : P.dmask;
-  const bool on = (q >= 1) ? (dm & 3u) != 0 : (dm & 4u) != 0;
-  const int k = i;
-  st.t[0][k] = tx;
-  st.t[1][k] = ty;
-  st.t[2][k] = tz;
-  st.c[0][k] = (uint16_t)ix;
-  st.c[1][k] = (uint16_t)iy;
-  st.c[2][k] = (uint16_t)iz;
-  st.q[k] = on ? (uint8_t)q : (uint8_t)0xFF;
-  if (on) {
-    mn[0] = min(mn[0], ix);
-    mn[1] = min(mn[1], iy);
-    mn[2] = min(mn[2], iz);
-    mx[0] = max(mx[0], ix);
-    mx[1] = max(mx[1], iy);
-    mx[2] = max(mx[2], iz);
-  }
-}
-
-// deposit a staged tile; every lane of the workgroup must call it
-template <typename R, bool NQ>
-__device__ __forceinline__ void deposit_staged(const KParams &P, double *__restrict__ dens, DepShared<R> &sh,
-                                               int *box, int mn[3], int mx[3]) {
-  const int tid = threadIdx.x;
-  const uint32_t dm = NQ ? 3u : P.dmask;
-  constexpr int kFields = NQ ? 2 : 3;  // brick fields
-  wave_box_last(mn, mx);
-  if ((tid & 63) == 63)
-    for (int d = 0; d < 3; ++d) {
-      atomicMin(&box[d], mn[d]);
-      atomicMax(&box[3 + d], mx[d]);
-    }
-  __syncthreads();  // staging and box complete
-  static_assert(kP == 4, "the wide staging reads take four slots");
-  DepIn<R> D;
-  {
-    const int k0 = tid * kP;
-    lds_load4(&sh.st.t[0][k0], D.tx);
-    lds_load4(&sh.st.t[1][k0], D.ty);
-    lds_load4(&sh.st.t[2][k0], D.tz);
-    const uint32_t q4 = *reinterpret_cast<const uint32_t *>(&sh.st.q[k0]);
-    uint2 c4[3];
-    for (int a = 0; a < 3; ++a) c4[a] = *reinterpret_cast<const uint2 *>(&sh.st.c[a][k0]);
-#pragma unroll
-    for (int p = 0; p < kP; ++p) {
-      const uint8_t q = (uint8_t)(q4 >> (8 * p));
-      D.on[p] = q != 0xFF;
-      D.q[p] = q;
-      const int sh16 = 16 * (p & 1);
-      D.ix[p] = (int)(((p < 2 ? c4[0].x : c4[0].y) >> sh16) & 0xffffu);
-      D.iy[p] = (int)(((p < 2 ? c4[1].x : c4[1].y) >> sh16) & 0xffffu);
-      D.iz[p] = (int)(((p < 2 ? c4[2].x : c4[2].y) >> sh16) & 0xffffu);
-    }
-  }
-  const int x0 = box[0], y0 = box[1], z0 = box[2];
-  const bool any = box[3] >= 0;
-  const int bx = box[3] - x0 + 2, by = box[4] - y0 + 2, bz = box[5] - z0 + 2;
-  __syncthreads();  // staging read: the brick may now reuse it
-  if (!any) return;
-  const int64_t nodes = (int64_t)bx * by * bz;
-  // the lanes' last runs: one segmented sum per wavefront, then only the
-  // last lane of each segment (usually 2-3 per wavefront) flushes
-  auto flush_last = [&](DepRun &L, auto &&flush) {
-    const int key = (int)L.node;
-    int seg;
-    bool tail;
-    wave_runs(key, seg, tail);
-    const SegSteps st = seg_steps(seg);
-    const bool out = tail && key >= 0;
-    for (int k = 0; k < 8; ++k) {
-      if (dm & 1u) {
-        const double v = seg_scan(st, L.a[k]);
-        if (out && v != 0.0) flush(key, 0, k, v);
-      }
-      if (dm & 2u) {
-        const double v = seg_scan(st, L.b[k]);
-        if (out && v != 0.0) flush(key, 1, k, v);
-      }
-      if (dm & 4u) {
-        const double v = seg_scan(st, L.c[k]);
-        if (out && v != 0.0) flush(key, 2, k, v);
-      }
-    }
-  };
-  if (nodes <= kDepBrick / kFields) {
-    const int nb = (int)nodes;
-    for (int i = tid; i < kFields * nb; i += kBlock) sh.brick[i] = 0.0;
-    __syncthreads();
-    double *br = sh.brick;
-    auto to_brick = [&](int64_t base, int f, int k, double v) {
-      const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-      atomicAdd(&br[f * nb + (int)base + dx + bx * (dy + by * dz)], v);
-    };
-    DepRun L;
-    run_accumulate<R, true>(
-        D, dm,
-        [&](int ix, int iy, int iz) -> int64_t { return (int64_t)((ix - x0) + bx * ((iy - y0) + by * (iz - z0))); },
-        to_brick, L);
-    flush_last(L, to_brick);
-    __syncthreads();
-    for (int i = tid; i < kFields * nb; i += kBlock) {
-      const double v = sh.brick[i];
-      if (v != 0.0) {
-        const int f = i / nb, li = i - f * nb;
-        const int lx = li % bx, ly = (li / bx) % by, lz = li / (bx * by);
-        const int64_t node = (int64_t)(x0 + lx) + (int64_t)P.nx1 * ((y0 + ly) + (int64_t)P.ny1 * (z0 + lz));
-        unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + node], v);
-      }
-    }
-  } else {
-    // a tile whose nodes do not fit the brick (typically one that spans two
-    // planes of cells): runs go to HBM, still summed over the wavefront
-    // first, so that the dense cells at either end take a few atomics each
-    const int nx1 = P.nx1, ny1 = P.ny1;
-    auto to_hbm = [&](int64_t base, int f, int k, double v) {
-      const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-      unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + base + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz)], v);
-    };
-    DepRun L;
-    run_accumulate<R, true>(
-        D, dm, [&](int ix, int iy, int iz) -> int64_t { return (int64_t)ix + (int64_t)nx1 * (iy + (int64_t)ny1 * iz); },
-        to_hbm, L);
-    flush_last(L, to_hbm);
-  }
-}
-
-__device__ __forceinline__ void box_init(int *box) {
-  if (threadIdx.x < 6) box[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -1;
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
 // Push + wall/aperture + MCC (+ deposit): slot j = tile + tid + 256 p.
 // ---------------------------------------------------------------------------
-// a lane's contribution to the next step's cell grids (chg_next: the ion
-// charge Q in channel 0, or one atom in its species' channel): lanes hold
-// consecutive slots, mostly of one cell, so the last lane of each run of
-// equal entries adds the run's sum with one atomic
-__device__ __forceinline__ void add_charge(uint32_t *__restrict__ chg, uint32_t cell, uint32_t q) {
-  int seg;
-  bool tail;
-  wave_runs((int64_t)cell, seg, tail);
-  q = seg_scan(seg_steps(seg), q);
-  if (tail && cell != 0xffffffffu && q != 0u) atomicAdd(&chg[cell], q);
-}
-
-// DEP: 0 no deposit, 1 deposit with the run's mask, 2 deposit of exactly the
 // ion number and charge fields
 template <typename R, int FLD, int DEP, bool EXT>
 __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__restrict__ T, Soa<R> S,
@@ -721,7 +91,13 @@ __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__rest
       const uint32_t id = S.pid[j];
       int Q = q_of(qs0);
       const int s = sp_of(qs0);
-      const uint8_t ev = advance<R, FLD, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur);
+      double u = 0.0;
+      if (needs_mcc_uniform(P)) {
+        const uint4 W = draw(P, id, step, S_STEP, 0);
+        u = u53(W.x, W.y);
+      }
+      const uint8_t ev =
+          advance<R, FLD, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur, u);
       S.x[j] = x;
       S.y[j] = y;
       S.z[j] = z;

@@ -33,6 +33,9 @@ struct Layout {
   size_t soa[2][9];  // offsets of x y z vx vy vz qs pid birth in buffer A and B
   size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, bfield,
       evlog;
+  size_t fchunks;  // chunk table of the fused step kernel
+  size_t big;      // its oversized chunks: count, then indices
+  size_t scratch64;  // sort space of the pools that exceed the LDS (fused kernel)
   size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
   size_t cxreq;   // exchanges per species and collision cell (ECR_FLAG_CX_PARTNER)
   size_t cxchunk; // per Coulomb chunk: any of them in its cells
@@ -72,6 +75,12 @@ Layout make_layout(const ecr_params *p) {
   o = align_up(o + 4 * N);
   L.chunks = o;
   o = align_up(o + 4 * (size_t)(coul_nchunks((int64_t)N) + 2));
+  L.fchunks = o;
+  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 2));
+  L.big = o;
+  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 1));
+  L.scratch64 = o;
+  o = align_up(o + 8 * N);
   L.pairs = o;
   o = align_up(o + sizeof(CoulItem) * kCoulItems * (size_t)coul_nchunks((int64_t)N));
   L.tris = o;  // per-chunk (pairs, triplets) counts
@@ -504,6 +513,13 @@ struct ProfScope {
   }
 };
 
+// the whole step in one kernel: the default, for the analytic magnetic
+// field without an electric field grid; ECR_FLAG_SPLIT (per-kernel timing)
+// and the field grids run the step as separate kernels
+bool fused(const ecr_run *r) {
+  return !(r->p.flags & ECR_FLAG_SPLIT) && !r->p.efield_nodes && !r->kp.bmap;
+}
+
 template <typename R>
 void do_sort(ecr_run *r, const uint32_t *given) {
   ProfScope ps(r, ECR_K_SORT);
@@ -511,11 +527,20 @@ void do_sort(ecr_run *r, const uint32_t *given) {
   launch_sort<R>(r->kp, soa<R>(r, a), soa<R>(r, b), given, at<uint32_t>(r, r->L.key), at<uint32_t>(r, r->L.rank),
                  at<uint32_t>(r, r->L.count), at<uint32_t>(r, r->L.cell_off), at<uint32_t>(r, r->L.bsum),
                  at<uint32_t>(r, r->L.cellid), r->ncell, r->stream);
-  if (r->kp.n > 0)
+  if (r->kp.n > 0) {
     launch_coul_chunks(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off), r->kp.n,
-                       at<uint32_t>(r, r->L.chunks), r->stream);
+                       at<uint32_t>(r, r->L.chunks), kCoulCap, r->stream);
+    if (fused(r)) {
+      launch_coul_chunks(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off), r->kp.n,
+                         at<uint32_t>(r, r->L.fchunks), kFCap, r->stream);
+      launch_big_list(at<uint32_t>(r, r->L.fchunks), r->kp.n, at<uint32_t>(r, r->L.big), r->stream);
+    }
+  }
   r->cur = b;
 }
+
+template <typename R>
+void step_tail(ecr_run *r, StepArg stepw, bool grids);
 
 // one step; sa gives the step number the kernels use (the host's counter in
 // eager launches, a device word plus an offset inside a captured graph)
@@ -532,6 +557,18 @@ void do_step(ecr_run *r, StepArg stepw) {
   uint32_t *chg_cur = grids ? at<uint32_t>(r, r->L.chg[r->chg_par]) : nullptr;
   uint32_t *chg_next = grids ? at<uint32_t>(r, r->L.chg[1 - r->chg_par]) : nullptr;
   const int64_t chg_words = r->ncell * (1 + r->p.n_species);
+  if (fused(r)) {
+    if (grids) launch_fill_u32(chg_next, 0u, chg_words, r->stream);
+    {
+      ProfScope ps(r, ECR_K_STEP);
+      launch_step<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks),
+                     at<uint32_t>(r, r->L.big), (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr,
+                     acc, (pm & ECR_P_DEPOSIT) ? at<double>(r, r->L.dens) : nullptr, at<double>(r, r->L.moments),
+                     at<uint64_t>(r, r->L.scratch64), stepw, chg_cur, chg_next, r->stream);
+    }
+    step_tail<R>(r, stepw, grids);
+    return;
+  }
   // the ordering kernel clears the next step's grids when it runs
   const bool fold = grids && (pm & ECR_P_COULOMB) && r->kp.n > 1;
   if (pm & ECR_P_COULOMB) {
@@ -554,11 +591,19 @@ void do_step(ecr_run *r, StepArg stepw) {
                    (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr, acc,
                    (dep && !split) ? at<double>(r, r->L.dens) : nullptr, stepw, chg_cur, chg_next, r->stream);
   }
-  if (grids) r->chg_par = 1 - r->chg_par;
   if (dep && split) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
   }
+  step_tail<R>(r, stepw, grids);
+}
+
+// after the push: the pressure moment, the exchange partners, the counters
+template <typename R>
+void step_tail(ecr_run *r, StepArg stepw, bool grids) {
+  DevAccum *acc = at<DevAccum>(r, r->L.acc);
+  const bool dep = (r->p.process_mask & ECR_P_DEPOSIT) != 0;
+  if (grids) r->chg_par = 1 - r->chg_par;
   if (dep && (r->p.deposit_mask & (1u << ECR_F_ION_P))) {
     ProfScope ps(r, ECR_K_DEPOSIT);
     launch_deposit_pressure<R>(r->kp, soa<R>(r, r->cur), at<double>(r, r->L.dens), r->stream);
@@ -970,10 +1015,6 @@ ecr_status ecr_read_tallies(ecr_run *r, ecr_tallies *out) {
   out->steps = r->steps;
   if (h.err & ERR_COUL_OVERFLOW) {
     r->err = "a Coulomb chunk exceeded the LDS capacity; its cells were skipped";
-    out->anomalies += 1;
-  }
-  if (h.err & ERR_PARTNER_OVERFLOW) {
-    r->err = "an exchange-partner chunk exceeded the LDS capacity; its exchanges found no partner";
     out->anomalies += 1;
   }
   if (out->anomalies > 0) return fail(r, ECR_ENUMERIC, r->err.empty() ? "anomalies counted" : r->err);

@@ -602,23 +602,28 @@ def test_kernel_timing_every_launch_and_sampled():
     # ecr_profile brackets launches with events; ecr_profile_stride keeps
     # one launch in stride of each kind; timing leaves the results unchanged
     params = W.with_(W.config("c1")[0], sort_every=10)
-    a, b = gpu_run(params), gpu_run(params)
-    a.init_ions()
-    b.init_ions()
-    a.profile(True)
-    a.step(20)
-    kt = a.kernel_times()
-    assert kt["push_deposit"][1] == 20 and kt["coul_order"][1] == 20 and kt["sort"][1] == 2
-    assert all(ms > 0 for ms, c in kt.values() if c)
-    a.profile(True, kinds=["push_deposit"], stride=6)
-    a.step(20)
-    kt = a.kernel_times()
-    assert kt["push_deposit"][1] == 4 and kt["coul_order"][1] == 0  # launches 0, 6, 12, 18
-    a.profile(False)
-    b.step(40)
-    sa, sb = a.get_state(), b.get_state()
-    for k in ("x", "vx", "q"):
-        assert np.array_equal(sa[k], sb[k])
+    for split, main in ((False, "step"), (True, "push")):
+        a, b = gpu_run(params, split=split), gpu_run(params, split=split)
+        a.init_ions()
+        b.init_ions()
+        a.profile(True)
+        a.step(20)
+        kt = a.kernel_times()
+        assert kt[main][1] == 20 and kt["sort"][1] == 2
+        if split:  # the step as separate kernels
+            assert kt["coul_order"][1] == kt["coul_pairs"][1] == 20 and kt["step"][1] == 0
+        else:  # the whole step in one kernel
+            assert kt["coul_order"][1] == kt["coul_pairs"][1] == kt["push_deposit"][1] == 0
+        assert all(ms > 0 for ms, c in kt.values() if c)
+        a.profile(True, kinds=[main], stride=6)
+        a.step(20)
+        kt = a.kernel_times()
+        assert kt[main][1] == 4 and kt["sort"][1] == 0  # launches 0, 6, 12, 18
+        a.profile(False)
+        b.step(40)
+        sa, sb = a.get_state(), b.get_state()
+        for k in ("x", "vx", "q"):
+            assert np.array_equal(sa[k], sb[k])
     import paper_1507_03392_amd as ecr
     with pytest.raises(ecr.EcrError):
         a.profile(True, stride=0)
@@ -681,6 +686,62 @@ def test_exchange_partners_in_a_chunk_beyond_the_lds():
     crowded = np.bincount(o.get_state()["cell"].astype(np.int64)).max()
     assert crowded >= 5000
     assert int((o.events()[:k] == W.EV_CX_PARTNER).sum()) > 0  # partners were taken in the crowded cell
+
+
+@pytest.mark.parametrize("m", [1500, 5001])
+def test_coulomb_pool_beyond_a_chunk(m):
+    # one cell whose pool holds m ions, more than a chunk of the one-kernel
+    # step (1024 slots): its pool is sorted by (key, id) with a bitonic
+    # network (in LDS for 1500, in global scratch memory for 5001) and every
+    # ion collides, bit for bit with the oracle, whose pool has no size limit
+    params = W.base_params(20_011, 16, 16, 32, seed=12)
+    params.update(process_mask=W.P_COULOMB | W.P_PUSH | W.P_DEPOSIT, weight=2e9)
+    st = W.random_state(params, seed=60 + m % 7, q_max=8, v_ev=5.0, frac_atoms=0.1)
+    hx, hz = 2 * params["R0"] / 16, params["L"] / 32
+    rng = np.random.default_rng(61)
+    st["x"][:m] = -params["R0"] + (5.2 + 0.6 * rng.random(m)) * hx
+    st["y"][:m] = -params["R0"] + (9.2 + 0.6 * rng.random(m)) * hx
+    st["z"][:m] = -params["L"] / 2 + (20.2 + 0.6 * rng.random(m)) * hz
+    st["q"][:m] = rng.integers(1, 9, m)
+    g, o = run_pair(params, st, 2, step0=3)
+    a, b = g.get_state(), o.get_state()
+    assert_state_close(a, b, params, what=f"pool of {m}")
+    assert np.bincount(b["cell"].astype(np.int64)).max() >= m
+    tg, to = g.tallies(), o.tallies()
+    assert tg["anomalies"] == 0
+    assert tg["coul_e"] == pytest.approx(to["coul_e"], rel=1e-12)
+    for f in (W.F_ION_N, W.F_ION_Q):
+        (dg, ng), (do, no) = g.density(f), o.density(f)
+        assert ng == no == 2 and np.abs(dg - do).max() <= 1e-12 * np.abs(do).max()
+    assert (a["vx"][:m] != st["vx"][:m]).mean() > 0.95  # the crowded cell's ions collided
+
+
+def test_split_kernels_flag_a_pool_beyond_their_chunk():
+    # the per-kernel (split) form orders at most 1024 ions per chunk in
+    # LDS: a larger pool skips the step's collisions and the read calls
+    # report it (ECR_ENUMERIC); the one-kernel step collides them
+    import paper_1507_03392_amd as ecr
+    params = W.base_params(4_000, 16, 16, 32, seed=13)
+    params.update(process_mask=W.P_COULOMB, weight=2e9)
+    st = W.random_state(params, seed=64, q_max=4, v_ev=5.0, frac_atoms=0.0)
+    hx, hz = 2 * params["R0"] / 16, params["L"] / 32
+    rng = np.random.default_rng(65)
+    m = 1500
+    st["x"][:m] = -params["R0"] + (5.2 + 0.6 * rng.random(m)) * hx
+    st["y"][:m] = -params["R0"] + (9.2 + 0.6 * rng.random(m)) * hx
+    st["z"][:m] = -params["L"] / 2 + (20.2 + 0.6 * rng.random(m)) * hz
+    g = gpu_run(params, split=True)
+    g.set_state(st, step=0)
+    g.step(1)
+    with pytest.raises(ecr.EcrError) as e:
+        g.tallies(allow_anomalies=False)
+    assert e.value.status == -5 and "Coulomb chunk" in str(e.value)
+    assert (g.get_state()["vx"][:m] == st["vx"][:m]).all()  # the crowded cell did not collide
+    f = gpu_run(params)
+    f.set_state(st, step=0)
+    f.step(1)
+    assert f.tallies(allow_anomalies=False)["anomalies"] == 0
+    assert (f.get_state()["vx"][:m] != st["vx"][:m]).mean() > 0.95
 
 
 def test_coulomb_in_a_cell_crowded_with_atoms():
