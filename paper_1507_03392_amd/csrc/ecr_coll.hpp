@@ -41,18 +41,18 @@ __device__ __forceinline__ void collide_acc(const KParams &P, const double *__re
   const R ux = vax - vbx, uy = vay - vby, uz = vaz - vbz;
   const R g2 = (ux * ux + uy * uy) + uz * uz;
   if (g2 == (R)0) return;
-  const R g = sqrt(g2);
+  const R g = sqrt_cont(g2);
   const double mu = P.mu[sa][sb];  // (ma mb) / (ma + mb), tabulated on the host
   const double qq = (double)q_of(qa) * (double)q_of(qb);
   const double num = ((P.Cs * (qq * qq)) * nc) * dtp;
   const double den = (mu * mu) * ((double)g2 * (double)g);
   const double sv = num / den;
   const R omc = (R)nanbu_omc(lnA, sv, u);
-  const R sinchi = sqrt(omc * ((R)2 - omc));
+  const R sinchi = sqrt_cont(omc * ((R)2 - omc));
   R sp, cp;
   sincospi_r((R)(2.0 * u2), &sp, &cp);  // phi = 2 pi u2
   const R ca = sinchi * cp, cb = sinchi * sp;
-  const R uperp = sqrt(ux * ux + uy * uy);
+  const R uperp = sqrt_cont(ux * ux + uy * uy);
   R dux, duy, duz;
   if (uperp > (R)0) {
     const R iu = (R)1 / uperp;

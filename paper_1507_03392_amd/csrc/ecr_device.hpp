@@ -436,6 +436,63 @@ __device__ __forceinline__ void elastic_outcome(const KParams &P, uint32_t id, u
 }
 
 // ---------------------------------------------------------------------------
+// Square root and log1p for continuous outcomes of a collision (never for a
+// decision, which keeps the correctly rounded library operations).
+// sqrt: the hardware reciprocal square root refined by two Goldschmidt
+// steps (coupled iterations on the root and half its reciprocal), then one
+// Newton correction of the root: within an ulp of the correctly rounded root
+// at half the library's cost.  Zero, subnormal, huge and non-finite inputs
+// take the library path.
+// log1p(x) for x in (-1, 0]: y = 1 + x and its rounding error d = x - (y - 1)
+// (exact: Sterbenz), y = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// log m = 2 atanh(s), s = (m - 1)/(m + 1), summed as 2 s sum_k z^k/(2k+1),
+// z = s^2 <= 0.0295, through k = 11 (truncation below 2^-60 relative);
+// log1p x = e ln2 + log m + d/y.  Within 2 ulp of the correctly rounded
+// value, at half the library's cost.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sqrt_cont(double x) {
+  if (!(x >= 0x1p-1000 && x <= 0x1p+1000)) return sqrt(x);
+  const double h = __builtin_amdgcn_rsq(x);
+  double g = x * h, hh = 0.5 * h;
+  const double r = fma(-g, hh, 0.5);
+  g = fma(g, r, g);
+  hh = fma(hh, r, hh);
+  const double d = fma(-g, g, x);
+  return fma(d, hh, g);
+}
+__device__ __forceinline__ float sqrt_cont(float x) { return sqrtf(x); }
+
+__device__ __forceinline__ double log1p_cont(double x) {
+  const double y = 1.0 + x;
+  const double d = x - (y - 1.0);
+  int e;
+  double m = frexp(y, &e);
+  if (m < 0.70710678118654752440) {
+    m = m + m;
+    e -= 1;
+  }
+  const double f = m - 1.0;
+  const double sv = f / (2.0 + f);
+  const double z = sv * sv;
+  double p = 2.0 / 23.0;
+  p = fma(p, z, 2.0 / 21.0);
+  p = fma(p, z, 2.0 / 19.0);
+  p = fma(p, z, 2.0 / 17.0);
+  p = fma(p, z, 2.0 / 15.0);
+  p = fma(p, z, 2.0 / 13.0);
+  p = fma(p, z, 2.0 / 11.0);
+  p = fma(p, z, 2.0 / 9.0);
+  p = fma(p, z, 2.0 / 7.0);
+  p = fma(p, z, 2.0 / 5.0);
+  p = fma(p, z, 2.0 / 3.0);
+  // ln 2 = ln2_hi + ln2_lo, ln2_hi with its low 32 bits zero (e ln2_hi exact)
+  constexpr double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+  const double de = (double)e;
+  const double lm = fma(sv * z, p, 2.0 * sv);
+  return fma(de, ln2_hi, lm + fma(de, ln2_lo, d / y));
+}
+
+// ---------------------------------------------------------------------------
 // Nanbu: 1 - cos(chi) = -log1p(u expm1(-2A))/A with A(s) from the table
 // (ln A linear in s between nodes), A = 1/s below 2^-20, isotropic from 8.
 // ---------------------------------------------------------------------------
@@ -461,7 +518,7 @@ __device__ __forceinline__ double nanbu_omc(const double *__restrict__ lnA, doub
     // for A > 20, exp(-2A) < 5e-18 is below half an ulp of 1, so expm1(-2A)
     // rounds to -1 exactly: skip the call (most pairs of a cool plasma)
     const double em = A > 20.0 ? -1.0 : expm1(-2.0 * A);
-    omc = -log1p(u * em) / A;
+    omc = -log1p_cont(u * em) / A;
   }
   omc = omc < 0.0 ? 0.0 : omc;
   omc = omc > 2.0 ? 2.0 : omc;

@@ -100,12 +100,18 @@ void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hi
 // launch_big_list at the sort); moments as for the Coulomb kernels;
 // scratch64: n 64-bit words of sort space for pools beyond the LDS.  With
 // chg_next, it must have been zeroed before.
+// At each sort, launch_step_prep lists the oversized chunks (big) and
+// tabulates the ordering's buckets of every other chunk: per slot
+// (bkinfo[n]) first bucket | log2(bucket count) << 16 of its cell, per chunk
+// (nbk[nchunks]) the bucket total.
 int64_t step_nchunks(int64_t n);
-void launch_big_list(const uint32_t *chunk_lo, int64_t n, uint32_t *big, hipStream_t st);
+void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, uint32_t *big, uint32_t *bkinfo,
+                      uint32_t *nbk, hipStream_t st);
 template <typename R>
 void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
-                 const uint32_t *big, uint8_t *evlog, DevAccum *acc, double *dens, double *moments,
-                 uint64_t *scratch64, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, hipStream_t st);
+                 const uint32_t *big, const uint32_t *bkinfo, const uint32_t *nbk, uint8_t *evlog, DevAccum *acc,
+                 double *dens, double *moments, uint64_t *scratch64, StepArg step, const uint32_t *chg_cur,
+                 uint32_t *chg_next, hipStream_t st);
 
 // sort by cell: keys either from positions or (given != nullptr) from given[pid]
 template <typename R>

@@ -96,6 +96,7 @@ __device__ __forceinline__ bool needs_mcc_uniform(const KParams &P) {
   return (P.pmask & (P_IONIZE | P_CX | P_ELASTIC)) != 0;
 }
 
+// birth[j]: the particle's birth step; P.cellid[jc]: its collision cell.
 // u: the particle's Monte-Carlo uniform of the step, u53 of words 0 and 1 of
 // its STEP draw (the caller draws it once; its word 2 is the Coulomb pairing
 // key of the same step)
@@ -103,7 +104,7 @@ template <typename R, int FLD, bool EXT>
 __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__restrict__ T,
                                            const double *__restrict__ ef, DevAccum *__restrict__ acc, uint32_t step,
                                            uint32_t id, int s, int &Q, R &x, R &y, R &z, R &vx, R &vy, R &vz,
-                                           uint32_t *__restrict__ birth, int64_t j,
+                                           uint32_t *__restrict__ birth, int64_t j, int64_t jc,
                                            const uint32_t *__restrict__ chg, double u) {
   uint8_t ev = EV_NONE;
   if (P.pmask & P_PUSH) {
@@ -232,7 +233,7 @@ __device__ __forceinline__ uint8_t advance(const KParams &P, const Tables *__res
         // the electron comes from a tracked atom of the collision cell,
         // picked at the end of the step; a Q = 1 ion is an atom from now
         // on and keeps its velocity
-        const uint32_t cc = P.cellid[j];
+        const uint32_t cc = P.cellid[jc];
         atomicAdd(&P.cxreq[(uint32_t)s * P.ncell + cc], 1u);
         // the chunk owning the cell: the one its first slot falls in
         P.cxchunk[P.cell_off[cc] / (uint32_t)kCoulCap] = 1u;
@@ -416,8 +417,19 @@ __device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int
   }
 }
 
-// deposit a staged tile; every lane of the workgroup must call it
-template <typename R, bool NQ>
+// exact i / d for 0 <= i < 2^22 and 0 < d < 2^22 (d uniform, rcp = 1/d in
+// binary32): the binary32 estimate is within one of the quotient
+__device__ __forceinline__ int small_div(int i, int d, float rcp) {
+  int q = (int)((float)i * rcp);
+  q = (q + 1) * d <= i ? q + 1 : q;
+  q = q * d > i ? q - 1 : q;
+  return q;
+}
+
+// deposit a staged tile; every lane of the workgroup must call it.  G: the
+// lanes' last runs are summed within groups of G lanes (G = 64: over the
+// whole wavefront) before the run's last lane in the group flushes them
+template <typename R, bool NQ, int G = 64>
 __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restrict__ dens, DepShared<R> &sh,
                                                int *box, int mn[3], int mx[3]) {
   const int tid = threadIdx.x;
@@ -451,33 +463,55 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
       D.iz[p] = (int)(((p < 2 ? c4[2].x : c4[2].y) >> sh16) & 0xffffu);
     }
   }
-  const int x0 = box[0], y0 = box[1], z0 = box[2];
-  const bool any = box[3] >= 0;
-  const int bx = box[3] - x0 + 2, by = box[4] - y0 + 2, bz = box[5] - z0 + 2;
+  // the box is the same for every lane: keep it in scalar registers
+  const int x0 = __builtin_amdgcn_readfirstlane(box[0]), y0 = __builtin_amdgcn_readfirstlane(box[1]);
+  const int z0 = __builtin_amdgcn_readfirstlane(box[2]);
+  const bool any = __builtin_amdgcn_readfirstlane(box[3]) >= 0;
+  const int bx = __builtin_amdgcn_readfirstlane(box[3]) - x0 + 2, by = __builtin_amdgcn_readfirstlane(box[4]) - y0 + 2;
+  const int bz = __builtin_amdgcn_readfirstlane(box[5]) - z0 + 2;
   __syncthreads();  // staging read: the brick may now reuse it
   if (!any) return;
   const int64_t nodes = (int64_t)bx * by * bz;
-  // the lanes' last runs: one segmented sum per wavefront, then only the
-  // last lane of each segment (usually 2-3 per wavefront) flushes
+  // the lanes' last runs: summed over runs of lanes (the whole wavefront,
+  // or groups of G lanes), then the last lane of each run flushes
   auto flush_last = [&](DepRun &L, auto &&flush) {
     const int key = (int)L.node;
     int seg;
     bool tail;
     wave_runs(key, seg, tail);
-    const SegSteps st = seg_steps(seg);
-    const bool out = tail && key >= 0;
-    for (int k = 0; k < 8; ++k) {
-      if (dm & 1u) {
-        const double v = seg_scan(st, L.a[k]);
-        if (out && v != 0.0) flush(key, 0, k, v);
+    if constexpr (G == 64) {
+      const SegSteps st = seg_steps(seg);
+      const bool out = tail && key >= 0;
+      for (int k = 0; k < 8; ++k) {
+        if (dm & 1u) {
+          const double v = seg_scan(st, L.a[k]);
+          if (out && v != 0.0) flush(key, 0, k, v);
+        }
+        if (dm & 2u) {
+          const double v = seg_scan(st, L.b[k]);
+          if (out && v != 0.0) flush(key, 1, k, v);
+        }
+        if (dm & 4u) {
+          const double v = seg_scan(st, L.c[k]);
+          if (out && v != 0.0) flush(key, 2, k, v);
+        }
       }
-      if (dm & 2u) {
-        const double v = seg_scan(st, L.b[k]);
-        if (out && v != 0.0) flush(key, 1, k, v);
-      }
-      if (dm & 4u) {
-        const double v = seg_scan(st, L.c[k]);
-        if (out && v != 0.0) flush(key, 2, k, v);
+    } else {
+      const GroupSteps<G> st = group_steps<G>(seg);
+      const bool out = (tail || (threadIdx.x & (G - 1)) == G - 1) && key >= 0;
+      for (int k = 0; k < 8; ++k) {
+        if (dm & 1u) {
+          const double v = group_scan<G>(st, L.a[k]);
+          if (out && v != 0.0) flush(key, 0, k, v);
+        }
+        if (dm & 2u) {
+          const double v = group_scan<G>(st, L.b[k]);
+          if (out && v != 0.0) flush(key, 1, k, v);
+        }
+        if (dm & 4u) {
+          const double v = group_scan<G>(st, L.c[k]);
+          if (out && v != 0.0) flush(key, 2, k, v);
+        }
       }
     }
   };
@@ -486,9 +520,11 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
     for (int i = tid; i < kFields * nb; i += kBlock) sh.brick[i] = 0.0;
     __syncthreads();
     double *br = sh.brick;
+    // corner k of a cell is node base + dx + bx (dy + by dz)
+    const int cyz = bx * by;
     auto to_brick = [&](int64_t base, int f, int k, double v) {
       const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-      atomicAdd(&br[f * nb + (int)base + dx + bx * (dy + by * dz)], v);
+      atomicAdd(&br[f * nb + (int)base + (dx + (dy ? bx : 0) + (dz ? cyz : 0))], v);
     };
     DepRun L;
     run_accumulate<R, true>(
@@ -497,11 +533,13 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
         to_brick, L);
     flush_last(L, to_brick);
     __syncthreads();
+    const float rnb = 1.0f / (float)nb, rbx = 1.0f / (float)bx, rby = 1.0f / (float)by;
     for (int i = tid; i < kFields * nb; i += kBlock) {
       const double v = sh.brick[i];
       if (v != 0.0) {
-        const int f = i / nb, li = i - f * nb;
-        const int lx = li % bx, ly = (li / bx) % by, lz = li / (bx * by);
+        const int f = small_div(i, nb, rnb), li = i - f * nb;
+        const int t = small_div(li, bx, rbx), lx = li - t * bx;
+        const int lz = small_div(t, by, rby), ly = t - lz * by;
         const int64_t node = (int64_t)(x0 + lx) + (int64_t)P.nx1 * ((y0 + ly) + (int64_t)P.ny1 * (z0 + lz));
         unsafeAtomicAdd(&dens[(int64_t)f * P.nnode + node], v);
       }

@@ -149,6 +149,59 @@ __device__ __forceinline__ uint32_t seg_scan(const SegSteps &s, uint32_t x) {
   return x;
 }
 
+// Segmented sums within aligned groups of G consecutive lanes (G = 2, 4, 8
+// or 16, inside a row of 16), by log2 G row_shr steps: a group boundary acts
+// as a run boundary, so after the steps a lane holds the sum over the lanes
+// of its run from the later of the run's first lane and the group's first
+// lane up to itself.  Cheaper than the whole-wavefront sums (fewer steps, no
+// bcast rows); the last lane of each run within a group carries the partial
+// sum that has to be flushed.
+template <int G>
+struct GroupSteps {
+  bool t[4];
+};
+
+template <int G>
+__device__ __forceinline__ GroupSteps<G> group_steps(int seg) {
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "groups inside a row of 16 lanes");
+  const int gl = (int)(threadIdx.x & (G - 1));  // lane within the group
+  GroupSteps<G> s;
+  s.t[0] = dpp_move<0x111, 0xf>(-1, seg) == seg && gl >= 1;
+  s.t[1] = G > 2 && dpp_move<0x112, 0xf>(-1, seg) == seg && gl >= 2;
+  s.t[2] = G > 4 && dpp_move<0x114, 0xf>(-1, seg) == seg && gl >= 4;
+  s.t[3] = G > 8 && dpp_move<0x118, 0xf>(-1, seg) == seg && gl >= 8;
+  return s;
+}
+
+// a lane's double from the lane CTRL names (any value where there is none:
+// the caller selects)
+template <int CTRL>
+__device__ __forceinline__ double dpp_take_d(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int G>
+__device__ __forceinline__ double group_scan(const GroupSteps<G> &s, double x) {
+  double o = dpp_take_d<0x111>(x);
+  x = s.t[0] ? x + o : x;
+  if (G > 2) {
+    o = dpp_take_d<0x112>(x);
+    x = s.t[1] ? x + o : x;
+  }
+  if (G > 4) {
+    o = dpp_take_d<0x114>(x);
+    x = s.t[2] ? x + o : x;
+  }
+  if (G > 8) {
+    o = dpp_take_d<0x118>(x);
+    x = s.t[3] ? x + o : x;
+  }
+  return x;
+}
+
 // the wavefront's cell-index bounding box (minima and maxima of three
 // indices) by the same DPP moves, in lane 63; called by all 64 lanes
 template <int CTRL, int ROWS>

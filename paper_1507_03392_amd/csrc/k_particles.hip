@@ -97,7 +97,7 @@ __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__rest
         u = u53(W.x, W.y);
       }
       const uint8_t ev =
-          advance<R, FLD, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur, u);
+          advance<R, FLD, EXT>(P, T, ef, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, j, chg_cur, u);
       S.x[j] = x;
       S.y[j] = y;
       S.z[j] = z;

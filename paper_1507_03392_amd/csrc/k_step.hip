@@ -54,17 +54,14 @@ constexpr int kBigWG = 4;                 // handler workgroups of oversized chu
 static_assert(kFMax == kTile, "the deposit stages one tile: the chunk");
 static_assert(kFLead <= 64, "per-wave counts fit one wavefront");
 
-// LDS layout in bytes.  Ordering (steps 1-2): skey, cells / scan scratch /
-// histogram, head index, first slot / first bucket of each cell, members by
-// bucket then by pool position.  Collisions (steps 3-5): the velocities over
+// LDS layout in bytes.  Ordering (steps 1-2): skey, the bucket histogram,
+// members by bucket then by pool position.  Collisions (steps 3-5): the velocities over
 // the ordering arrays, the work items beyond both.  Ids and charges (steps
 // 1-4) beyond all of these.  Deposit (steps 6-7): the staging and brick over
 // everything.
 constexpr int kSkeyOff = 0;
 constexpr int kR1Off = kSkeyOff + 8 * kFMax;
-constexpr int kHdOff = kR1Off + 4 * (kFMax + 2);
-constexpr int kHcOff = kHdOff + 2 * kFMax;
-constexpr int kOrdOff = kHcOff + 2 * (kFMax + 2);
+constexpr int kOrdOff = kR1Off + 4 * (kFMax + 2);
 constexpr int kOrdEnd = kOrdOff + 2 * kFMax;
 constexpr int align16(int v) { return (v + 15) / 16 * 16; }
 template <typename R>
@@ -153,7 +150,7 @@ __device__ __forceinline__ void push_tile_global(const KParams &P, const Tables 
         u = u53(W.x, W.y);
       }
       const uint8_t ev =
-          advance<R, 0, EXT>(P, T, nullptr, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, chg_cur, u);
+          advance<R, 0, EXT>(P, T, nullptr, acc, step, id, s, Q, x, y, z, vx, vy, vz, S.birth, j, j, chg_cur, u);
       S.x[j] = x;
       S.y[j] = y;
       S.z[j] = z;
@@ -286,7 +283,9 @@ template <typename R, int DEP, bool EXT>
 __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k_step(KParams P, const Tables *__restrict__ T, Soa<R> S,
                                               const uint32_t *__restrict__ cellid,
                                               const uint32_t *__restrict__ chunk_lo,
-                                              const uint32_t *__restrict__ big, uint8_t *__restrict__ evlog,
+                                              const uint32_t *__restrict__ big,
+                                              const uint32_t *__restrict__ bkinfo,
+                                              const uint32_t *__restrict__ nbk, uint8_t *__restrict__ evlog,
                                               DevAccum *__restrict__ acc, double *__restrict__ dens,
                                               double *__restrict__ moments, uint64_t *__restrict__ scratch64,
                                               StepArg sa, const uint32_t *__restrict__ chg_cur,
@@ -311,35 +310,49 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
   const int64_t lo = chunk_lo[b];
   const int nsl = (int)((int64_t)chunk_lo[b + 1] - lo);
   if (nsl <= 0 || nsl > kFMax) return;  // empty, or an oversized chunk (taken by a handler)
+  // the chunk's arrays from its first slot: uniform bases, 32-bit offsets
+  S.x += lo;
+  S.y += lo;
+  S.z += lo;
+  S.vx += lo;
+  S.vy += lo;
+  S.vz += lo;
+  S.qs += lo;
+  S.pid += lo;
+  S.birth += lo;
+  bkinfo += lo;
+  if (evlog) evlog += lo;
   const int lane = tid & 63, wv = tid >> 6;
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const bool coul = (P.pmask & P_COULOMB) != 0 && nsl >= 2;
   const bool mcc = needs_mcc_uniform(P);
   uint64_t *skey = reinterpret_cast<uint64_t *>(lds + kSkeyOff);
-  uint32_t *r1 = reinterpret_cast<uint32_t *>(lds + kR1Off);
-  uint16_t *hd = reinterpret_cast<uint16_t *>(lds + kHdOff);
-  uint16_t *hcell = reinterpret_cast<uint16_t *>(lds + kHcOff);
+  uint32_t *hist = reinterpret_cast<uint32_t *>(lds + kR1Off);
   uint16_t *ord = reinterpret_cast<uint16_t *>(lds + kOrdOff);
   R *vs = reinterpret_cast<R *>(lds);
   uint64_t *items = reinterpret_cast<uint64_t *>(lds + items_off<R>());
   uint32_t *sid = reinterpret_cast<uint32_t *>(lds + sid_off<R>());
   uint8_t *sqs = lds + sqs_off<R>();
 
-  // 1. load; one STEP draw per particle: uniform (words 0-1) and pairing key (word 2)
+  // 1. load; one STEP draw per particle: uniform (words 0-1) and pairing key
+  //    (word 2); the slot's buckets (first bucket, log2 of their number: its
+  //    cell's, set at the sort)
   uint8_t qs[kFR];
-  uint32_t id[kFR], key[kFR];
+  uint32_t id[kFR], key[kFR], bki[kFR];
   double u[kFR];
   bool pool[kFR];
+  const int nbuckets = coul ? (int)nbk[b] : 0;
+  for (int i = tid; i <= nbuckets; i += kFB) hist[i] = 0u;
 #pragma unroll
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
     qs[k] = 0;
-    id[k] = key[k] = 0u;
+    id[k] = key[k] = bki[k] = 0u;
     u[k] = 0.0;
     pool[k] = false;
     if (i < nsl) {
-      const int64_t j = lo + i;
+      const int j = i;
       qs[k] = S.qs[j];
       id[k] = S.pid[j];
       pool[k] = coul && q_of(qs[k]) >= 1;
@@ -349,7 +362,7 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
         key[k] = W.z;
       }
       if (coul) {
-        r1[i] = cellid[j];
+        bki[k] = bkinfo[j];
         skey[i] = ((uint64_t)key[k] << 32) | id[k];
         sid[i] = id[k];
         sqs[i] = qs[k];
@@ -359,59 +372,15 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
   int nitems = 0, ntri = 0;
   if (coul) {
     __syncthreads();
-    // 2a. cells: heads (ballots per round and wave, a scan of the counts),
-    //     the cell index of every slot, the first slot of every cell
-    uint32_t fl[kFR];
-    uint64_t hb[kFR];
-#pragma unroll
-    for (int k = 0; k < kFR; ++k) {
-      const int i = tid + k * kFB;
-      fl[k] = (i < nsl && (i == 0 || r1[i] != r1[i - 1])) ? 1u : 0u;
-      hb[k] = __ballot(fl[k] != 0u);
-      if (lane == 0) lead[k * (kFB / 64) + wv] = (uint32_t)__popcll(hb[k]);
-    }
-    __syncthreads();
-    const uint32_t hc = lane < kFLead ? lead[lane] : 0u;
-    const uint32_t hincl = wave_incl_scan(hc), hexcl = hincl - hc;
-    const int nheads = __builtin_amdgcn_readlane((int)hincl, kFLead - 1);
-#pragma unroll
-    for (int k = 0; k < kFR; ++k) {
-      const int i = tid + k * kFB;
-      if (i < nsl) {
-        const int h = __builtin_amdgcn_readlane((int)hexcl, k * (kFB / 64) + wvu) + (int)__popcll(hb[k] & below) +
-                      (int)fl[k] - 1;
-        hd[i] = (uint16_t)h;
-        if (fl[k]) hcell[h] = (uint16_t)i;
-      }
-    }
-    if (tid == 0) hcell[nheads] = (uint16_t)nsl;
-    __syncthreads();
-    // 2b. buckets per cell: 2^floor(log2(slots of the cell)), at most one per slot
-    for (int h = tid; h < nheads; h += kFB) {
-      const int m = hcell[h + 1] - hcell[h];
-      const int lg = m <= 1 ? 0 : 31 - __clz(m);
-      r1[h] = 1u << lg;
-    }
-    __syncthreads();
-    const int nbuckets = (int)wg_exscan<kFB>(r1, nheads, wsum);
-    uint16_t *hbase = hcell;  // the cells' first slots are dead: their first buckets
-    for (int h = tid; h < nheads; h += kFB) hbase[h] = (uint16_t)r1[h];
-    if (tid == 0) hbase[nheads] = (uint16_t)nbuckets;
-    __syncthreads();
     // 2c. histogram of the pool members over their cell's buckets
-    uint32_t *hist = r1;
-    for (int i = tid; i <= nbuckets; i += kFB) hist[i] = 0u;
-    __syncthreads();
     int bk[kFR], arr[kFR];
 #pragma unroll
     for (int k = 0; k < kFR; ++k) {
-      const int i = tid + k * kFB;
       bk[k] = 0;
       arr[k] = 0;
       if (pool[k]) {
-        const int h = hd[i];
-        const int lg = 31 - __clz(hbase[h + 1] - hbase[h]);
-        bk[k] = hbase[h] + (lg ? (int)(key[k] >> (32 - lg)) : 0);
+        const int lg = (int)(bki[k] >> 16);
+        bk[k] = (int)(bki[k] & 0xffffu) + (lg ? (int)(key[k] >> (32 - lg)) : 0);
         arr[k] = (int)atomicAdd(&hist[bk[k]], 1u);
       }
     }
@@ -438,9 +407,9 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
         int rib = 0;
         for (int t = b0; t < b1; ++t) rib += skey[ord[t]] < me ? 1 : 0;
         pos[k] = b0 + rib;
-        const int h = hd[i];
-        const int pstart = (int)hist[hbase[h]];
-        mm[k] = (int)hist[hbase[h + 1]] - pstart;
+        const int c0 = (int)(bki[k] & 0xffffu);
+        const int pstart = (int)hist[c0];
+        mm[k] = (int)hist[c0 + (1 << (bki[k] >> 16))] - pstart;
         rr[k] = pos[k] - pstart;
       }
     }
@@ -494,7 +463,7 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
     if (i < nsl) {
-      const int64_t j = lo + i;
+      const int j = i;
       vs[i] = S.vx[j];
       vs[kFMax + i] = S.vy[j];
       vs[2 * kFMax + i] = S.vz[j];
@@ -536,7 +505,7 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
-    const int64_t j = lo + i;
+    const int j = i;
     uint32_t ccell = 0xffffffffu, cq = 0u;
     if (i >= nsl) {
       if (DEP) dsh.st.q[i] = 0xFF;
@@ -546,7 +515,7 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
       int Q = q_of(qs[k]);
       const int s = sp_of(qs[k]);
       const uint8_t ev = advance<R, 0, EXT>(P, T, nullptr, acc, step, id[k], s, Q, x, y, z, vx, vy, vz, S.birth, j,
-                                            chg_cur, u[k]);
+                                            lo + j, chg_cur, u[k]);
       S.x[j] = x;
       S.y[j] = y;
       S.z[j] = z;
@@ -564,8 +533,76 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
     }
     if (EXT && chg_next) add_charge(chg_next, ccell, cq);
   }
-  // 7. deposit
-  if (DEP) deposit_staged<R, DEP == 2>(P, dens, dsh, box, mn, mx);
+  // 7. deposit; the lanes' last runs summed within groups of four lanes
+  if (DEP) deposit_staged<R, DEP == 2, 4>(P, dens, dsh, box, mn, mx);
+}
+
+// Once per sort, for every chunk of the fast path: the buckets of each
+// cell of the ordering (2^floor(log2 m) buckets for a cell of m slots,
+// numbered cell after cell from the chunk's first slot), stored per slot as
+// first bucket | log2(bucket count) << 16, and each chunk's bucket total.
+// The cells of a slot range are fixed from one sort to the next; the step
+// kernel only histograms its keys into them.
+__global__ void __launch_bounds__(kFB) k_step_prep(const uint32_t *__restrict__ cellid,
+                                                   const uint32_t *__restrict__ chunk_lo,
+                                                   uint32_t *__restrict__ bkinfo, uint32_t *__restrict__ nbk) {
+  __shared__ uint32_t cell[kFMax + 1];
+  __shared__ uint16_t hd[kFMax], hcell[kFMax + 1];
+  __shared__ uint32_t lead[kFLead], wsum[kFB / 64], nbs[kFMax + 1];
+  const int64_t b = blockIdx.x;
+  const int64_t lo = chunk_lo[b];
+  const int nsl = (int)((int64_t)chunk_lo[b + 1] - lo);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  if (nsl <= 0 || nsl > kFMax) {
+    if (tid == 0) nbk[b] = 0u;
+    return;
+  }
+  for (int i = tid; i < nsl; i += kFB) cell[i] = cellid[lo + i];
+  __syncthreads();
+  // heads of cells (ballots per round and wave, a scan of the counts), the
+  // cell index of every slot, the first slot of every cell
+  uint32_t fl[kFR];
+  uint64_t hb[kFR];
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) {
+    const int i = tid + k * kFB;
+    fl[k] = (i < nsl && (i == 0 || cell[i] != cell[i - 1])) ? 1u : 0u;
+    hb[k] = __ballot(fl[k] != 0u);
+    if (lane == 0) lead[k * (kFB / 64) + wv] = (uint32_t)__popcll(hb[k]);
+  }
+  __syncthreads();
+  const uint32_t hc = lane < kFLead ? lead[lane] : 0u;
+  const uint32_t hincl = wave_incl_scan(hc), hexcl = hincl - hc;
+  const int nheads = __builtin_amdgcn_readlane((int)hincl, kFLead - 1);
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) {
+    const int i = tid + k * kFB;
+    if (i < nsl) {
+      const int h = __builtin_amdgcn_readlane((int)hexcl, k * (kFB / 64) + wvu) + (int)__popcll(hb[k] & below) +
+                    (int)fl[k] - 1;
+      hd[i] = (uint16_t)h;
+      if (fl[k]) hcell[h] = (uint16_t)i;
+    }
+  }
+  if (tid == 0) hcell[nheads] = (uint16_t)nsl;
+  __syncthreads();
+  // buckets per cell: 2^floor(log2(slots of the cell)), at most one per slot
+  for (int h = tid; h < nheads; h += kFB) {
+    const int m = hcell[h + 1] - hcell[h];
+    const int lg = m <= 1 ? 0 : 31 - __clz(m);
+    nbs[h] = 1u << lg;
+  }
+  __syncthreads();
+  const uint32_t total = wg_exscan<kFB>(nbs, nheads, wsum);  // nbs: first bucket of each cell
+  for (int i = tid; i < nsl; i += kFB) {
+    const int h = hd[i];
+    const uint32_t first = nbs[h];
+    const uint32_t cnt = (h + 1 < nheads ? nbs[h + 1] : total) - first;
+    bkinfo[lo + i] = first | ((uint32_t)(31 - __clz(cnt)) << 16);
+  }
+  if (tid == 0) nbk[b] = total;
 }
 
 // chunks of more than kFMax slots, listed once per sort: big[0] = count,
@@ -578,48 +615,53 @@ __global__ void k_big_list(const uint32_t *__restrict__ chunk_lo, int64_t nchunk
 
 int64_t step_nchunks(int64_t n) { return (n + kFCap - 1) / kFCap; }
 
-void launch_big_list(const uint32_t *chunk_lo, int64_t n, uint32_t *big, hipStream_t st) {
+void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, uint32_t *big, uint32_t *bkinfo,
+                      uint32_t *nbk, hipStream_t st) {
   const int64_t nc = step_nchunks(n);
   launch_fill_u32(big, 0u, 1, st);
-  if (nc > 0) hipLaunchKernelGGL(k_big_list, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, chunk_lo, nc, big);
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_big_list, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, chunk_lo, nc, big);
+  hipLaunchKernelGGL(k_step_prep, dim3((unsigned)nc), dim3(kFB), 0, st, cellid, chunk_lo, bkinfo, nbk);
 }
 
 template <typename R, bool EXT>
 static void launch_step_e(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid,
-                          const uint32_t *chunk_lo, const uint32_t *big, uint8_t *evlog, DevAccum *acc, double *dens,
+                          const uint32_t *chunk_lo, const uint32_t *big, const uint32_t *bkinfo, const uint32_t *nbk,
+                          uint8_t *evlog, DevAccum *acc, double *dens,
                           double *moments, uint64_t *scratch64, StepArg step, const uint32_t *chg_cur,
                           uint32_t *chg_next, hipStream_t st) {
   const dim3 g((unsigned)(kBigWG + step_nchunks(P.n))), b(kFB);
   if (!dens)
-    hipLaunchKernelGGL((k_step<R, 0, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, evlog, acc, dens, moments,
-                       scratch64, step, chg_cur, chg_next);
+    hipLaunchKernelGGL((k_step<R, 0, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens,
+                       moments, scratch64, step, chg_cur, chg_next);
   else if ((P.dmask & 7u) == 3u)
-    hipLaunchKernelGGL((k_step<R, 2, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, evlog, acc, dens, moments,
-                       scratch64, step, chg_cur, chg_next);
+    hipLaunchKernelGGL((k_step<R, 2, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens,
+                       moments, scratch64, step, chg_cur, chg_next);
   else
-    hipLaunchKernelGGL((k_step<R, 1, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, evlog, acc, dens, moments,
-                       scratch64, step, chg_cur, chg_next);
+    hipLaunchKernelGGL((k_step<R, 1, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens,
+                       moments, scratch64, step, chg_cur, chg_next);
 }
 
 template <typename R>
 void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
-                 const uint32_t *big, uint8_t *evlog, DevAccum *acc, double *dens, double *moments,
+                 const uint32_t *big, const uint32_t *bkinfo, const uint32_t *nbk, uint8_t *evlog, DevAccum *acc,
+                 double *dens, double *moments,
                  uint64_t *scratch64, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, hipStream_t st) {
   if (P.n <= 0) return;
   const bool ext = chg_cur || chg_next || (P.pmask & (P_HEAT | P_ELASTIC)) || P.nion > 1;
   if (ext)
-    launch_step_e<R, true>(P, T, S, cellid, chunk_lo, big, evlog, acc, dens, moments, scratch64, step, chg_cur,
-                           chg_next, st);
+    launch_step_e<R, true>(P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens, moments, scratch64, step,
+                           chg_cur, chg_next, st);
   else
-    launch_step_e<R, false>(P, T, S, cellid, chunk_lo, big, evlog, acc, dens, moments, scratch64, step, chg_cur,
-                            chg_next, st);
+    launch_step_e<R, false>(P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens, moments, scratch64, step,
+                            chg_cur, chg_next, st);
 }
 
 template void launch_step<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *, const uint32_t *,
-                                  const uint32_t *, uint8_t *, DevAccum *, double *, double *, uint64_t *, StepArg,
-                                  const uint32_t *, uint32_t *, hipStream_t);
+                                  const uint32_t *, const uint32_t *, const uint32_t *, uint8_t *, DevAccum *, double *,
+                                  double *, uint64_t *, StepArg, const uint32_t *, uint32_t *, hipStream_t);
 template void launch_step<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const uint32_t *,
-                                 const uint32_t *, uint8_t *, DevAccum *, double *, double *, uint64_t *, StepArg,
-                                 const uint32_t *, uint32_t *, hipStream_t);
+                                 const uint32_t *, const uint32_t *, const uint32_t *, uint8_t *, DevAccum *, double *,
+                                 double *, uint64_t *, StepArg, const uint32_t *, uint32_t *, hipStream_t);
 
 }  // namespace ecr

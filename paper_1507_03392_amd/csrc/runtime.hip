@@ -35,6 +35,7 @@ struct Layout {
       evlog;
   size_t fchunks;  // chunk table of the fused step kernel
   size_t big;      // its oversized chunks: count, then indices
+  size_t nbk;      // its ordering buckets per chunk (the per-slot ones reuse the sort's rank array)
   size_t scratch64;  // sort space of the pools that exceed the LDS (fused kernel)
   size_t chg[2];  // ion charge per cell, double-buffered (ECR_FLAG_SELF_NE)
   size_t cxreq;   // exchanges per species and collision cell (ECR_FLAG_CX_PARTNER)
@@ -78,6 +79,8 @@ Layout make_layout(const ecr_params *p) {
   L.fchunks = o;
   o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 2));
   L.big = o;
+  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 1));
+  L.nbk = o;
   o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 1));
   L.scratch64 = o;
   o = align_up(o + 8 * N);
@@ -533,7 +536,9 @@ void do_sort(ecr_run *r, const uint32_t *given) {
     if (fused(r)) {
       launch_coul_chunks(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off), r->kp.n,
                          at<uint32_t>(r, r->L.fchunks), kFCap, r->stream);
-      launch_big_list(at<uint32_t>(r, r->L.fchunks), r->kp.n, at<uint32_t>(r, r->L.big), r->stream);
+      // the per-slot buckets go into the sort's rank array, free until the next sort
+      launch_step_prep(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks), r->kp.n,
+                       at<uint32_t>(r, r->L.big), at<uint32_t>(r, r->L.rank), at<uint32_t>(r, r->L.nbk), r->stream);
     }
   }
   r->cur = b;
@@ -562,7 +567,8 @@ void do_step(ecr_run *r, StepArg stepw) {
     {
       ProfScope ps(r, ECR_K_STEP);
       launch_step<R>(r->kp, T, soa<R>(r, r->cur), at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks),
-                     at<uint32_t>(r, r->L.big), (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr,
+                     at<uint32_t>(r, r->L.big), at<uint32_t>(r, r->L.rank), at<uint32_t>(r, r->L.nbk),
+                     (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr,
                      acc, (pm & ECR_P_DEPOSIT) ? at<double>(r, r->L.dens) : nullptr, at<double>(r, r->L.moments),
                      at<uint64_t>(r, r->L.scratch64), stepw, chg_cur, chg_next, r->stream);
     }
