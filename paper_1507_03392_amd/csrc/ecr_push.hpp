@@ -283,20 +283,25 @@ constexpr int kStage = kPad(kTile);
 // unpadded: the push writes one slot per lane (consecutive addresses), and
 // lane l reads its kP consecutive slots back with wide loads, both free of
 // bank conflicts; 31 KB in binary64, so that five workgroups share a CU
-template <typename R>
+// TILE: slots of a staged tile (kP per lane of the workgroup)
+template <typename R, int TILE = kTile>
 struct alignas(16) DepStage {
-  R t[3][kTile];
-  uint16_t c[3][kTile];
-  uint8_t q[kTile];  // charge, or 0xFF: nothing to deposit
+  R t[3][TILE];
+  uint16_t c[3][TILE];
+  uint8_t q[TILE];  // charge, or 0xFF: nothing to deposit
 };
 
 // the brick reuses the staging memory: as many doubles as binary64 staging holds
-constexpr int kDepBrick = (int)(sizeof(DepStage<double>) / sizeof(double));
+template <int TILE>
+constexpr int dep_brick() {
+  return (int)(sizeof(DepStage<double, TILE>) / sizeof(double));
+}
+constexpr int kDepBrick = dep_brick<kTile>();
 
-template <typename R>
+template <typename R, int TILE = kTile>
 union DepShared {
-  DepStage<R> st;
-  double brick[kDepBrick];
+  DepStage<R, TILE> st;
+  double brick[dep_brick<TILE>()];
 };
 
 // kP consecutive staged values of lane l (16-byte aligned: kP = 4)
@@ -389,8 +394,8 @@ __device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, N
 // stage the deposit input of tile slot i (lane = slot layout)
 // NQ: the deposit mask is known to hold exactly the ion number and ion
 // charge fields (the default); the atom-field paths then compile away
-template <typename R, bool NQ>
-__device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R> &st, int i, R x, R y, R z, int q, int mn[3],
+template <typename R, bool NQ, int TILE = kTile>
+__device__ __forceinline__ void stage_cic(const KParams &P, DepStage<R, TILE> &st, int i, R x, R y, R z, int q, int mn[3],
                                           int mx[3]) {
   int ix, iy, iz;
   R tx, ty, tz;
@@ -429,9 +434,10 @@ __device__ __forceinline__ int small_div(int i, int d, float rcp) {
 // deposit a staged tile; every lane of the workgroup must call it.  G: the
 // lanes' last runs are summed within groups of G lanes (G = 64: over the
 // whole wavefront) before the run's last lane in the group flushes them
-template <typename R, bool NQ, int G = 64>
-__device__ __forceinline__ void deposit_staged(const KParams &P, double *__restrict__ dens, DepShared<R> &sh,
+template <typename R, bool NQ, int G = 64, int NT = kBlock>
+__device__ __forceinline__ void deposit_staged(const KParams &P, double *__restrict__ dens, DepShared<R, NT * kP> &sh,
                                                int *box, int mn[3], int mx[3]) {
+  constexpr int kBrickCap = dep_brick<NT * kP>();
   const int tid = threadIdx.x;
   const uint32_t dm = NQ ? 3u : P.dmask;
   constexpr int kFields = NQ ? 2 : 3;  // brick fields
@@ -515,9 +521,9 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
       }
     }
   };
-  if (nodes <= kDepBrick / kFields) {
+  if (nodes <= kBrickCap / kFields) {
     const int nb = (int)nodes;
-    for (int i = tid; i < kFields * nb; i += kBlock) sh.brick[i] = 0.0;
+    for (int i = tid; i < kFields * nb; i += NT) sh.brick[i] = 0.0;
     __syncthreads();
     double *br = sh.brick;
     // corner k of a cell is node base + dx + bx (dy + by dz)
@@ -534,7 +540,7 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
     flush_last(L, to_brick);
     __syncthreads();
     const float rnb = 1.0f / (float)nb, rbx = 1.0f / (float)bx, rby = 1.0f / (float)by;
-    for (int i = tid; i < kFields * nb; i += kBlock) {
+    for (int i = tid; i < kFields * nb; i += NT) {
       const double v = sh.brick[i];
       if (v != 0.0) {
         const int f = small_div(i, nb, rnb), li = i - f * nb;

@@ -3,8 +3,9 @@
 // cell, then the push in the magnetic field, wall / aperture loss,
 // ionisation or charge exchange, and the cloud-in-cell deposit.
 //
-// One workgroup owns a chunk of whole collision cells: the cells whose first
-// sorted slot lies in [b*kFCap, (b+1)*kFCap) (table rebuilt at every sort).
+// One workgroup (four wavefronts) owns a chunk of whole collision cells: the
+// cells whose first sorted slot lies in [b*kFCap, (b+1)*kFCap) (table rebuilt
+// at every sort).
 // Cells never straddle chunks and nothing couples two cells within a step
 // except the density grid and the tallies (atomics), so each chunk is
 // stepped start to finish by its workgroup and the state is read once and
@@ -46,12 +47,16 @@ namespace ecr {
 
 namespace {
 
+// four wavefronts per workgroup (two per workgroup with chunks of 320 slots
+// ran 7% slower at 2M ions: a chunk's 160 pairs leave more lanes idle in the
+// collisions than 384 do)
 constexpr int kFB = 256;                  // lanes per workgroup
 constexpr int kFR = 4;                    // rounds of kFB slots
 constexpr int kFMax = kFB * kFR;          // slots of a chunk on the fast path
 constexpr int kFLead = kFR * (kFB / 64);  // (round, wavefront) entries
 constexpr int kBigWG = 4;                 // handler workgroups of oversized chunks
-static_assert(kFMax == kTile, "the deposit stages one tile: the chunk");
+static_assert(kFR == kP, "the deposit stages one tile of kP slots per lane: the chunk");
+static_assert(kFMax > kFCap, "a chunk fits the fast path unless one of its cells is large");
 static_assert(kFLead <= 64, "per-wave counts fit one wavefront");
 
 // LDS layout in bytes.  Ordering (steps 1-2): skey, the bucket histogram,
@@ -78,8 +83,8 @@ constexpr int sqs_off() {
 }
 template <typename R>
 constexpr int lds_bytes() {
-  return align16(sqs_off<R>() + kFMax > (int)sizeof(DepShared<R>) ? sqs_off<R>() + kFMax
-                                                                  : (int)sizeof(DepShared<R>));
+  return align16(sqs_off<R>() + kFMax > (int)sizeof(DepShared<R, kFMax>) ? sqs_off<R>() + kFMax
+                                                                         : (int)sizeof(DepShared<R, kFMax>));
 }
 
 // velocities and charges of the chunk's slots in LDS
@@ -119,7 +124,7 @@ __device__ __forceinline__ uint32_t wg_sum_u32(uint32_t v, uint32_t *red) {
   return s;
 }
 
-// push + wall/aperture + MCC + deposit of slots [t0, min(t0 + kTile, hi)),
+// push + wall/aperture + MCC + deposit of slots [t0, min(t0 + kFMax, hi)),
 // lane = slot, every value loaded from global memory and the uniform drawn
 // here (the oversized chunks' path)
 template <typename R, int DEP, bool EXT>
@@ -127,12 +132,12 @@ __device__ __forceinline__ void push_tile_global(const KParams &P, const Tables 
                                                  uint8_t *__restrict__ evlog, DevAccum *__restrict__ acc,
                                                  double *__restrict__ dens, uint32_t step,
                                                  const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next,
-                                                 int64_t t0, int64_t hi, DepShared<R> &dsh, int *box) {
+                                                 int64_t t0, int64_t hi, DepShared<R, kFMax> &dsh, int *box) {
   if (DEP) box_init(box);
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
 #pragma unroll
   for (int p = 0; p < kP; ++p) {
-    const int i = threadIdx.x + p * kBlock;
+    const int i = threadIdx.x + p * kFB;
     const int64_t j = t0 + i;
     uint32_t ccell = 0xffffffffu, cq = 0u;
     if (j >= hi) {
@@ -164,11 +169,11 @@ __device__ __forceinline__ void push_tile_global(const KParams &P, const Tables 
         ccell = Q >= 1 ? c : (uint32_t)(1 + s) * P.ncell + c;
         cq = Q >= 1 ? (uint32_t)Q : 1u;
       }
-      if (DEP) stage_cic<R, DEP == 2>(P, dsh.st, i, x, y, z, Q, mn, mx);
+      if (DEP) stage_cic<R, DEP == 2, kFMax>(P, dsh.st, i, x, y, z, Q, mn, mx);
     }
     if (EXT && chg_next) add_charge(chg_next, ccell, cq);
   }
-  if (DEP) deposit_staged<R, DEP == 2>(P, dens, dsh, box, mn, mx);
+  if (DEP) deposit_staged<R, DEP == 2, 4, kFB>(P, dens, dsh, box, mn, mx);
 }
 
 // an oversized chunk [lo, hi), chunk index b, by one workgroup
@@ -179,7 +184,8 @@ __device__ void big_chunk(const KParams &P, const Tables *__restrict__ T, Soa<R>
                           uint32_t step, const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next,
                           unsigned char *lds, int *box, uint32_t *red, uint32_t *gcount) {
   const int tid = threadIdx.x;
-  constexpr int kBigLds = lds_bytes<R>() / 8 >= 4096 ? 4096 : 2048;  // (key, slot) values the LDS holds
+  // (key, slot) values the LDS holds: the largest power of two that fits
+  constexpr int kBigLds = lds_bytes<R>() / 8 >= 4096 ? 4096 : (lds_bytes<R>() / 8 >= 2048 ? 2048 : 1024);
   static_assert(kBigLds * 8 <= lds_bytes<R>(), "LDS sort buffer");
   double cacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (P.pmask & P_COULOMB) {
@@ -270,8 +276,8 @@ __device__ void big_chunk(const KParams &P, const Tables *__restrict__ T, Soa<R>
     }
     flush_moments(cacc, moments + (b * (kFB / 64) + (tid >> 6)) * 5);
   }
-  DepShared<R> &dsh = *reinterpret_cast<DepShared<R> *>(lds);
-  for (int64_t t0 = lo; t0 < hi; t0 += kTile) {
+  DepShared<R, kFMax> &dsh = *reinterpret_cast<DepShared<R, kFMax> *>(lds);
+  for (int64_t t0 = lo; t0 < hi; t0 += kFMax) {
     push_tile_global<R, DEP, EXT>(P, T, S, evlog, acc, dens, step, chg_cur, chg_next, t0, hi, dsh, box);
     __syncthreads();  // the brick is read before the next tile stages over it
   }
@@ -496,9 +502,10 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
   // velocity, and the same lane reads the one before it writes the other,
   // so the velocities need no copy; the staged cells and charges lie over
   // the work items and ids, dead after the collisions
-  static_assert(offsetof(DepStage<R>, t) == 0 && sizeof(DepStage<R>::t) == 3 * kFMax * sizeof(R),
+  using Stage = DepStage<R, kFMax>;
+  static_assert(offsetof(Stage, t) == 0 && sizeof(Stage::t) == 3 * kFMax * sizeof(R),
                 "the staged offsets overlay the velocities slot by slot");
-  DepShared<R> &dsh = *reinterpret_cast<DepShared<R> *>(lds);
+  DepShared<R, kFMax> &dsh = *reinterpret_cast<DepShared<R, kFMax> *>(lds);
   __syncthreads();  // collisions done (the staged cells go over the items)
   if (DEP) box_init(box);
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
@@ -529,12 +536,12 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
         ccell = Q >= 1 ? c : (uint32_t)(1 + s) * P.ncell + c;
         cq = Q >= 1 ? (uint32_t)Q : 1u;
       }
-      if (DEP) stage_cic<R, DEP == 2>(P, dsh.st, i, x, y, z, Q, mn, mx);
+      if (DEP) stage_cic<R, DEP == 2, kFMax>(P, dsh.st, i, x, y, z, Q, mn, mx);
     }
     if (EXT && chg_next) add_charge(chg_next, ccell, cq);
   }
   // 7. deposit; the lanes' last runs summed within groups of four lanes
-  if (DEP) deposit_staged<R, DEP == 2, 4>(P, dens, dsh, box, mn, mx);
+  if (DEP) deposit_staged<R, DEP == 2, 4, kFB>(P, dens, dsh, box, mn, mx);
 }
 
 // Once per sort, for every chunk of the fast path: the buckets of each
