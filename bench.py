@@ -91,10 +91,14 @@ ALG_BYTES_FP32 = {
 
 
 def kernel_sources_sha256():
-    """Hash of the sources of the fused push kernel (what the traffic counters measured)."""
+    """Hash of every kernel source and the boundary header (what the traffic
+    counters measured): any change to them voids a committed summary."""
     h = hashlib.sha256()
-    for f in ("k_particles.hip", "ecr_device.hpp", "ecr_kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_1507_03392_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1507_03392_amd", "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    for path in [os.path.join(csrc, f) for f in files] + [os.path.join(ROOT, "include", "ecrpic.h")]:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
             h.update(fh.read())
     return h.hexdigest()
 
@@ -279,6 +283,8 @@ def main():
                     help="every charge exchange takes its electron from a tracked atom of the cell (implies --self-n0)")
     ap.add_argument("--self-n0", action="store_true",
                     help="neutral gas of charge exchange and elastic scattering from the tracked atoms per cell")
+    ap.add_argument("--pressure", action="store_true",
+                    help="also deposit the ion pressure moment (its own kernel after the step)")
     ap.add_argument("--heat", action="store_true",
                     help="add the electron-ion heating kick (diamagnetic bias with --self-ne)")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
@@ -323,6 +329,8 @@ def main():
         params["self_ne"] = True
     if args.heat:
         params["process_mask"] |= ecr.P_HEAT
+    if args.pressure:
+        params["deposit_mask"] |= 1 << W.F_ION_P
     if args.self_n0 or args.cx_partner:
         params["self_n0"] = True
     if args.cx_partner:
@@ -394,7 +402,7 @@ def main():
     step_frac = step_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS
     # the counters were taken on the default step (fixed electron background,
     # no optional physics, fused deposit): another configuration runs other code
-    default_step = not (args.self_ne or args.heat or args.split or args.self_n0 or args.cx_partner)
+    default_step = not (args.self_ne or args.heat or args.split or args.self_n0 or args.cx_partner or args.pressure)
     traffic = measured_traffic(args.workload, dom) if default_step else None
 
     drift = None

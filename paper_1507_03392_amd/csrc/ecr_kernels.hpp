@@ -113,6 +113,46 @@ void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *ce
                  double *dens, double *moments, uint64_t *scratch64, StepArg step, const uint32_t *chg_cur,
                  uint32_t *chg_next, hipStream_t st);
 
+// Batched step: one launch steps several runs (each a default step: fused
+// kernel, ion number and charge deposited, no optional physics).  A run's
+// arguments sit in its job in device memory (written by launch_set_job,
+// passed by value); the launch's list names each job, its step and its
+// first workgroup (run j owns step_batch_wgs(n_j) workgroups from wg0[j]).
+template <typename R>
+struct StepJob {
+  KParams P;
+  const Tables *T;
+  Soa<R> S;
+  const uint32_t *cellid, *chunk_lo, *big, *bkinfo, *nbk;
+  uint8_t *evlog;
+  DevAccum *acc;
+  double *dens, *moments;
+  uint64_t *scratch64;
+};
+constexpr int kMaxBatch = 32;
+template <typename R>
+struct StepBatch {
+  const StepJob<R> *job[kMaxBatch];
+  const uint32_t *stepw[kMaxBatch];  // step = *stepw + step, or step alone when stepw is null
+  uint32_t step[kMaxBatch];
+  uint32_t wg0[kMaxBatch + 1];
+  int n;
+};
+// a few 32-bit words set from the launch's arguments (the step counters
+// read by captured graphs)
+struct SetWords {
+  uint32_t *ptr[kMaxBatch];
+  uint32_t val[kMaxBatch];
+  int n;
+};
+bool step_batchable(const KParams &P, bool dens, bool grids);
+uint32_t step_batch_wgs(int64_t n);
+template <typename R>
+void launch_step_batch(const StepBatch<R> &B, hipStream_t st);
+template <typename R>
+void launch_set_job(const StepJob<R> &J, StepJob<R> *dst, hipStream_t st);
+void launch_set_words(const SetWords &w, hipStream_t st);
+
 // sort by cell: keys either from positions or (given != nullptr) from given[pid]
 template <typename R>
 void launch_sort(const KParams &P, Soa<R> A, Soa<R> B, const uint32_t *given, uint32_t *key, uint32_t *rank,

@@ -178,7 +178,7 @@ __device__ __forceinline__ void push_tile_global(const KParams &P, const Tables 
 
 // an oversized chunk [lo, hi), chunk index b, by one workgroup
 template <typename R, int DEP, bool EXT>
-__device__ void big_chunk(const KParams &P, const Tables *__restrict__ T, Soa<R> S, const uint32_t *__restrict__ cellid,
+__device__ __forceinline__ void big_chunk(const KParams &P, const Tables *__restrict__ T, Soa<R> S, const uint32_t *__restrict__ cellid,
                           int64_t lo, int64_t hi, int64_t b, uint8_t *__restrict__ evlog, DevAccum *__restrict__ acc,
                           double *__restrict__ dens, double *__restrict__ moments, uint64_t *__restrict__ scratch64,
                           uint32_t step, const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next,
@@ -285,26 +285,26 @@ __device__ void big_chunk(const KParams &P, const Tables *__restrict__ T, Soa<R>
 
 }  // namespace
 
+// workgroup wg of one run's step: wg < kBigWG handles the oversized chunks,
+// wg = kBigWG + b steps chunk b
 template <typename R, int DEP, bool EXT>
-__global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k_step(KParams P, const Tables *__restrict__ T, Soa<R> S,
-                                              const uint32_t *__restrict__ cellid,
-                                              const uint32_t *__restrict__ chunk_lo,
-                                              const uint32_t *__restrict__ big,
-                                              const uint32_t *__restrict__ bkinfo,
-                                              const uint32_t *__restrict__ nbk, uint8_t *__restrict__ evlog,
-                                              DevAccum *__restrict__ acc, double *__restrict__ dens,
-                                              double *__restrict__ moments, uint64_t *__restrict__ scratch64,
-                                              StepArg sa, const uint32_t *__restrict__ chg_cur,
-                                              uint32_t *__restrict__ chg_next) {
+__device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restrict__ T, Soa<R> S,
+                                        const uint32_t *__restrict__ cellid, const uint32_t *__restrict__ chunk_lo,
+                                        const uint32_t *__restrict__ big, const uint32_t *__restrict__ bkinfo,
+                                        const uint32_t *__restrict__ nbk, uint8_t *__restrict__ evlog,
+                                        DevAccum *__restrict__ acc, double *__restrict__ dens,
+                                        double *__restrict__ moments, uint64_t *__restrict__ scratch64, StepArg sa,
+                                        const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next,
+                                        const uint32_t wg) {
   __shared__ __align__(16) unsigned char lds[lds_bytes<R>()];
   __shared__ uint32_t lead[kFLead], wsum[kFB / 64];
   __shared__ int box[6];
   const uint32_t step = sa.get();
   const int tid = threadIdx.x;
-  if (blockIdx.x < (unsigned)kBigWG) {
+  if (wg < (unsigned)kBigWG) {
     __shared__ uint32_t gcount;
     const uint32_t nbig = big[0];
-    for (uint32_t e = blockIdx.x; e < nbig; e += kBigWG) {
+    for (uint32_t e = wg; e < nbig; e += kBigWG) {
       const uint32_t b = big[1 + e];
       big_chunk<R, DEP, EXT>(P, T, S, cellid, chunk_lo[b], chunk_lo[b + 1], b, evlog, acc, dens, moments, scratch64,
                              step, chg_cur, chg_next, lds, box, wsum, &gcount);
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
     }
     return;
   }
-  const int64_t b = (int64_t)blockIdx.x - kBigWG;
+  const int64_t b = (int64_t)wg - kBigWG;
   const int64_t lo = chunk_lo[b];
   const int nsl = (int)((int64_t)chunk_lo[b + 1] - lo);
   if (nsl <= 0 || nsl > kFMax) return;  // empty, or an oversized chunk (taken by a handler)
@@ -544,6 +544,40 @@ __global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k
   if (DEP) deposit_staged<R, DEP == 2, 4, kFB>(P, dens, dsh, box, mn, mx);
 }
 
+template <typename R, int DEP, bool EXT>
+__global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4)))
+k_step(KParams P, const Tables *__restrict__ T, Soa<R> S, const uint32_t *__restrict__ cellid,
+       const uint32_t *__restrict__ chunk_lo, const uint32_t *__restrict__ big, const uint32_t *__restrict__ bkinfo,
+       const uint32_t *__restrict__ nbk, uint8_t *__restrict__ evlog, DevAccum *__restrict__ acc,
+       double *__restrict__ dens, double *__restrict__ moments, uint64_t *__restrict__ scratch64, StepArg sa,
+       const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next) {
+  step_wg<R, DEP, EXT>(P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens, moments, scratch64, sa, chg_cur,
+                       chg_next, blockIdx.x);
+}
+
+// one step of several runs in one launch: run j owns workgroups
+// [wg0[j], wg0[j+1]) and reads its arguments from its job in device memory
+template <typename R>
+__global__ void __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(4))) k_step_batch(StepBatch<R> B) {
+  const uint32_t wg = blockIdx.x;
+  int j = 0;
+  for (int t = 1; t < B.n; ++t) j = wg >= B.wg0[t] ? t : j;
+  const StepJob<R> *__restrict__ J = B.job[j];
+  step_wg<R, 2, false>(J->P, J->T, J->S, J->cellid, J->chunk_lo, J->big, J->bkinfo, J->nbk, J->evlog, J->acc,
+                       J->dens, J->moments, J->scratch64, StepArg{B.stepw[j], B.step[j]}, nullptr, nullptr,
+                       wg - B.wg0[j]);
+}
+
+// a run's job, passed by value, into device memory (one lane writes it)
+template <typename R>
+__global__ void k_set_job(StepJob<R> J, StepJob<R> *__restrict__ dst) {
+  if (threadIdx.x == 0) *dst = J;
+}
+
+__global__ void k_set_words(SetWords w) {
+  if ((int)threadIdx.x < w.n) *w.ptr[threadIdx.x] = w.val[threadIdx.x];
+}
+
 // Once per sort, for every chunk of the fast path: the buckets of each
 // cell of the ordering (2^floor(log2 m) buckets for a cell of m slots,
 // numbered cell after cell from the chunk's first slot), stored per slot as
@@ -663,6 +697,32 @@ void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *ce
     launch_step_e<R, false>(P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens, moments, scratch64, step,
                             chg_cur, chg_next, st);
 }
+
+bool step_batchable(const KParams &P, bool dens, bool grids) {
+  return P.n > 0 && dens && (P.dmask & 7u) == 3u && !grids && !(P.pmask & (P_HEAT | P_ELASTIC)) && P.nion <= 1;
+}
+
+template <typename R>
+void launch_step_batch(const StepBatch<R> &B, hipStream_t st) {
+  if (B.n <= 0 || B.wg0[B.n] == 0) return;
+  hipLaunchKernelGGL((k_step_batch<R>), dim3(B.wg0[B.n]), dim3(kFB), 0, st, B);
+}
+
+uint32_t step_batch_wgs(int64_t n) { return (uint32_t)(kBigWG + step_nchunks(n)); }
+
+template <typename R>
+void launch_set_job(const StepJob<R> &J, StepJob<R> *dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_set_job<R>), dim3(1), dim3(64), 0, st, J, dst);
+}
+
+void launch_set_words(const SetWords &w, hipStream_t st) {
+  if (w.n > 0) hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, w);
+}
+
+template void launch_step_batch<double>(const StepBatch<double> &, hipStream_t);
+template void launch_step_batch<float>(const StepBatch<float> &, hipStream_t);
+template void launch_set_job<double>(const StepJob<double> &, StepJob<double> *, hipStream_t);
+template void launch_set_job<float>(const StepJob<float> &, StepJob<float> *, hipStream_t);
 
 template void launch_step<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *, const uint32_t *,
                                   const uint32_t *, const uint32_t *, const uint32_t *, uint8_t *, DevAccum *, double *,

@@ -13,6 +13,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -31,8 +33,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t soa[2][9];  // offsets of x y z vx vy vz qs pid birth in buffer A and B
-  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, efield, bfield,
-      evlog;
+  size_t key, rank, cellid, chunks, pairs, tris, moments, count, cell_off, bsum, dens, acc, tables, stepc, job, efield,
+      bfield, evlog;
   size_t fchunks;  // chunk table of the fused step kernel
   size_t big;      // its oversized chunks: count, then indices
   size_t nbk;      // its ordering buckets per chunk (the per-slot ones reuse the sort's rank array)
@@ -104,6 +106,8 @@ Layout make_layout(const ecr_params *p) {
   o = align_up(o + sizeof(Tables));
   L.stepc = o;
   o = align_up(o + 4);
+  L.job = o;  // the batched step's two jobs (one per SoA buffer)
+  o = align_up(o + 2 * sizeof(StepJob<double>));
   L.efield = o;
   if (p->efield_nodes) o = align_up(o + 8 * 3 * (size_t)nnodes(p));
   L.bfield = o;
@@ -251,6 +255,7 @@ struct ecr_run {
   // and handle of its device; ecr_destroy releases them instead of freeing
   bool is_static = false;
   bool live = false;
+  uint64_t uid = 0;  // unique over the process: names the run in the batched graphs
 };
 
 namespace {
@@ -628,6 +633,150 @@ void step_tail(ecr_run *r, StepArg stepw, bool grids) {
   r->steps++;
 }
 
+// ---------------------------------------------------------------------------
+// Batched stepping: the default steps of several runs on one stream in one
+// launch per step (k_step_batch), each run's arguments read from its job in
+// its own arena.  The jobs of both SoA buffers are written once, at init.
+// ---------------------------------------------------------------------------
+template <typename R>
+StepJob<R> make_job(ecr_run *r, int b) {
+  StepJob<R> J;
+  J.P = r->kp;
+  J.T = at<Tables>(r, r->L.tables);
+  J.S = soa<R>(r, b);
+  J.cellid = at<uint32_t>(r, r->L.cellid);
+  J.chunk_lo = at<uint32_t>(r, r->L.fchunks);
+  J.big = at<uint32_t>(r, r->L.big);
+  J.bkinfo = at<uint32_t>(r, r->L.rank);
+  J.nbk = at<uint32_t>(r, r->L.nbk);
+  J.evlog = (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr;
+  J.acc = at<DevAccum>(r, r->L.acc);
+  J.dens = at<double>(r, r->L.dens);
+  J.moments = at<double>(r, r->L.moments);
+  J.scratch64 = at<uint64_t>(r, r->L.scratch64);
+  return J;
+}
+
+template <typename R>
+void write_jobs(ecr_run *r) {
+  for (int b = 0; b < 2; ++b) launch_set_job<R>(make_job<R>(r, b), at<StepJob<R>>(r, r->L.job) + b, r->stream);
+}
+
+// a run whose step the batched kernel can take: the default fused step
+bool batchable(const ecr_run *r) {
+  const bool grids = (r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0)) != 0;
+  return fused(r) && !r->prof && step_batchable(r->kp, (r->p.process_mask & ECR_P_DEPOSIT) != 0, grids);
+}
+
+// one step of the batchable runs rs (all of precision R), step numbers sa:
+// each run's sort when due, one launch per kMaxBatch runs, then each run's tail
+template <typename R>
+void batch_step(const std::vector<ecr_run *> &rs, const std::vector<StepArg> &sa, hipStream_t st) {
+  for (ecr_run *r : rs)
+    if (r->need_sort || r->step % r->p.sort_every == 0) {
+      do_sort<R>(r, nullptr);
+      r->need_sort = false;
+    }
+  for (size_t k0 = 0; k0 < rs.size(); k0 += kMaxBatch) {
+    StepBatch<R> B{};
+    B.n = (int)std::min(rs.size() - k0, (size_t)kMaxBatch);
+    B.wg0[0] = 0;
+    for (int j = 0; j < B.n; ++j) {
+      ecr_run *r = rs[k0 + j];
+      B.job[j] = at<StepJob<R>>(r, r->L.job) + r->cur;
+      B.stepw[j] = sa[k0 + j].base;
+      B.step[j] = sa[k0 + j].off;
+      B.wg0[j + 1] = B.wg0[j] + step_batch_wgs(r->kp.n);
+    }
+    launch_step_batch<R>(B, st);
+  }
+  for (size_t k = 0; k < rs.size(); ++k) step_tail<R>(rs[k], sa[k], false);
+}
+
+// one step of every run of a batch; base: each run's step counter word in
+// a captured graph (offset off), else the host's counters
+void batch_step_all(const std::vector<ecr_run *> &runs, hipStream_t st, bool captured, uint32_t off) {
+  std::vector<ecr_run *> bd, bf;
+  std::vector<StepArg> sd, sf;
+  for (ecr_run *r : runs) {
+    const StepArg a = captured ? StepArg{at<uint32_t>(r, r->L.stepc), off} : StepArg{nullptr, (uint32_t)r->step};
+    if (!batchable(r)) {
+      if (r->fp32) do_step<float>(r, a);
+      else do_step<double>(r, a);
+    } else if (r->fp32) {
+      bf.push_back(r);
+      sf.push_back(a);
+    } else {
+      bd.push_back(r);
+      sd.push_back(a);
+    }
+  }
+  if (!bd.empty()) batch_step<double>(bd, sd, st);
+  if (!bf.empty()) batch_step<float>(bf, sf, st);
+}
+
+// sort periods of a set of runs captured as one graph, keyed by the runs'
+// ids and the buffers they start from; kept until one of the runs is
+// destroyed (or the cache is full)
+struct BatchGraph {
+  hipStream_t stream;
+  std::vector<uint64_t> key;
+  hipGraphExec_t ge;
+};
+std::mutex g_bgraph_mu;
+std::vector<BatchGraph> g_bgraphs;
+constexpr size_t kMaxBatchGraphs = 16;
+
+std::vector<uint64_t> batch_key(const std::vector<ecr_run *> &runs) {
+  std::vector<uint64_t> k;
+  for (ecr_run *r : runs) k.push_back(r->uid << 2 | (uint64_t)r->cur << 1 | (uint64_t)r->chg_par);
+  return k;
+}
+
+hipError_t capture_batch_period(const std::vector<ecr_run *> &runs, hipStream_t st, int64_t K, hipGraphExec_t *out) {
+  struct Saved {
+    int64_t step, steps, dens;
+    int cur, par;
+    bool need;
+  };
+  std::vector<Saved> sv;
+  for (ecr_run *r : runs) sv.push_back({r->step, r->steps, r->dens_steps, r->cur, r->chg_par, r->need_sort});
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  for (int64_t i = 0; i < K; ++i) batch_step_all(runs, st, true, (uint32_t)i);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(st, &g);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  for (size_t k = 0; k < runs.size(); ++k) {
+    ecr_run *r = runs[k];
+    r->step = sv[k].step;
+    r->steps = sv[k].steps;
+    r->dens_steps = sv[k].dens;
+    r->cur = sv[k].cur;
+    r->chg_par = sv[k].par;
+    r->need_sort = sv[k].need;
+  }
+  return e;
+}
+
+// drop the batched graphs that hold run r (its stream synchronised first)
+void forget_batch_graphs(const ecr_run *r) {
+  std::lock_guard<std::mutex> lock(g_bgraph_mu);
+  for (size_t i = 0; i < g_bgraphs.size();) {
+    bool has = false;
+    for (uint64_t k : g_bgraphs[i].key) has |= (k >> 2) == r->uid;
+    if (has) {
+      (void)hipStreamSynchronize(g_bgraphs[i].stream);
+      (void)hipGraphExecDestroy(g_bgraphs[i].ge);
+      g_bgraphs.erase(g_bgraphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
 // ion charge and atoms per cell of the state just set (ECR_FLAG_SELF_NE,
 // ECR_FLAG_SELF_N0)
 void build_charge_grid(ecr_run *r) {
@@ -746,6 +895,7 @@ namespace {
 
 // release what a run holds besides its arena: events and captured graphs
 void release_run(ecr_run *r) {
+  forget_batch_graphs(r);
   harvest(r);
   for (auto e : r->free_events) (void)hipEventDestroy(e);
   r->free_events.clear();
@@ -799,6 +949,10 @@ ecr_status init_run(ecr_run *r, const ecr_params *params, const Layout &L, const
   r->kp.bden = needs_bden(params) ? at<double>(r, L.bden) : nullptr;
   if (r->kp.bden) launch_cell_bden(r->kp, at<double>(r, L.bden), r->stream);
   zero_accumulators(r);
+  static std::atomic<uint64_t> next_uid{1};
+  r->uid = next_uid++;
+  if (r->fp32) write_jobs<float>(r);
+  else write_jobs<double>(r);
   return ECR_OK;
 }
 
@@ -993,18 +1147,75 @@ ecr_status ecr_step_graph(ecr_run *r, int64_t n_steps) {
 
 ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps, void *hip_stream) {
   if (!runs || n_runs < 0 || n_steps < 0) return fail(nullptr, ECR_EINVAL, "bad batch arguments");
-  for (int32_t k = 0; k < n_runs; ++k)
-    if (!runs[k] || runs[k]->failed || !runs[k]->initialized || runs[k]->stream != (hipStream_t)hip_stream)
-      return fail(nullptr, ECR_EINVAL, "every run must be initialised and bound to the batch stream");
-  for (int64_t i = 0; i < n_steps; ++i)
-    for (int32_t k = 0; k < n_runs; ++k) {
-      ecr_run *r = runs[k];
-      if (r->fp32) do_step<float>(r, StepArg{nullptr, (uint32_t)r->step});
-      else do_step<double>(r, StepArg{nullptr, (uint32_t)r->step});
-    }
+  const hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<ecr_run *> rs;
   for (int32_t k = 0; k < n_runs; ++k) {
-    const ecr_status st = check_hip(runs[k], hipGetLastError(), "batch step launch");
-    if (st != ECR_OK) return st;
+    ecr_run *r = runs[k];
+    if (!r || r->failed || !r->initialized || r->stream != st)
+      return fail(nullptr, ECR_EINVAL, "every run must be initialised and bound to the batch stream");
+    for (ecr_run *q : rs)
+      if (q == r) return fail(nullptr, ECR_EINVAL, "a run appears twice in the batch");
+    rs.push_back(r);
+  }
+  if (rs.empty()) return ECR_OK;
+  const int64_t K = rs[0]->p.sort_every;
+  while (n_steps > 0) {
+    bool aligned = st != nullptr && n_steps >= K;
+    for (ecr_run *r : rs)
+      aligned = aligned && r->p.sort_every == K && r->step % K == 0 && !r->prof && r->step + K <= 0xffffffffLL;
+    if (!aligned) {
+      // not at the start of a common sort period: one step, batched launches
+      batch_step_all(rs, st, false, 0u);
+      for (ecr_run *r : rs) {
+        const ecr_status s2 = check_hip(r, hipGetLastError(), "batch step launch");
+        if (s2 != ECR_OK) return s2;
+      }
+      --n_steps;
+      continue;
+    }
+    const std::vector<uint64_t> key = batch_key(rs);
+    hipGraphExec_t ge = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(g_bgraph_mu);
+      for (const BatchGraph &g : g_bgraphs)
+        if (g.stream == st && g.key == key) ge = g.ge;
+    }
+    if (!ge) {
+      const hipError_t e = capture_batch_period(rs, st, K, &ge);
+      if (e != hipSuccess) return check_hip(rs[0], e, "batch graph capture");
+      std::lock_guard<std::mutex> lock(g_bgraph_mu);
+      if (g_bgraphs.size() >= kMaxBatchGraphs) {
+        (void)hipStreamSynchronize(g_bgraphs.front().stream);
+        (void)hipGraphExecDestroy(g_bgraphs.front().ge);
+        g_bgraphs.erase(g_bgraphs.begin());
+      }
+      g_bgraphs.push_back({st, key, ge});
+    }
+    // every run's first step of the period into its counter word, then the period
+    for (size_t k0 = 0; k0 < rs.size(); k0 += kMaxBatch) {
+      SetWords w{};
+      w.n = (int)std::min(rs.size() - k0, (size_t)kMaxBatch);
+      for (int j = 0; j < w.n; ++j) {
+        w.ptr[j] = at<uint32_t>(rs[k0 + j], rs[k0 + j]->L.stepc);
+        w.val[j] = (uint32_t)rs[k0 + j]->step;
+      }
+      launch_set_words(w, st);
+    }
+    const hipError_t e = hipGraphLaunch(ge, st);
+    if (e != hipSuccess) return check_hip(rs[0], e, "batch graph launch");
+    for (ecr_run *r : rs) {
+      r->step += K;
+      r->steps += K;
+      if (r->p.process_mask & ECR_P_DEPOSIT) r->dens_steps += K;
+      r->cur = 1 - r->cur;
+      if ((r->p.flags & (ECR_FLAG_SELF_NE | ECR_FLAG_SELF_N0)) && (K & 1)) r->chg_par = 1 - r->chg_par;
+      r->need_sort = false;
+    }
+    n_steps -= K;
+  }
+  for (ecr_run *r : rs) {
+    const ecr_status s2 = check_hip(r, hipGetLastError(), "batch step");
+    if (s2 != ECR_OK) return s2;
   }
   return ECR_OK;
 }

@@ -661,6 +661,64 @@ def test_step_batch_matches_separate_steps():
         assert_tallies_equal(r.tallies(), alone.tallies(), "batch vs alone")
 
 
+def test_step_batch_replays_sort_periods_of_mixed_runs():
+    # runs at the start of a common sort period are advanced a period at a
+    # time by one captured graph in which every batchable run's step is one
+    # shared launch (binary64 and binary32 runs in launches of their own
+    # precision; a run with self-consistent electrons keeps its own kernels);
+    # the graphs are reused on later periods and forgotten when a run is
+    # destroyed.  Each run ends bit for bit where it ends stepped alone.
+    import torch
+
+    import paper_1507_03392_amd as ecr
+    stream = torch.cuda.Stream()
+    cases = []
+    for i, (n, q, extra) in enumerate(((3_001, 3, {}), (20_011, 8, {"precision": W.PREC_FP32}),
+                                       (4_099, 4, {"self_ne": True}), (700, 1, {}), (61_001, 6, {}))):
+        p = boosted(W.base_params(n, 16, 16, 32, seed=60 + i))
+        p.update(process_mask=W.P_ALL, sort_every=7, **extra)
+        cases.append((p, W.random_state(p, seed=70 + i, q_max=q, v_ev=30.0)))
+
+    def batch(runs, calls):
+        for k in calls:
+            ecr.step_batch(runs, k, stream)
+        stream.synchronize()
+
+    def check(case_runs, steps, step0):
+        for (p, st), r in case_runs:
+            alone = gpu_run(p, events=True)
+            alone.set_state(st, step=step0)
+            alone.step(steps)
+            a, b = r.get_state(), alone.get_state()
+            for k in ("x", "y", "z", "vx", "vy", "vz", "q", "cell", "birth"):
+                assert np.array_equal(a[k], b[k]), (p["n"], k)
+            assert a["step"] == b["step"] == step0 + steps
+            assert np.array_equal(r.events(), alone.events())
+            assert_tallies_equal(r.tallies(), alone.tallies(), "batch vs alone")
+            da, db = r.density(W.F_ION_Q)[0], alone.density(W.F_ION_Q)[0]
+            assert np.allclose(da, db, rtol=0, atol=1e-12 * max(1.0, np.abs(db).max()))
+
+    runs = []
+    for p, st in cases:
+        r = gpu_run(p, events=True, stream=stream)
+        r.set_state(st, step=14)
+        runs.append(r)
+    # 4 whole periods (two graphs, each replayed once), then 5 single steps
+    batch(runs, (30, 3))
+    check(list(zip(cases, runs)), 33, 14)
+    # a run leaves and another joins: the new set's graphs, not the old ones
+    runs[1].close()
+    p, st = cases[1]
+    r = gpu_run(p, events=True, stream=stream)
+    r.set_state(st, step=40)
+    r.step(7)
+    stream.synchronize()
+    # all at step 47: two single steps, one period as a graph, five single steps
+    batch([runs[0], r, runs[3]], (14,))
+    check([(cases[0], runs[0]), (cases[3], runs[3])], 33 + 14, 14)
+    check([((p, st), r)], 21, 40)
+
+
 def test_exchange_partners_in_a_chunk_beyond_the_lds():
     # a cell of 5000 atoms (more slots than the exchange-partner kernel
     # stages in LDS) whose ions exchange charge: the partners are picked
