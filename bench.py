@@ -204,16 +204,17 @@ def serve_bench(args):
     from paper_1507_03392_amd.serve import Request, Server, summary
 
     prec = W.PREC_FP64 if args.fp64 else W.PREC_FP32
-    trace = W.c5_trace(precision=prec)
+    trace = W.c5_trace(precision=prec, rate_hz=args.rate, n_hi=args.n_hi)
     reqs = [Request(rid=i, arrival=a, params=p, steps=st) for i, (a, p, st) in enumerate(trace)]
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
     # warm-up: two small requests (code objects, graph capture path)
     warm = [Request(rid=i, arrival=0.0, params=W.with_(trace[i][1], n=20_000), steps=100) for i in range(2)]
-    Server(hbm_budget=budget, max_active=args.slots).serve(warm)
+    Server(hbm_budget=budget, max_active=args.slots, batch_max_n=args.batch_max_n).serve(warm)
     torch.cuda.synchronize()
-    log(f"bench: serving {len(reqs)} requests, {args.slots} slots, HBM budget {budget / 2**30:.1f} GiB")
-    srv = Server(hbm_budget=budget, max_active=args.slots)
+    log(f"bench: serving {len(reqs)} requests at {args.rate:g}/s, {args.slots} slots, batch of runs up to "
+        f"{args.batch_max_n} particles, HBM budget {budget / 2**30:.1f} GiB")
+    srv = Server(hbm_budget=budget, max_active=args.slots, batch_max_n=args.batch_max_n)
     res = srv.serve(reqs)
     torch.cuda.synchronize()
     s = summary(res)
@@ -247,10 +248,12 @@ def serve_bench(args):
         "vs_baseline": None,
         "dtype": "f64" if args.fp64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"c5: {len(reqs)} scan requests, Poisson arrivals at 20/s, N log-uniform "
-                               f"10k-2M, n0 3e10-3e11 cm^-3, T_e 0.3-3 keV with n_e scaled, 2000 steps each, "
-                               f"mesh 64x64x128, {'FP64' if args.fp64 else 'FP32-mixed'}, {args.slots} slots",
-                   "requests": len(reqs), "slots": args.slots, "hbm_budget_bytes": budget},
+        "config": {"workload": f"c5: {len(reqs)} scan requests, Poisson arrivals at {args.rate:g}/s, N log-uniform "
+                               f"10k-{args.n_hi / 1e6:g}M, n0 3e10-3e11 cm^-3, T_e 0.3-3 keV with n_e scaled, 2000 steps each, "
+                               f"mesh 64x64x128, {'FP64' if args.fp64 else 'FP32-mixed'}, {args.slots} slots"
+                               + (f", runs up to {args.batch_max_n} particles batched" if args.batch_max_n else ""),
+                   "requests": len(reqs), "slots": args.slots, "hbm_budget_bytes": budget,
+                   "arrival_rate_hz": args.rate, "batch_max_n": args.batch_max_n, "n_hi": args.n_hi},
         "roofline": None,
         "serving": {"p50_s": s["p50_s"], "p99_s": s["p99_s"], "completed": s["completed"],
                     "span_s": s["span_s"], "particle_steps": s["particle_steps"],
@@ -289,6 +292,10 @@ def main():
                     help="add the electron-ion heating kick (diamagnetic bias with --self-ne)")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
     ap.add_argument("--slots", type=int, default=16, help="c5: run slots (one HIP stream each)")
+    ap.add_argument("--rate", type=float, default=20.0, help="c5: mean arrival rate of the requests (1/s)")
+    ap.add_argument("--n-hi", type=int, default=2_000_000, help="c5: largest request (particles)")
+    ap.add_argument("--batch-max-n", type=int, default=0,
+                    help="c5: requests of at most this many particles share one batch (ecr_step_batch)")
     ap.add_argument("--split", action="store_true",
                     help="run push and deposit as two kernels (per-kernel timing; the default fuses them)")
     ap.add_argument("--copy-mb", type=int, default=0,

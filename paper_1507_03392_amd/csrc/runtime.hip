@@ -726,6 +726,11 @@ struct BatchGraph {
 std::mutex g_bgraph_mu;
 std::vector<BatchGraph> g_bgraphs;
 constexpr size_t kMaxBatchGraphs = 16;
+// the keys of periods stepped eagerly: a set of runs is captured the second
+// time one of its periods comes up (a batch whose members change at every
+// period would otherwise pay a capture per period)
+std::vector<std::vector<uint64_t>> g_bseen;
+constexpr size_t kMaxBatchSeen = 64;
 
 std::vector<uint64_t> batch_key(const std::vector<ecr_run *> &runs) {
   std::vector<uint64_t> k;
@@ -1175,10 +1180,31 @@ ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps,
     }
     const std::vector<uint64_t> key = batch_key(rs);
     hipGraphExec_t ge = nullptr;
+    bool seen = false;
     {
       std::lock_guard<std::mutex> lock(g_bgraph_mu);
       for (const BatchGraph &g : g_bgraphs)
         if (g.stream == st && g.key == key) ge = g.ge;
+      if (!ge) {
+        // a set of runs is the same set whichever buffers its runs start from
+        std::vector<uint64_t> ids;
+        for (uint64_t k : key) ids.push_back(k >> 2);
+        for (const auto &q : g_bseen) seen |= q == ids;
+        if (!seen) {
+          if (g_bseen.size() >= kMaxBatchSeen) g_bseen.erase(g_bseen.begin());
+          g_bseen.push_back(ids);
+        }
+      }
+    }
+    if (!ge && !seen) {
+      // first period of this set of runs: stepped eagerly, batched launches
+      for (int64_t i = 0; i < K; ++i) batch_step_all(rs, st, false, 0u);
+      for (ecr_run *r : rs) {
+        const ecr_status s2 = check_hip(r, hipGetLastError(), "batch step launch");
+        if (s2 != ECR_OK) return s2;
+      }
+      n_steps -= K;
+      continue;
     }
     if (!ge) {
       const hipError_t e = capture_batch_period(rs, st, K, &ge);

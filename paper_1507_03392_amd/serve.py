@@ -31,6 +31,13 @@ Runs on different slots overlap on the device (their streams map to
 separate hardware queues); a run's result depends only on its own
 parameters, so it is the same alone and in any mix (tallies and state bit
 for bit, density within FP64 atomic rounding).
+
+With batch_max_n, requests of at most that many particles are not given a
+slot of their own: they join one batch that shares a stream and is advanced
+with ecr_step_batch, so that each step of all its runs is one kernel launch
+(the batch's common sort periods replay as one captured graph).  The batch
+takes new members and retires finished ones between its launches, up to
+max_batch runs; its members' results are the same as alone.
 """
 from __future__ import annotations
 
@@ -40,7 +47,7 @@ import time
 
 import numpy as np
 
-from . import EcrError, Run, footprint
+from . import EcrError, Run, footprint, step_batch
 
 
 @dataclasses.dataclass
@@ -93,7 +100,8 @@ class Server:
     density_fields: density grids to read back at retirement.
     """
 
-    def __init__(self, hbm_budget, max_active=8, period=None, density_fields=(), device="cuda"):
+    def __init__(self, hbm_budget, max_active=8, period=None, density_fields=(), device="cuda", batch_max_n=0,
+                 max_batch=32):
         import torch
         if max_active < 1:
             raise ValueError("max_active must be >= 1")
@@ -103,13 +111,18 @@ class Server:
         self.fields = tuple(density_fields)
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_active)]
+        self.batch_max_n = int(batch_max_n)
+        self.max_batch = int(max_batch)
+        self.batch_stream = torch.cuda.Stream(device=self.device) if self.batch_max_n > 0 else None
         self.log = []  # (t, event, rid, active runs, resident bytes)
 
     def serve(self, requests, poll_s=0.0002):
         import torch
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         waiting = collections.deque()
-        active = {}
+        active = {}   # slot -> _Active
+        batch = {}    # rid -> _Active, the members of the batch
+        bstate = {"event": None}
         free = list(range(self.max_active))[::-1]
         used = 0
         results = {}
@@ -119,109 +132,157 @@ class Server:
             return time.monotonic() - t0
 
         def note(ev, rid):
-            self.log.append((now(), ev, rid, len(active), used))
+            self.log.append((now(), ev, rid, len(active) + len(batch), used))
 
-        while pending or waiting or active:
+        def batch_idle():
+            return bstate["event"] is None or bstate["event"].query()
+
+        def reject(req, res, msg):
+            res.error, res.finished = msg, now()
+            results[req.rid] = res
+            note("reject", req.rid)
+
+        def release(a):
+            nonlocal used
+            a.res.finished = now()
+            a.res.steps_run = a.done
+            results[a.req.rid] = a.res
+            a.run.close()
+            used -= a.res.nbytes
+
+        def checkpoint(a):
+            """Warm-up read and retirement of an idle run; True when it retired."""
+            if a.req.warmup > 0 and a.base is None and a.done >= a.req.warmup:
+                try:
+                    a.base = a.run.tallies()
+                except EcrError as e:
+                    a.res.error = str(e)
+                    a.halt = True
+                else:
+                    if a.base["anomalies"] > 0:
+                        a.res.error = _anomaly_error(a.run, a.base, "warm-up")
+                        a.halt = True
+            if a.done >= a.req.steps or a.halt:
+                try:
+                    t = a.run.tallies()
+                    a.res.tallies = tallies_window(t, a.base) if a.base is not None else t
+                    a.res.density = {f: a.run.density(f)[0] for f in self.fields}
+                    if t["anomalies"] > 0 and a.res.error is None:
+                        a.res.error = _anomaly_error(a.run, t, "run")
+                except EcrError as e:
+                    a.res.error = str(e)
+                release(a)
+                return True
+            return False
+
+        def next_steps(a):
+            k = self.period or int(a.req.params["sort_every"])
+            stop = a.req.warmup if a.base is None and a.done < a.req.warmup else a.req.steps
+            return min(k, stop - a.done)
+
+        while pending or waiting or active or batch:
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
             # admission, in arrival order
-            while waiting and free:
+            while waiting:
                 req = waiting[0]
+                small = self.batch_stream is not None and int(req.params["n"]) <= self.batch_max_n
+                if small and (not batch_idle() or len(batch) >= self.max_batch):
+                    break
+                if not small and not free:
+                    break
                 res = Result(rid=req.rid, n=int(req.params["n"]), arrival=req.arrival)
                 if not 0 <= req.warmup < req.steps:
                     waiting.popleft()
-                    res.error, res.finished = f"warmup {req.warmup} must be in [0, steps {req.steps})", now()
-                    results[req.rid] = res
-                    note("reject", req.rid)
+                    reject(req, res, f"warmup {req.warmup} must be in [0, steps {req.steps})")
                     continue
                 try:
                     nb = footprint(req.params)
                 except EcrError as e:
                     waiting.popleft()
-                    res.error, res.finished = str(e), now()
-                    results[req.rid] = res
-                    note("reject", req.rid)
+                    reject(req, res, str(e))
                     continue
                 if nb > self.budget:
                     waiting.popleft()
-                    res.error, res.finished = f"footprint {nb} B exceeds the HBM budget {self.budget} B", now()
-                    results[req.rid] = res
-                    note("reject", req.rid)
+                    reject(req, res, f"footprint {nb} B exceeds the HBM budget {self.budget} B")
                     continue
                 if used + nb > self.budget:
                     break
                 waiting.popleft()
-                slot = free.pop()
+                slot = -1 if small else free.pop()
+                stream = self.batch_stream if small else self.streams[slot]
                 try:
-                    run = Run(req.params, stream=self.streams[slot], device=self.device)
+                    run = Run(req.params, stream=stream, device=self.device)
                     if req.state is not None:
                         run.set_state(req.state, step=req.step0)
                     else:
                         run.init_ions()
                 except EcrError as e:
-                    free.append(slot)
-                    res.error, res.finished = str(e), now()
-                    results[req.rid] = res
-                    note("reject", req.rid)
+                    if not small:
+                        free.append(slot)
+                    reject(req, res, str(e))
                     continue
                 used += nb
                 res.admitted, res.nbytes = now(), nb
-                active[slot] = _Active(req, res, run, slot)
+                if small:
+                    batch[req.rid] = _Active(req, res, run, slot)
+                else:
+                    active[slot] = _Active(req, res, run, slot)
                 note("admit", req.rid)
-            # progress
+            # progress of the runs with a slot of their own
             moved = False
             for slot in list(active):
                 a = active[slot]
                 if a.event is not None and not a.event.query():
                     continue
                 moved = True
-                if a.req.warmup > 0 and a.base is None and a.done >= a.req.warmup:
-                    try:
-                        a.base = a.run.tallies()
-                    except EcrError as e:
-                        a.res.error = str(e)
-                        a.halt = True
-                    else:
-                        if a.base["anomalies"] > 0:
-                            a.res.error = _anomaly_error(a.run, a.base, "warm-up")
-                            a.halt = True
-                if a.done >= a.req.steps or a.halt:
-                    try:
-                        t = a.run.tallies()
-                        a.res.tallies = tallies_window(t, a.base) if a.base is not None else t
-                        a.res.density = {f: a.run.density(f)[0] for f in self.fields}
-                        if t["anomalies"] > 0 and a.res.error is None:
-                            a.res.error = _anomaly_error(a.run, t, "run")
-                    except EcrError as e:
-                        a.res.error = str(e)
-                    a.res.finished = now()
-                    a.res.steps_run = a.done
-                    results[a.req.rid] = a.res
-                    a.run.close()
+                if checkpoint(a):
                     del active[slot]
                     free.append(slot)
-                    used -= a.res.nbytes
                     note("finish", a.req.rid)
                     continue
-                k = self.period or int(a.req.params["sort_every"])
-                stop = a.req.warmup if a.base is None and a.done < a.req.warmup else a.req.steps
-                n = min(k, stop - a.done)
+                n = next_steps(a)
                 try:
                     a.run.step_graph(n)
                 except EcrError as e:
-                    a.res.error, a.res.finished = str(e), now()
-                    results[a.req.rid] = a.res
+                    a.res.error = str(e)
                     self.streams[slot].synchronize()  # nothing may still use the arena
-                    a.run.close()
+                    release(a)
                     del active[slot]
                     free.append(slot)
-                    used -= a.res.nbytes
                     note("evict", a.req.rid)
                     continue
                 a.done += n
                 a.event = torch.cuda.Event()
                 a.event.record(self.streams[slot])
+            # progress of the batch: all its members at once, when idle
+            if batch and batch_idle():
+                moved = True
+                for rid in list(batch):
+                    if checkpoint(batch[rid]):
+                        del batch[rid]
+                        note("finish", rid)
+                if batch:
+                    members = list(batch.values())
+                    n = min(next_steps(a) for a in members)
+                    try:
+                        step_batch([a.run for a in members], n, self.batch_stream)
+                    except EcrError as e:
+                        self.batch_stream.synchronize()
+                        batch.clear()
+                        for a in members:
+                            a.res.error = f"batch step failed: {e}"
+                            release(a)
+                            note("evict", a.req.rid)
+                        bstate["event"] = None
+                    else:
+                        for a in members:
+                            a.done += n
+                        bstate["event"] = torch.cuda.Event()
+                        bstate["event"].record(self.batch_stream)
+                else:
+                    bstate["event"] = None
             if not moved:
                 time.sleep(poll_s)
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]

@@ -703,7 +703,8 @@ def test_step_batch_replays_sort_periods_of_mixed_runs():
         r = gpu_run(p, events=True, stream=stream)
         r.set_state(st, step=14)
         runs.append(r)
-    # 4 whole periods (two graphs, each replayed once), then 5 single steps
+    # 4 whole periods (the first eagerly, then one graph per buffer, the
+    # first of them replayed), then 5 single steps
     batch(runs, (30, 3))
     check(list(zip(cases, runs)), 33, 14)
     # a run leaves and another joins: the new set's graphs, not the old ones
@@ -713,10 +714,11 @@ def test_step_batch_replays_sort_periods_of_mixed_runs():
     r.set_state(st, step=40)
     r.step(7)
     stream.synchronize()
-    # all at step 47: two single steps, one period as a graph, five single steps
-    batch([runs[0], r, runs[3]], (14,))
-    check([(cases[0], runs[0]), (cases[3], runs[3])], 33 + 14, 14)
-    check([((p, st), r)], 21, 40)
+    # all at step 47: two single steps; the new set's first period eagerly,
+    # its next two captured (one per buffer), the fourth replayed
+    batch([runs[0], r, runs[3]], (30,))
+    check([(cases[0], runs[0]), (cases[3], runs[3])], 33 + 30, 14)
+    check([((p, st), r)], 37, 40)
 
 
 def test_exchange_partners_in_a_chunk_beyond_the_lds():

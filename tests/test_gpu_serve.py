@@ -43,14 +43,18 @@ def _same(r1, r2, what):
         assert np.abs(d - e).max() <= 1e-12 * max(1.0, np.abs(e).max()), f"{what}: density {f}"
 
 
+@pytest.mark.parametrize("batched", [False, True])
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_FP32])
-def test_alone_vs_mix(prec):
+def test_alone_vs_mix(prec, batched):
     import paper_1507_03392_amd as ecr
     from paper_1507_03392_amd.serve import Server, summary
     reqs = _scan(prec=prec)
     fields = (W.F_ION_N, W.F_ION_Q)
-    srv = Server(hbm_budget=1 << 34, max_active=4, density_fields=fields)
+    # batched: the requests below 30k particles share one batch
+    srv = Server(hbm_budget=1 << 34, max_active=4, density_fields=fields, batch_max_n=30_000 if batched else 0)
     mix = srv.serve(reqs)
+    if batched:
+        assert sum(r.params["n"] <= 30_000 for r in reqs) >= 2
     assert max(e[3] for e in srv.log) >= 2, "no two runs were ever resident together"
     s = summary(mix)
     assert s["completed"] == len(reqs) and s["p99_s"] >= s["p50_s"] > 0
@@ -64,6 +68,42 @@ def test_alone_vs_mix(prec):
                           density={f: plain.density(f)[0] for f in fields})
         _same(alone, ref, f"request {r.rid} served vs plain steps")
         assert alone.tallies["ionized"].sum() > 0
+
+
+def test_batched_mix_with_large_requests():
+    """Requests of 0.5M and 2M particles with their own slots beside a batch
+    of small ones (arriving while the large ones run, some warmed up): each
+    result equals a plain step-by-step run of its request."""
+    import paper_1507_03392_amd as ecr
+    from paper_1507_03392_amd.serve import Request, Server
+    rng = np.random.default_rng(8)
+    reqs = []
+    for i, n in enumerate((2_000_000, 500_000, 12_000, 4_000, 60_000, 9_000, 20_000)):
+        te = float(rng.uniform(300, 3000))
+        p = W.base_params(n, 64, 64, 128, seed=200 + i, precision=W.PREC_FP32 if i % 2 else W.PREC_FP64)
+        p.update(ne_in=float(rng.uniform(0.3, 2.5)) * 1e18, Te_in_eV=te)
+        p["species"] = [W.argon(n0_m3=float(rng.uniform(3e16, 3e17)), te_ev=te)]
+        reqs.append(Request(rid=i, arrival=0.0 if i < 2 else 0.01 * i, params=p, steps=110,
+                            warmup=30 if i in (1, 3) else 0))
+    fields = (W.F_ION_N, W.F_ION_Q)
+    srv = Server(hbm_budget=1 << 34, max_active=2, density_fields=fields, batch_max_n=100_000)
+    out = srv.serve(reqs)
+    assert max(e[3] for e in srv.log) >= 3
+    for r in reqs:
+        plain = ecr.Run(r.params)
+        plain.init_ions()
+        base = None
+        if r.warmup:
+            plain.step(r.warmup)
+            base = plain.tallies()
+        plain.step(r.steps - r.warmup)
+        t = plain.tallies()
+        from paper_1507_03392_amd.serve import tallies_window
+        ref = type(out[0])(rid=r.rid, n=r.params["n"], arrival=0.0,
+                           tallies=tallies_window(t, base) if base is not None else t,
+                           density={f: plain.density(f)[0] for f in fields})
+        _same(out[r.rid], ref, f"request {r.rid} ({r.params['n']} particles) served vs plain steps")
+        plain.close()
 
 
 def test_admission_by_footprint_and_errors():
