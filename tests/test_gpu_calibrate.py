@@ -8,6 +8,8 @@ from a weight 2.5x too large and a temperature 2.5x too small, the loop must
 meet both targets within 10% and land near the reference inputs.  The
 served warm-up window is checked against two reads of a plain run.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -61,3 +63,54 @@ def test_calibration_recovers_weight_and_temperature():
     assert res.converged, hist
     assert abs(res.gas_flow_pmA / flow - 1) <= 0.1 and abs(res.power_W / power - 1) <= 0.1
     assert res.w == pytest.approx(W_REF, rel=0.25) and res.te_ev == pytest.approx(TE_REF, rel=0.25)
+
+
+def test_calibration_matches_the_oracle():
+    """The whole outer loop on a tiny hot instance (3000 Ar ions, T_i = 100 eV,
+    dt = 10 ns, 100 warm-up + 600 counted steps), once with the served GPU
+    runs and once with the FP64 oracle evaluating every candidate: the two
+    loops visit the same (w, T_ew) points with the same outputs (every tally
+    an integer count or an FP64 sum at parity, so the Newton steps agree to
+    rounding) and end in the same state."""
+    from oracle.binding import OracleSim
+    from paper_1507_03392_amd.calibrate import ServedEvaluator, Targets, calibrate, outputs
+    from paper_1507_03392_amd.serve import tallies_window
+    warmup, steps = 100, 600
+
+    def make(w, te):
+        p = W.base_params(3_000, 16, 16, 32, seed=5)
+        p.update(Ti0_eV=100.0, dt=1e-8, ne_in=3e18, weight=w, Te_in_eV=te)
+        p["species"] = [W.argon(te_ev=te)]
+        return p
+
+    def oracle_eval(points):
+        out = []
+        for w, te in points:
+            p = make(w, te)
+            o = OracleSim(p)
+            o.init_ions()
+            o.step(warmup)
+            t0 = o.tallies()
+            o.step(steps)
+            out.append(outputs(tallies_window(o.tallies(), t0), p["weight"], p["dt"], te, [W.AR_IP_EV]))
+        return out
+
+    gpu_eval = ServedEvaluator(make, [W.AR_IP_EV], steps, warmup=warmup, hbm_budget=4 << 30)
+    (flow, power), = oracle_eval([(W_REF, TE_REF)])
+    assert flow > 0 and power > 0
+    (gflow, gpower), = gpu_eval([(W_REF, TE_REF)])
+    assert gflow == pytest.approx(flow, rel=1e-12) and gpower == pytest.approx(power, rel=1e-12)
+    tg = Targets(power_W=power, gas_flow_pmA=flow, rtol=0.1)
+    ro = calibrate(oracle_eval, tg, w0=2.5 * W_REF, te0_ev=TE_REF / 2.5, max_iter=6)
+    rg = calibrate(gpu_eval, tg, w0=2.5 * W_REF, te0_ev=TE_REF / 2.5, max_iter=6)
+    hist = [(round(h.w / W_REF, 4), round(h.te_ev / TE_REF, 4), round(h.gas_flow_pmA / flow, 4),
+             round(h.power_W / power, 4)) for h in ro.history]
+    print(f"oracle loop (w, T_ew, flow, power relative to the reference): {hist}")
+    assert (ro.converged, ro.iterations, ro.evaluations) == (rg.converged, rg.iterations, rg.evaluations)
+    for a, b in zip(ro.history, rg.history):
+        for k in ("w", "te_ev", "gas_flow_pmA", "power_W"):
+            assert getattr(b, k) == pytest.approx(getattr(a, k), rel=1e-9), (k, a, b)
+    # the loop did its work: the last point is nearer both targets than the start
+    first, last = ro.history[0], ro.history[-1]
+    err = lambda h: max(abs(math.log(h.gas_flow_pmA / flow)), abs(math.log(h.power_W / power)))
+    assert ro.converged or err(last) < 0.5 * err(first), hist
