@@ -229,10 +229,18 @@ typedef struct ecr_run ecr_run;
 /* Device bytes a run with these parameters needs.  ECR_EINVAL on bad params. */
 ecr_status ecr_footprint(const ecr_params *params, size_t *device_bytes);
 
-/* Create a run in a caller-owned device arena, bound to a caller-owned HIP
- * stream (NULL: the null stream).  Copies params (and the E-field nodes, if
- * given) and uploads the derived tables.  ECR_EDT if the per-step ionisation
- * plus charge-exchange probability can exceed 0.1. */
+/* Create a run of the ion model of Sec. II (its chamber, field, electron
+ * background and species; Table I gives the paper's values) in a
+ * caller-owned device arena of arena_bytes >= ecr_footprint() bytes (the
+ * caller keeps ownership and must keep it alive until ecr_destroy), bound to
+ * a caller-owned HIP stream (NULL: the null stream).  Copies params (and the
+ * E-field nodes, if given) and uploads the derived tables (Boris factors,
+ * per-step ionisation and exchange probabilities, Nanbu's A(s)).
+ * ECR_EINVAL on bad parameters or a short arena, ECR_EABI on a foreign
+ * abi_version, ECR_EDT if the per-step ionisation plus charge-exchange
+ * probability can exceed 0.1 (the first-order Monte Carlo collision limit
+ * of Sec. II), ECR_EDEVICE if the upload fails.  *out is set only on
+ * ECR_OK. */
 ecr_status ecr_create(const ecr_params *params, void *device_arena, size_t arena_bytes,
                       void *hip_stream, ecr_run **out);
 
@@ -260,8 +268,13 @@ ecr_status ecr_create_static(const ecr_params *params, void *hip_stream, ecr_run
  * (Sec. II); zeroes tallies and density; step counter 0. */
 ecr_status ecr_init_ions(ecr_run *run);
 
-/* Advance n_steps steps (sort every sort_every steps, then Coulomb, push,
- * wall/aperture, ionisation/charge exchange, deposit).  Asynchronous. */
+/* Advance n_steps time steps of Sec. II: the sort by cell every sort_every
+ * steps; then, per step, the Coulomb block (Takizuka-Abe pairing within
+ * each collision cell, Nanbu's scattering angle), the Boris push in the
+ * magnetic field, wall and aperture loss, ionisation and charge exchange
+ * with the background (Monte Carlo collisions), and the cloud-in-cell
+ * deposit of the densities.  Asynchronous on the run's stream; launch
+ * failures return ECR_EDEVICE with the HIP message in ecr_last_error. */
 ecr_status ecr_step(ecr_run *run, int64_t n_steps);
 
 /* Same as ecr_step(run, n_steps), with the same results, but every whole
@@ -273,7 +286,19 @@ ecr_status ecr_step(ecr_run *run, int64_t n_steps);
  * graphs (one per sort buffer) until ecr_destroy.  Asynchronous. */
 ecr_status ecr_step_graph(ecr_run *run, int64_t n_steps);
 
-/* Advance several independent runs that share one stream by n_steps each. */
+/* Advance several independent runs (the scans of Sec. III: one run per
+ * gas-flow or power point) that share the stream hip_stream by n_steps
+ * each, with the same results as ecr_step on each run.  Each step of all
+ * the runs whose step is the default one (fused step, deposit of exactly
+ * ECR_F_ION_N and ECR_F_ION_Q, no optional physics, not profiled) is one
+ * kernel launch over the chunks of every such run (at most 32 runs per
+ * launch), which reads each run's arguments from a job in the run's own
+ * arena; other runs are stepped as ecr_step does.  When every run is at the
+ * start of a sort period of the same length and n_steps covers it, the
+ * period is replayed from a graph captured for that set of runs (captured
+ * the second time the set comes up, kept until one of its runs is
+ * destroyed).  ECR_EINVAL if a run is NULL, failed, uninitialised, bound to
+ * another stream or listed twice.  Asynchronous. */
 ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps, void *hip_stream);
 
 /* Tallies since the last init/set_state.  Synchronises.  ECR_ENUMERIC (with
@@ -281,7 +306,10 @@ ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps,
 ecr_status ecr_read_tallies(ecr_run *run, ecr_tallies *host_out);
 
 /* Time-integrated CIC deposit of one field: (nx+1)(ny+1)(nz+1) doubles in
- * x-fastest node order, plus the number of deposited steps.  Synchronises. */
+ * x-fastest node order into host_out (caller-owned), plus the number of
+ * deposited steps; divided by that number these are the time-averaged
+ * distributions of Sec. III.B.  Synchronises.  ECR_EINVAL for a field
+ * outside ECR_F_* or a NULL output. */
 ecr_status ecr_read_density(ecr_run *run, uint32_t field, double *host_out, int64_t *steps_accum);
 
 /* Particle state by id (checkpoint and parity).  Synchronises. */
