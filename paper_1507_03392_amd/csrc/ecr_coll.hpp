@@ -50,7 +50,7 @@ __device__ __forceinline__ void collide_acc(const KParams &P, const double *__re
   const R omc = (R)nanbu_omc(lnA, sv, u);
   const R sinchi = sqrt_cont(omc * ((R)2 - omc));
   R sp, cp;
-  sincospi_r((R)(2.0 * u2), &sp, &cp);  // phi = 2 pi u2
+  sincos_2pi(u2, &sp, &cp);  // phi = 2 pi u2
   const R ca = sinchi * cp, cb = sinchi * sp;
   const R uperp = sqrt_cont(ux * ux + uy * uy);
   R dux, duy, duz;

@@ -152,6 +152,42 @@ __device__ __forceinline__ void sincos_r(float x, float *s, float *c) { sincosf(
 __device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
 __device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
 
+// sin and cos of 2 pi u for u in [0, 1) (the azimuth of a collision, a
+// continuous outcome): 4u = q + f exactly with q = rint(4u), f in [-1/2, 1/2],
+// theta = f pi/2 in [-pi/4, pi/4]; Taylor polynomials in theta^2 through
+// theta^17 (sine) and theta^18 (cosine), truncation below 5e-17; the quarter
+// turn q mod 4 swaps and negates.  Within a few ulp of the exact values.
+__device__ __forceinline__ void sincos_2pi(double u, double *sn, double *cs) {
+  const double t = 4.0 * u;
+  const double q = rint(t);
+  const double th = (t - q) * 1.5707963267948966192;
+  const double z = th * th;
+  double ps = 1.0 / 355687428096000.0;
+  ps = fma(ps, z, -1.0 / 1307674368000.0);
+  ps = fma(ps, z, 1.0 / 6227020800.0);
+  ps = fma(ps, z, -1.0 / 39916800.0);
+  ps = fma(ps, z, 1.0 / 362880.0);
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  const double s = fma(th * z, ps, th);
+  double pc = -1.0 / 6402373705728000.0;
+  pc = fma(pc, z, 1.0 / 20922789888000.0);
+  pc = fma(pc, z, -1.0 / 87178291200.0);
+  pc = fma(pc, z, 1.0 / 479001600.0);
+  pc = fma(pc, z, -1.0 / 3628800.0);
+  pc = fma(pc, z, 1.0 / 40320.0);
+  pc = fma(pc, z, -1.0 / 720.0);
+  pc = fma(pc, z, 1.0 / 24.0);
+  pc = fma(pc, z, -0.5);
+  const double c = fma(z, pc, 1.0);
+  const int k = (int)q & 3;
+  const double a = (k & 1) ? c : s, b = (k & 1) ? s : c;
+  *sn = (k & 2) ? -a : a;
+  *cs = (k == 1 || k == 2) ? -b : b;
+}
+__device__ __forceinline__ void sincos_2pi(double u, float *sn, float *cs) { sincospif((float)(2.0 * u), sn, cs); }
+
 // two standard normals from two uniforms
 __device__ __forceinline__ void box_muller(double ua, double ub, double &n1, double &n2) {
   const double r = sqrt(-2.0 * log(1.0 - ua));

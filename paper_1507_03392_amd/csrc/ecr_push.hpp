@@ -362,7 +362,7 @@ __device__ __forceinline__ void run_accumulate(const DepIn<R> &D, uint32_t dm, N
     }
     const R wx[2] = {(R)1 - D.tx[p], D.tx[p]}, wy[2] = {(R)1 - D.ty[p], D.ty[p]};
     const R wz[2] = {(R)1 - D.tz[p], D.tz[p]};
-    const bool ion = D.q[p] >= 1;
+    const bool ion = (dm & 4u) ? D.q[p] >= 1 : true;  // without the atom field only ions are staged
     const double qd = (double)D.q[p];
     int k = 0;
     for (int dz = 0; dz < 2; ++dz)
@@ -431,6 +431,32 @@ __device__ __forceinline__ int small_div(int i, int d, float rcp) {
   return q;
 }
 
+// the box of base cells of a tile: each wavefront's last lane writes the
+// wavefront's min / max into the wavefront's own six entries of box (6 ints
+// per wavefront of the workgroup: no atomics, nothing to clear first);
+// after a barrier every lane reduces them (uniform reads, scalar results)
+__device__ __forceinline__ void box_publish(int *box, int mn[3], int mx[3]) {
+  wave_box_last(mn, mx);
+  if ((threadIdx.x & 63) == 63) {
+    int *b = box + 6 * (threadIdx.x >> 6);
+    for (int d = 0; d < 3; ++d) {
+      b[d] = mn[d];
+      b[3 + d] = mx[d];
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void box_reduce(const int *box, int out[6]) {
+  for (int d = 0; d < 6; ++d) out[d] = box[d];
+  for (int w = 1; w < NT / 64; ++w)
+    for (int d = 0; d < 3; ++d) {
+      out[d] = min(out[d], box[6 * w + d]);
+      out[3 + d] = max(out[3 + d], box[6 * w + 3 + d]);
+    }
+  for (int d = 0; d < 6; ++d) out[d] = __builtin_amdgcn_readfirstlane(out[d]);
+}
+
 // deposit a staged tile; every lane of the workgroup must call it.  G: the
 // lanes' last runs are summed within groups of G lanes (G = 64: over the
 // whole wavefront) before the run's last lane in the group flushes them
@@ -441,12 +467,7 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
   const int tid = threadIdx.x;
   const uint32_t dm = NQ ? 3u : P.dmask;
   constexpr int kFields = NQ ? 2 : 3;  // brick fields
-  wave_box_last(mn, mx);
-  if ((tid & 63) == 63)
-    for (int d = 0; d < 3; ++d) {
-      atomicMin(&box[d], mn[d]);
-      atomicMax(&box[3 + d], mx[d]);
-    }
+  box_publish(box, mn, mx);
   __syncthreads();  // staging and box complete
   static_assert(kP == 4, "the wide staging reads take four slots");
   DepIn<R> D;
@@ -470,11 +491,11 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
     }
   }
   // the box is the same for every lane: keep it in scalar registers
-  const int x0 = __builtin_amdgcn_readfirstlane(box[0]), y0 = __builtin_amdgcn_readfirstlane(box[1]);
-  const int z0 = __builtin_amdgcn_readfirstlane(box[2]);
-  const bool any = __builtin_amdgcn_readfirstlane(box[3]) >= 0;
-  const int bx = __builtin_amdgcn_readfirstlane(box[3]) - x0 + 2, by = __builtin_amdgcn_readfirstlane(box[4]) - y0 + 2;
-  const int bz = __builtin_amdgcn_readfirstlane(box[5]) - z0 + 2;
+  int bb[6];
+  box_reduce<NT>(box, bb);
+  const int x0 = bb[0], y0 = bb[1], z0 = bb[2];
+  const bool any = bb[3] >= 0;
+  const int bx = bb[3] - x0 + 2, by = bb[4] - y0 + 2, bz = bb[5] - z0 + 2;
   __syncthreads();  // staging read: the brick may now reuse it
   if (!any) return;
   const int64_t nodes = (int64_t)bx * by * bz;
@@ -567,10 +588,6 @@ __device__ __forceinline__ void deposit_staged(const KParams &P, double *__restr
   }
 }
 
-__device__ __forceinline__ void box_init(int *box) {
-  if (threadIdx.x < 6) box[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -1;
-  __syncthreads();
-}
 
 // a lane's contribution to the next step's cell grids (chg_next: the ion
 // charge Q in channel 0, or one atom in its species' channel): lanes hold

@@ -73,8 +73,7 @@ __device__ __forceinline__ void push_tile(const KParams &P, const Tables *__rest
                                           const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next) {
   __shared__ DepShared<R> sh;
   const uint32_t step = sa.get();
-  __shared__ int box[6];
-  if (DEP) box_init(box);
+  __shared__ int box[6 * (kBlock / 64)];
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
   const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll
@@ -144,8 +143,7 @@ k_push_lean(KParams P, const Tables *__restrict__ T, Soa<double> S, const double
 template <typename R, bool NQ>
 __global__ void __launch_bounds__(kBlock) k_deposit(KParams P, Soa<R> S, double *__restrict__ dens) {
   __shared__ DepShared<R> sh;
-  __shared__ int box[6];
-  box_init(box);
+  __shared__ int box[6 * (kBlock / 64)];
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
   const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll
@@ -180,8 +178,7 @@ union PShared {
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_deposit_pressure(KParams P, Soa<R> S, double *__restrict__ dens) {
   __shared__ PShared<R> sh;
-  __shared__ int box[6];
-  box_init(box);
+  __shared__ int box[6 * (kBlock / 64)];
   const int tid = threadIdx.x;
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
   const int64_t base = (int64_t)blockIdx.x * kTile;
@@ -216,12 +213,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_pressure(KParams P, Soa<R> S
       }
     }
   }
-  wave_box_last(mn, mx);
-  if ((tid & 63) == 63)
-    for (int d = 0; d < 3; ++d) {
-      atomicMin(&box[d], mn[d]);
-      atomicMax(&box[3 + d], mx[d]);
-    }
+  box_publish(box, mn, mx);
   __syncthreads();  // staging and box complete
   int ix[kP], iy[kP], iz[kP];
   R tx[kP], ty[kP], tz[kP];
@@ -237,9 +229,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit_pressure(KParams P, Soa<R> S
     iy[p] = sh.st.c[1][k];
     iz[p] = sh.st.c[2][k];
   }
-  const int x0 = box[0], y0 = box[1], z0 = box[2];
-  const bool any = box[3] >= 0;
-  const int bx = box[3] - x0 + 2, by = box[4] - y0 + 2, bz = box[5] - z0 + 2;
+  int bb[6];
+  box_reduce<kBlock>(box, bb);
+  const int x0 = bb[0], y0 = bb[1], z0 = bb[2];
+  const bool any = bb[3] >= 0;
+  const int bx = bb[3] - x0 + 2, by = bb[4] - y0 + 2, bz = bb[5] - z0 + 2;
   __syncthreads();  // staging read: the brick may now reuse it
   if (!any) return;
   const int64_t nodes = (int64_t)bx * by * bz;

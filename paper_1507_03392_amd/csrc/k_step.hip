@@ -133,7 +133,6 @@ __device__ __forceinline__ void push_tile_global(const KParams &P, const Tables 
                                                  double *__restrict__ dens, uint32_t step,
                                                  const uint32_t *__restrict__ chg_cur, uint32_t *__restrict__ chg_next,
                                                  int64_t t0, int64_t hi, DepShared<R, kFMax> &dsh, int *box) {
-  if (DEP) box_init(box);
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
 #pragma unroll
   for (int p = 0; p < kP; ++p) {
@@ -298,7 +297,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
                                         const uint32_t wg) {
   __shared__ __align__(16) unsigned char lds[lds_bytes<R>()];
   __shared__ uint32_t lead[kFLead], wsum[kFB / 64];
-  __shared__ int box[6];
+  __shared__ int box[6 * (kFB / 64)];
   const uint32_t step = sa.get();
   const int tid = threadIdx.x;
   if (wg < (unsigned)kBigWG) {
@@ -507,7 +506,6 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
                 "the staged offsets overlay the velocities slot by slot");
   DepShared<R, kFMax> &dsh = *reinterpret_cast<DepShared<R, kFMax> *>(lds);
   __syncthreads();  // collisions done (the staged cells go over the items)
-  if (DEP) box_init(box);
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
 #pragma unroll
   for (int k = 0; k < kFR; ++k) {
