@@ -9,6 +9,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 import bench
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -35,8 +37,9 @@ def test_traffic_is_read_only_for_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("w", "k") is None  # the kernel changed since the counters were taken
 
 
-def test_committed_summary_names_a_hash_of_the_right_form():
-    path = os.path.join(ROOT, "profiles", "push_deposit_c2_traffic.md")
+@pytest.mark.parametrize("name", ["step_c2_traffic.md", "step_c4_traffic.md"])
+def test_committed_summary_names_a_hash_of_the_right_form(name):
+    path = os.path.join(ROOT, "profiles", name)
     kv = {}
     with open(path) as fh:
         for line in fh:
