@@ -10,10 +10,10 @@
 // except the density grid and the tallies (atomics), so each chunk is
 // stepped start to finish by its workgroup and the state is read once and
 // written once:
-//  1. lane = slot, four rounds of 256: charge, id, collision cell and
-//     velocity are loaded; each particle's STEP draw is made once: words 0-1
-//     are its Monte-Carlo uniform (kept in registers for step 6), word 2 its
-//     pairing key;
+//  1. lane = slot, four rounds of 256: charge, id and the slot's buckets
+//     (tabulated per cell at the sort) are loaded; each particle's STEP
+//     draw is made once: words 0-1 are its Monte-Carlo uniform (kept in
+//     registers for step 6), word 2 its pairing key;
 //  2. the pool of each cell (its ions) is ordered by (key, id) in LDS: a
 //     cell of m slots gets 2^floor(log2 m) buckets on the top key bits, an
 //     LDS histogram and scan place the members bucket by bucket, and a
@@ -24,8 +24,8 @@
 //  4. one lane per work item collides the pair (or the triplet's three
 //     pairs at dt/2, in order) in LDS; momentum and energy sums go to one
 //     slot per wavefront of the chunk;
-//  5. the velocities come back to registers;
-//  6. lane = slot again: positions are loaded, each particle is pushed,
+//  5-6. lane = slot again: positions are loaded, the velocities read back
+//     from LDS, each particle is pushed,
 //     tested against the walls and the aperture, and draws its ionisation /
 //     exchange outcome from the uniform of step 1; the state is stored;
 //  7. the deposit inputs are staged and deposited through an LDS brick.
