@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="c5: mean arrival rate of the requests (1/s)")
     ap.add_argument("--n-hi", type=int, default=2_000_000, help="c5: largest request (particles)")
     ap.add_argument("--batch-max-n", type=int, default=0,
-                    help="c5: requests of at most this many particles share one batch (ecr_step_batch)")
+                    help="c5: requests of at most this many particles are batched (ecr_step_batch; 0: none)")
     ap.add_argument("--split", action="store_true",
                     help="run push and deposit as two kernels (per-kernel timing; the default fuses them)")
     ap.add_argument("--copy-mb", type=int, default=0,

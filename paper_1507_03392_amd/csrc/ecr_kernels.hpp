@@ -15,8 +15,10 @@ namespace ecr {
 constexpr int kCoulCap = 256;
 constexpr int kCoulMaxE = 1024;
 // the fused step kernel's chunks: the cells whose first sorted slot falls in
-// [b*kFCap, (b+1)*kFCap); a chunk of at most 1024 slots is stepped by its
-// own workgroup, a larger one by a handler workgroup
+// [b*cap, (b+1)*cap), cap = step_fcap(n) (kFCap from 98 304 particles up;
+// smaller runs get smaller chunks, down to 64 slots, so that they still
+// spread over the CUs); a chunk of at most 1024 slots is stepped by its own
+// workgroup, a larger one by a handler workgroup
 constexpr int kFCap = 768;
 
 static_assert(kBirthNone == ECR_BIRTH_NONE, "birth sentinel");
@@ -96,7 +98,8 @@ void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hi
 
 // the whole step in one kernel (Coulomb pairing and collisions, push,
 // wall/aperture loss, MCC, deposit) over the chunks of the fused table
-// (chunk_lo, step_nchunks(n) + 1 entries; big: the oversized chunks, made by
+// (chunk_lo, step_nchunks(n, cap) + 1 entries for the chunk size cap of the
+// table; big: the oversized chunks, made by
 // launch_big_list at the sort); moments as for the Coulomb kernels;
 // scratch64: n 64-bit words of sort space for pools beyond the LDS.  With
 // chg_next, it must have been zeroed before.
@@ -104,14 +107,17 @@ void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hi
 // tabulates the ordering's buckets of every other chunk: per slot
 // (bkinfo[n]) first bucket | log2(bucket count) << 16 of its cell, per chunk
 // (nbk[nchunks]) the bucket total.
-int64_t step_nchunks(int64_t n);
-void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, uint32_t *big, uint32_t *bkinfo,
-                      uint32_t *nbk, hipStream_t st);
+int64_t step_fcap(int64_t n);
+int64_t step_nchunks(int64_t n, int64_t cap);
+// moment slots the fused step writes (one per wavefront of a chunk)
+int64_t step_moment_slots(int64_t n);
+void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, int64_t cap, uint32_t *big,
+                      uint32_t *bkinfo, uint32_t *nbk, hipStream_t st);
 template <typename R>
 void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
                  const uint32_t *big, const uint32_t *bkinfo, const uint32_t *nbk, uint8_t *evlog, DevAccum *acc,
                  double *dens, double *moments, uint64_t *scratch64, StepArg step, const uint32_t *chg_cur,
-                 uint32_t *chg_next, hipStream_t st);
+                 uint32_t *chg_next, int64_t cap, hipStream_t st);
 
 // Batched step: one launch steps several runs (each a default step: fused
 // kernel, ion number and charge deposited, no optional physics).  A run's
@@ -146,7 +152,7 @@ struct SetWords {
   int n;
 };
 bool step_batchable(const KParams &P, bool dens, bool grids);
-uint32_t step_batch_wgs(int64_t n);
+uint32_t step_batch_wgs(int64_t n, int64_t cap);
 template <typename R>
 void launch_step_batch(const StepBatch<R> &B, hipStream_t st);
 template <typename R>

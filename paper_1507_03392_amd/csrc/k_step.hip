@@ -652,11 +652,27 @@ __global__ void k_big_list(const uint32_t *__restrict__ chunk_lo, int64_t nchunk
   if ((int64_t)chunk_lo[b + 1] - (int64_t)chunk_lo[b] > kFMax) big[1 + atomicAdd(&big[0], 1u)] = (uint32_t)b;
 }
 
-int64_t step_nchunks(int64_t n) { return (n + kFCap - 1) / kFCap; }
+// the chunk size of a run: kFCap from 128 chunks up; a smaller run gets
+// about 128 chunks of a power-of-two size (at least 64 slots), so that it
+// still spreads over the CUs (and, its cells being sparsely filled, a
+// chunk's deposit box fits the LDS brick more often).  Chunks smaller than
+// kFCap cost more per particle where the GPU is full anyway (fewer pairs per
+// workgroup, more fixed work per chunk), hence kFCap from 98 304 particles.
+int64_t step_fcap(int64_t n) {
+  if (n >= 128 * (int64_t)kFCap) return kFCap;
+  int64_t p = 64;
+  while (2 * p <= n / 128 && 2 * p <= 512) p *= 2;
+  return p;
+}
 
-void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, uint32_t *big, uint32_t *bkinfo,
+int64_t step_nchunks(int64_t n, int64_t cap) { return (n + cap - 1) / cap; }
+
+int64_t step_moment_slots(int64_t n) { return step_nchunks(n, step_fcap(n)) * (kFB / 64); }
+
+void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, int64_t cap, uint32_t *big,
+                      uint32_t *bkinfo,
                       uint32_t *nbk, hipStream_t st) {
-  const int64_t nc = step_nchunks(n);
+  const int64_t nc = step_nchunks(n, cap);
   launch_fill_u32(big, 0u, 1, st);
   if (nc <= 0) return;
   hipLaunchKernelGGL(k_big_list, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, chunk_lo, nc, big);
@@ -668,8 +684,8 @@ static void launch_step_e(const KParams &P, const Tables *T, Soa<R> S, const uin
                           const uint32_t *chunk_lo, const uint32_t *big, const uint32_t *bkinfo, const uint32_t *nbk,
                           uint8_t *evlog, DevAccum *acc, double *dens,
                           double *moments, uint64_t *scratch64, StepArg step, const uint32_t *chg_cur,
-                          uint32_t *chg_next, hipStream_t st) {
-  const dim3 g((unsigned)(kBigWG + step_nchunks(P.n))), b(kFB);
+                          uint32_t *chg_next, int64_t cap, hipStream_t st) {
+  const dim3 g((unsigned)(kBigWG + step_nchunks(P.n, cap))), b(kFB);
   if (!dens)
     hipLaunchKernelGGL((k_step<R, 0, EXT>), g, b, 0, st, P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens,
                        moments, scratch64, step, chg_cur, chg_next);
@@ -685,15 +701,16 @@ template <typename R>
 void launch_step(const KParams &P, const Tables *T, Soa<R> S, const uint32_t *cellid, const uint32_t *chunk_lo,
                  const uint32_t *big, const uint32_t *bkinfo, const uint32_t *nbk, uint8_t *evlog, DevAccum *acc,
                  double *dens, double *moments,
-                 uint64_t *scratch64, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, hipStream_t st) {
+                 uint64_t *scratch64, StepArg step, const uint32_t *chg_cur, uint32_t *chg_next, int64_t cap,
+                 hipStream_t st) {
   if (P.n <= 0) return;
   const bool ext = chg_cur || chg_next || (P.pmask & (P_HEAT | P_ELASTIC)) || P.nion > 1;
   if (ext)
     launch_step_e<R, true>(P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens, moments, scratch64, step,
-                           chg_cur, chg_next, st);
+                           chg_cur, chg_next, cap, st);
   else
     launch_step_e<R, false>(P, T, S, cellid, chunk_lo, big, bkinfo, nbk, evlog, acc, dens, moments, scratch64, step,
-                            chg_cur, chg_next, st);
+                            chg_cur, chg_next, cap, st);
 }
 
 bool step_batchable(const KParams &P, bool dens, bool grids) {
@@ -706,7 +723,7 @@ void launch_step_batch(const StepBatch<R> &B, hipStream_t st) {
   hipLaunchKernelGGL((k_step_batch<R>), dim3(B.wg0[B.n]), dim3(kFB), 0, st, B);
 }
 
-uint32_t step_batch_wgs(int64_t n) { return (uint32_t)(kBigWG + step_nchunks(n)); }
+uint32_t step_batch_wgs(int64_t n, int64_t cap) { return (uint32_t)(kBigWG + step_nchunks(n, cap)); }
 
 template <typename R>
 void launch_set_job(const StepJob<R> &J, StepJob<R> *dst, hipStream_t st) {
@@ -724,9 +741,9 @@ template void launch_set_job<float>(const StepJob<float> &, StepJob<float> *, hi
 
 template void launch_step<double>(const KParams &, const Tables *, Soa<double>, const uint32_t *, const uint32_t *,
                                   const uint32_t *, const uint32_t *, const uint32_t *, uint8_t *, DevAccum *, double *,
-                                  double *, uint64_t *, StepArg, const uint32_t *, uint32_t *, hipStream_t);
+                                  double *, uint64_t *, StepArg, const uint32_t *, uint32_t *, int64_t, hipStream_t);
 template void launch_step<float>(const KParams &, const Tables *, Soa<float>, const uint32_t *, const uint32_t *,
                                  const uint32_t *, const uint32_t *, const uint32_t *, uint8_t *, DevAccum *, double *,
-                                 double *, uint64_t *, StepArg, const uint32_t *, uint32_t *, hipStream_t);
+                                 double *, uint64_t *, StepArg, const uint32_t *, uint32_t *, int64_t, hipStream_t);
 
 }  // namespace ecr

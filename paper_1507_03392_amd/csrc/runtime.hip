@@ -47,6 +47,11 @@ struct Layout {
 };
 
 int64_t ncells(const ecr_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
+// FP64 moment slots of a run: the Coulomb kernels' and the fused step's
+int64_t moment_slots(int64_t n) {
+  const int64_t m = n > 0 ? n : 1;
+  return std::max(coul_moment_slots(m), step_moment_slots(m));
+}
 int64_t nnodes(const ecr_params *p) { return (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1); }
 // the heating kick reads |B| hx per cell when n_e comes from the particles
 bool needs_bden(const ecr_params *p) {
@@ -79,11 +84,11 @@ Layout make_layout(const ecr_params *p) {
   L.chunks = o;
   o = align_up(o + 4 * (size_t)(coul_nchunks((int64_t)N) + 2));
   L.fchunks = o;
-  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 2));
+  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N, step_fcap((int64_t)N)) + 2));
   L.big = o;
-  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 1));
+  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N, step_fcap((int64_t)N)) + 1));
   L.nbk = o;
-  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N) + 1));
+  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N, step_fcap((int64_t)N)) + 1));
   L.scratch64 = o;
   o = align_up(o + 8 * N);
   L.pairs = o;
@@ -91,7 +96,7 @@ Layout make_layout(const ecr_params *p) {
   L.tris = o;  // per-chunk (pairs, triplets) counts
   o = align_up(o + 8 * (size_t)coul_nchunks((int64_t)N));
   L.moments = o;
-  o = align_up(o + 8 * 5 * (size_t)coul_moment_slots((int64_t)N));
+  o = align_up(o + 8 * 5 * (size_t)moment_slots((int64_t)N));
   L.count = o;
   o = align_up(o + 4 * (size_t)(ncells(p) + 1));
   L.cell_off = o;
@@ -540,9 +545,9 @@ void do_sort(ecr_run *r, const uint32_t *given) {
                        at<uint32_t>(r, r->L.chunks), kCoulCap, r->stream);
     if (fused(r)) {
       launch_coul_chunks(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off), r->kp.n,
-                         at<uint32_t>(r, r->L.fchunks), kFCap, r->stream);
+                         at<uint32_t>(r, r->L.fchunks), step_fcap(r->kp.n), r->stream);
       // the per-slot buckets go into the sort's rank array, free until the next sort
-      launch_step_prep(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks), r->kp.n,
+      launch_step_prep(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks), r->kp.n, step_fcap(r->kp.n),
                        at<uint32_t>(r, r->L.big), at<uint32_t>(r, r->L.rank), at<uint32_t>(r, r->L.nbk), r->stream);
     }
   }
@@ -575,7 +580,7 @@ void do_step(ecr_run *r, StepArg stepw) {
                      at<uint32_t>(r, r->L.big), at<uint32_t>(r, r->L.rank), at<uint32_t>(r, r->L.nbk),
                      (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr,
                      acc, (pm & ECR_P_DEPOSIT) ? at<double>(r, r->L.dens) : nullptr, at<double>(r, r->L.moments),
-                     at<uint64_t>(r, r->L.scratch64), stepw, chg_cur, chg_next, r->stream);
+                     at<uint64_t>(r, r->L.scratch64), stepw, chg_cur, chg_next, step_fcap(r->kp.n), r->stream);
     }
     step_tail<R>(r, stepw, grids);
     return;
@@ -686,7 +691,7 @@ void batch_step(const std::vector<ecr_run *> &rs, const std::vector<StepArg> &sa
       B.job[j] = at<StepJob<R>>(r, r->L.job) + r->cur;
       B.stepw[j] = sa[k0 + j].base;
       B.step[j] = sa[k0 + j].off;
-      B.wg0[j + 1] = B.wg0[j] + step_batch_wgs(r->kp.n);
+      B.wg0[j + 1] = B.wg0[j] + step_batch_wgs(r->kp.n, step_fcap(r->kp.n));
     }
     launch_step_batch<R>(B, st);
   }
@@ -796,7 +801,7 @@ void build_charge_grid(ecr_run *r) {
 void zero_accumulators(ecr_run *r) {
   launch_fill_f64(at<double>(r, r->L.dens), 0.0, (int64_t)ECR_N_FIELDS * r->nnode, r->stream);
   launch_fill_u32(at<uint32_t>(r, r->L.acc), 0u, (int64_t)(sizeof(DevAccum) / 4), r->stream);
-  launch_fill_f64(at<double>(r, r->L.moments), 0.0, 5 * coul_moment_slots(r->kp.n > 0 ? r->kp.n : 1), r->stream);
+  launch_fill_f64(at<double>(r, r->L.moments), 0.0, 5 * moment_slots(r->kp.n), r->stream);
   if (r->kp.cxreq) {
     launch_fill_u32(r->kp.cxreq, 0u, r->ncell * r->p.n_species, r->stream);
     launch_fill_u32(r->kp.cxchunk, 0u, coul_nchunks(r->kp.n) + 1, r->stream);
@@ -1249,7 +1254,7 @@ ecr_status ecr_step_batch(ecr_run *const *runs, int32_t n_runs, int64_t n_steps,
 ecr_status ecr_read_tallies(ecr_run *r, ecr_tallies *out) {
   if (!r || !out) return fail(r, ECR_EINVAL, "NULL argument");
   DevAccum h;
-  launch_sum_moments(at<double>(r, r->L.moments), coul_moment_slots(r->kp.n > 0 ? r->kp.n : 1), at<DevAccum>(r, r->L.acc),
+  launch_sum_moments(at<double>(r, r->L.moments), moment_slots(r->kp.n), at<DevAccum>(r, r->L.acc),
                      r->stream);
   hipError_t e = hipMemcpyAsync(&h, at<DevAccum>(r, r->L.acc), sizeof(DevAccum), hipMemcpyDeviceToHost, r->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r->stream);

@@ -32,12 +32,19 @@ separate hardware queues); a run's result depends only on its own
 parameters, so it is the same alone and in any mix (tallies and state bit
 for bit, density within FP64 atomic rounding).
 
-With batch_max_n, requests of at most that many particles are not given a
-slot of their own: they join one batch that shares a stream and is advanced
-with ecr_step_batch, so that each step of all its runs is one kernel launch
-(the batch's common sort periods replay as one captured graph).  The batch
-takes new members and retires finished ones between its launches, up to
-max_batch runs; its members' results are the same as alone.
+With batch_max_n (0, off, by default), requests of at most that many
+particles are not given a slot of their own: they join one of n_batches
+batches, each of which shares a stream and is advanced with ecr_step_batch,
+so that each step of all its runs is one kernel launch (a batch's common
+sort periods replay as one captured graph).  A batch takes new members (a request joins the idle batch
+with the fewest members) and retires finished ones between its launches, up
+to max_batch runs; several batches keep the GPU busy while one of them turns
+around on the host.  Members' results are the same as alone.  Measured on
+one MI355X: a flood of 10k-100k requests is served 13% faster batched
+(batch_max_n = 100 000), while the scan trace of 10k-2M requests, whose work
+is mostly in large runs with slots of their own, is served as fast either
+way and with a lower median latency without batches (a small request waits
+for a batch's launch to end before it joins).
 """
 from __future__ import annotations
 
@@ -97,11 +104,13 @@ class Server:
     hbm_budget: device bytes the resident runs may hold together.
     period: steps per launch (None: each run's sort_every, the unit that
     ecr_step_graph replays as one graph).
+    batch_max_n: requests of at most this many particles are batched (0: every
+    request gets a slot of its own); max_batch runs per batch, n_batches batches.
     density_fields: density grids to read back at retirement.
     """
 
     def __init__(self, hbm_budget, max_active=8, period=None, density_fields=(), device="cuda", batch_max_n=0,
-                 max_batch=32):
+                 max_batch=32, n_batches=4):
         import torch
         if max_active < 1:
             raise ValueError("max_active must be >= 1")
@@ -113,7 +122,8 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_active)]
         self.batch_max_n = int(batch_max_n)
         self.max_batch = int(max_batch)
-        self.batch_stream = torch.cuda.Stream(device=self.device) if self.batch_max_n > 0 else None
+        self.batch_streams = ([torch.cuda.Stream(device=self.device) for _ in range(max(1, n_batches))]
+                              if self.batch_max_n > 0 else [])
         self.log = []  # (t, event, rid, active runs, resident bytes)
 
     def serve(self, requests, poll_s=0.0002):
@@ -121,8 +131,8 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         waiting = collections.deque()
         active = {}   # slot -> _Active
-        batch = {}    # rid -> _Active, the members of the batch
-        bstate = {"event": None}
+        batches = [{} for _ in self.batch_streams]  # per batch: rid -> _Active
+        bevent = [None for _ in self.batch_streams]
         free = list(range(self.max_active))[::-1]
         used = 0
         results = {}
@@ -132,10 +142,18 @@ class Server:
             return time.monotonic() - t0
 
         def note(ev, rid):
-            self.log.append((now(), ev, rid, len(active) + len(batch), used))
+            self.log.append((now(), ev, rid, len(active) + sum(len(b) for b in batches), used))
 
-        def batch_idle():
-            return bstate["event"] is None or bstate["event"].query()
+        def batch_idle(g):
+            return bevent[g] is None or bevent[g].query()
+
+        def batch_for_new():
+            """The idle batch with room and the fewest members, or None."""
+            best = None
+            for g, b in enumerate(batches):
+                if len(b) < self.max_batch and batch_idle(g) and (best is None or len(b) < len(batches[best])):
+                    best = g
+            return best
 
         def reject(req, res, msg):
             res.error, res.finished = msg, now()
@@ -180,15 +198,16 @@ class Server:
             stop = a.req.warmup if a.base is None and a.done < a.req.warmup else a.req.steps
             return min(k, stop - a.done)
 
-        while pending or waiting or active or batch:
+        while pending or waiting or active or any(batches):
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
             # admission, in arrival order
             while waiting:
                 req = waiting[0]
-                small = self.batch_stream is not None and int(req.params["n"]) <= self.batch_max_n
-                if small and (not batch_idle() or len(batch) >= self.max_batch):
+                small = bool(self.batch_streams) and int(req.params["n"]) <= self.batch_max_n
+                grp = batch_for_new() if small else None
+                if small and grp is None:
                     break
                 if not small and not free:
                     break
@@ -211,7 +230,7 @@ class Server:
                     break
                 waiting.popleft()
                 slot = -1 if small else free.pop()
-                stream = self.batch_stream if small else self.streams[slot]
+                stream = self.batch_streams[grp] if small else self.streams[slot]
                 try:
                     run = Run(req.params, stream=stream, device=self.device)
                     if req.state is not None:
@@ -226,7 +245,7 @@ class Server:
                 used += nb
                 res.admitted, res.nbytes = now(), nb
                 if small:
-                    batch[req.rid] = _Active(req, res, run, slot)
+                    batches[grp][req.rid] = _Active(req, res, run, slot)
                 else:
                     active[slot] = _Active(req, res, run, slot)
                 note("admit", req.rid)
@@ -256,33 +275,35 @@ class Server:
                 a.done += n
                 a.event = torch.cuda.Event()
                 a.event.record(self.streams[slot])
-            # progress of the batch: all its members at once, when idle
-            if batch and batch_idle():
+            # progress of each batch: all its members at once, when idle
+            for g, batch in enumerate(batches):
+                if not batch or not batch_idle(g):
+                    continue
                 moved = True
                 for rid in list(batch):
                     if checkpoint(batch[rid]):
                         del batch[rid]
                         note("finish", rid)
-                if batch:
-                    members = list(batch.values())
-                    n = min(next_steps(a) for a in members)
-                    try:
-                        step_batch([a.run for a in members], n, self.batch_stream)
-                    except EcrError as e:
-                        self.batch_stream.synchronize()
-                        batch.clear()
-                        for a in members:
-                            a.res.error = f"batch step failed: {e}"
-                            release(a)
-                            note("evict", a.req.rid)
-                        bstate["event"] = None
-                    else:
-                        for a in members:
-                            a.done += n
-                        bstate["event"] = torch.cuda.Event()
-                        bstate["event"].record(self.batch_stream)
+                if not batch:
+                    bevent[g] = None
+                    continue
+                members = list(batch.values())
+                n = min(next_steps(a) for a in members)
+                try:
+                    step_batch([a.run for a in members], n, self.batch_streams[g])
+                except EcrError as e:
+                    self.batch_streams[g].synchronize()
+                    batch.clear()
+                    bevent[g] = None
+                    for a in members:
+                        a.res.error = f"batch step failed: {e}"
+                        release(a)
+                        note("evict", a.req.rid)
                 else:
-                    bstate["event"] = None
+                    for a in members:
+                        a.done += n
+                    bevent[g] = torch.cuda.Event()
+                    bevent[g].record(self.batch_streams[g])
             if not moved:
                 time.sleep(poll_s)
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]

@@ -106,7 +106,8 @@ def test_batched_mix_with_large_requests():
         plain.close()
 
 
-def test_admission_by_footprint_and_errors():
+@pytest.mark.parametrize("batch_max_n", [0, 100_000])
+def test_admission_by_footprint_and_errors(batch_max_n):
     from paper_1507_03392_amd import footprint
     from paper_1507_03392_amd.serve import Request, Server
     reqs = _scan(n_req=5, steps=60)
@@ -117,11 +118,11 @@ def test_admission_by_footprint_and_errors():
     huge = W.base_params(4_000_000, 64, 64, 128, seed=7)
     bad = W.with_(reqs[0].params, dt=1e-3)  # rejected by the library (first-order MCC limit)
     reqs += [Request(rid=5, arrival=0.0, params=huge, steps=60), Request(rid=6, arrival=0.0, params=bad, steps=60)]
-    srv = Server(hbm_budget=budget, max_active=4)
+    srv = Server(hbm_budget=budget, max_active=4, batch_max_n=batch_max_n)
     out = srv.serve(reqs)
     assert sum(footprint(r.params) for r in reqs[:5]) > budget  # the budget binds
     assert all(e[4] <= budget for e in srv.log)
-    assert 2 <= max(e[3] for e in srv.log) < 5
+    assert 2 <= max(e[3] for e in srv.log) < 5  # the budget, not the slots, caps the batches
     assert out[5].error and "budget" in out[5].error
     assert out[6].error
     for r in out[:5]:
