@@ -451,13 +451,20 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
     const int np = (int)(tot & 0xffffu);
     ntri = (int)(tot >> 16);
     nitems = np + ntri;
+    // a triplet (three collisions in one lane) holds its wavefront three
+    // times as long as a pair: with two rounds of items, of which the second
+    // leaves the last wavefront idle, the triplets take that wavefront's
+    // first-round slots (the workgroup's longest wavefront then runs three
+    // collisions instead of four); else they come first
+    const int tbase = (nitems > kFB && nitems <= 2 * kFB - 64 && ntri <= 64) ? kFB - 64 : 0;
 #pragma unroll
     for (int k = 0; k < kFR; ++k) {
       const uint32_t before = (uint32_t)__builtin_amdgcn_readlane((int)excl, k * (kFB / 64) + wvu);
       if (lt[k]) {
         const int p = pos[k];
         const uint32_t a = ord[p], bb = ord[p + 1], cc = lt[k] == 2 ? ord[p + 2] : 0u;
-        const int slot = lt[k] == 2 ? (int)(before >> 16) + li[k] : ntri + (int)(before & 0xffffu) + li[k];
+        const int pi = (int)(before & 0xffffu) + li[k];  // pair number (pairs precede the triplets' block)
+        const int slot = lt[k] == 2 ? tbase + (int)(before >> 16) + li[k] : (pi < tbase ? pi : pi + ntri);
         items[slot] = make_item(a, bb, cc, (uint32_t)mm[k], lt[k] == 2);
       }
     }

@@ -83,7 +83,9 @@ def test_batched_mix_with_large_requests():
         p = W.base_params(n, 64, 64, 128, seed=200 + i, precision=W.PREC_FP32 if i % 2 else W.PREC_FP64)
         p.update(ne_in=float(rng.uniform(0.3, 2.5)) * 1e18, Te_in_eV=te)
         p["species"] = [W.argon(n0_m3=float(rng.uniform(3e16, 3e17)), te_ev=te)]
-        reqs.append(Request(rid=i, arrival=0.0 if i < 2 else 0.01 * i, params=p, steps=110,
+        # the large runs (600 steps, tens of ms) are still resident when the
+        # small ones arrive a millisecond apart
+        reqs.append(Request(rid=i, arrival=0.0 if i < 2 else 0.001 * i, params=p, steps=600 if i < 2 else 110,
                             warmup=30 if i in (1, 3) else 0))
     fields = (W.F_ION_N, W.F_ION_Q)
     srv = Server(hbm_budget=1 << 34, max_active=2, density_fields=fields, batch_max_n=100_000)
