@@ -345,6 +345,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   //    cell's, set at the sort)
   uint8_t qs[kFR];
   uint32_t id[kFR], key[kFR], bki[kFR];
+  R vr[kFR][3];  // the velocities, loaded here so that their latency overlaps the ordering
   double u[kFR];
   bool pool[kFR];
   const int nbuckets = coul ? (int)nbk[b] : 0;
@@ -360,6 +361,9 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
       const int j = i;
       qs[k] = S.qs[j];
       id[k] = S.pid[j];
+      vr[k][0] = S.vx[j];
+      vr[k][1] = S.vy[j];
+      vr[k][2] = S.vz[j];
       pool[k] = coul && q_of(qs[k]) >= 1;
       if (mcc || pool[k]) {
         const uint4 W = draw(P, id[k], step, S_STEP, 0);
@@ -475,10 +479,9 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
     if (i < nsl) {
-      const int j = i;
-      vs[i] = S.vx[j];
-      vs[kFMax + i] = S.vy[j];
-      vs[2 * kFMax + i] = S.vz[j];
+      vs[i] = vr[k][0];
+      vs[kFMax + i] = vr[k][1];
+      vs[2 * kFMax + i] = vr[k][2];
     }
   }
   if (coul) {
