@@ -48,9 +48,10 @@ __device__ __forceinline__ double wave_sum_last(double x) {
 }
 
 // in-place exclusive scan of a[0..L) by a workgroup of NT lanes; returns the
-// total (wsum: NT / 64 words of LDS)
+// total, also stored in a[L] when store_total (wsum: NT / 64 words of LDS);
+// a, a[L] included, is complete for every lane on return
 template <int NT>
-__device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum) {
+__device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum, bool store_total = false) {
   const int tid = threadIdx.x;
   const int per = (L + NT - 1) / NT;
   const int b = tid * per, e = min(b + per, L);
@@ -71,6 +72,7 @@ __device__ __forceinline__ uint32_t wg_exscan(uint32_t *a, int L, uint32_t *wsum
     a[i] = run;
     run += v;
   }
+  if (store_total && tid == 0) a[L] = tot;
   __syncthreads();
   return tot;
 }

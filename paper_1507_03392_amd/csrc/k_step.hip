@@ -60,14 +60,15 @@ static_assert(kFMax > kFCap, "a chunk fits the fast path unless one of its cells
 static_assert(kFLead <= 64, "per-wave counts fit one wavefront");
 
 // LDS layout in bytes.  Ordering (steps 1-2): skey, the bucket histogram,
-// members by bucket then by pool position.  Collisions (steps 3-5): the velocities over
+// members by bucket, members by pool position.  Collisions (steps 3-5): the velocities over
 // the ordering arrays, the work items beyond both.  Ids and charges (steps
 // 1-4) beyond all of these.  Deposit (steps 6-7): the staging and brick over
 // everything.
 constexpr int kSkeyOff = 0;
 constexpr int kR1Off = kSkeyOff + 8 * kFMax;
 constexpr int kOrdOff = kR1Off + 4 * (kFMax + 2);
-constexpr int kOrdEnd = kOrdOff + 2 * kFMax;
+constexpr int kPordOff = kOrdOff + 2 * kFMax;
+constexpr int kOrdEnd = kPordOff + 2 * kFMax;
 constexpr int align16(int v) { return (v + 15) / 16 * 16; }
 template <typename R>
 constexpr int items_off() {
@@ -335,6 +336,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   uint64_t *skey = reinterpret_cast<uint64_t *>(lds + kSkeyOff);
   uint32_t *hist = reinterpret_cast<uint32_t *>(lds + kR1Off);
   uint16_t *ord = reinterpret_cast<uint16_t *>(lds + kOrdOff);
+  uint16_t *pord = reinterpret_cast<uint16_t *>(lds + kPordOff);
   R *vs = reinterpret_cast<R *>(lds);
   uint64_t *items = reinterpret_cast<uint64_t *>(lds + items_off<R>());
   uint32_t *sid = reinterpret_cast<uint32_t *>(lds + sid_off<R>());
@@ -395,9 +397,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
     }
     __syncthreads();
     // 2d. bucket offsets; members listed bucket by bucket
-    const int npool = (int)wg_exscan<kFB>(hist, nbuckets, wsum);
-    if (tid == 0) hist[nbuckets] = (uint32_t)npool;
-    __syncthreads();
+    (void)wg_exscan<kFB>(hist, nbuckets, wsum, true);  // hist[nbuckets] = pool total
 #pragma unroll
     for (int k = 0; k < kFR; ++k) {
       const int i = tid + k * kFB;
@@ -422,11 +422,11 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
         rr[k] = pos[k] - pstart;
       }
     }
-    __syncthreads();
-    // 2f. pool order, and the pair and triplet leaders per round and wave
+    // 2f. pool order (in its own array: other wavefronts may still read the
+    // bucket lists), and the pair and triplet leaders per round and wave
 #pragma unroll
     for (int k = 0; k < kFR; ++k)
-      if (pool[k]) ord[pos[k]] = (uint16_t)(tid + k * kFB);
+      if (pool[k]) pord[pos[k]] = (uint16_t)(tid + k * kFB);
     const int nk = (nsl + kFB - 1) / kFB;  // rounds that hold slots
     int lt[kFR], li[kFR];
 #pragma unroll
@@ -466,7 +466,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
       const uint32_t before = (uint32_t)__builtin_amdgcn_readlane((int)excl, k * (kFB / 64) + wvu);
       if (lt[k]) {
         const int p = pos[k];
-        const uint32_t a = ord[p], bb = ord[p + 1], cc = lt[k] == 2 ? ord[p + 2] : 0u;
+        const uint32_t a = pord[p], bb = pord[p + 1], cc = lt[k] == 2 ? pord[p + 2] : 0u;
         const int pi = (int)(before & 0xffffu) + li[k];  // pair number (pairs precede the triplets' block)
         const int slot = lt[k] == 2 ? tbase + (int)(before >> 16) + li[k] : (pi < tbase ? pi : pi + ntri);
         items[slot] = make_item(a, bb, cc, (uint32_t)mm[k], lt[k] == 2);
