@@ -40,11 +40,11 @@ sort periods replay as one captured graph).  A batch takes new members (a reques
 with the fewest members) and retires finished ones between its launches, up
 to max_batch runs; several batches keep the GPU busy while one of them turns
 around on the host.  Members' results are the same as alone.  Measured on
-one MI355X: a flood of 10k-100k requests is served 13% faster batched
+one MI355X: a flood of 10k-100k requests is served 15% faster batched
 (batch_max_n = 100 000), while the scan trace of 10k-2M requests, whose work
 is mostly in large runs with slots of their own, is served as fast either
-way and with a lower median latency without batches (a small request waits
-for a batch's launch to end before it joins).
+way, and above capacity with a lower median latency without batches (a
+small request waits for a batch's launch to end before it joins).
 """
 from __future__ import annotations
 
