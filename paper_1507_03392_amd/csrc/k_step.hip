@@ -59,16 +59,15 @@ static_assert(kFR == kP, "the deposit stages one tile of kP slots per lane: the 
 static_assert(kFMax > kFCap, "a chunk fits the fast path unless one of its cells is large");
 static_assert(kFLead <= 64, "per-wave counts fit one wavefront");
 
-// LDS layout in bytes.  Ordering (steps 1-2): skey, the bucket histogram,
-// members by bucket, members by pool position.  Collisions (steps 3-5): the velocities over
-// the ordering arrays, the work items beyond both.  Ids and charges (steps
-// 1-4) beyond all of these.  Deposit (steps 6-7): the staging and brick over
-// everything.
-constexpr int kSkeyOff = 0;
-constexpr int kR1Off = kSkeyOff + 8 * kFMax;
+// LDS layout in bytes.  Ordering (steps 1-2): the members' (key, id) by
+// bucket, the bucket histogram, the members by pool position.  Collisions
+// (steps 3-5): the velocities over the ordering arrays, the work items beyond
+// both.  Ids and charges (steps 1-4) beyond all of these.  Deposit (steps
+// 6-7): the staging and brick over everything.
+constexpr int kBkeyOff = 0;
+constexpr int kR1Off = kBkeyOff + 8 * kFMax;
 constexpr int kOrdOff = kR1Off + 4 * (kFMax + 2);
-constexpr int kPordOff = kOrdOff + 2 * kFMax;
-constexpr int kOrdEnd = kPordOff + 2 * kFMax;
+constexpr int kOrdEnd = kOrdOff + 2 * kFMax;
 constexpr int align16(int v) { return (v + 15) / 16 * 16; }
 template <typename R>
 constexpr int items_off() {
@@ -333,10 +332,9 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const bool coul = (P.pmask & P_COULOMB) != 0 && nsl >= 2;
   const bool mcc = needs_mcc_uniform(P);
-  uint64_t *skey = reinterpret_cast<uint64_t *>(lds + kSkeyOff);
+  uint64_t *bkey = reinterpret_cast<uint64_t *>(lds + kBkeyOff);
   uint32_t *hist = reinterpret_cast<uint32_t *>(lds + kR1Off);
-  uint16_t *ord = reinterpret_cast<uint16_t *>(lds + kOrdOff);
-  uint16_t *pord = reinterpret_cast<uint16_t *>(lds + kPordOff);
+  uint16_t *pord = reinterpret_cast<uint16_t *>(lds + kOrdOff);
   R *vs = reinterpret_cast<R *>(lds);
   uint64_t *items = reinterpret_cast<uint64_t *>(lds + items_off<R>());
   uint32_t *sid = reinterpret_cast<uint32_t *>(lds + sid_off<R>());
@@ -374,7 +372,6 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
       }
       if (coul) {
         bki[k] = bkinfo[j];
-        skey[i] = ((uint64_t)key[k] << 32) | id[k];
         sid[i] = id[k];
         sqs[i] = qs[k];
       }
@@ -396,25 +393,22 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
       }
     }
     __syncthreads();
-    // 2d. bucket offsets; members listed bucket by bucket
+    // 2d. bucket offsets; the members' (key, id) listed bucket by bucket
     (void)wg_exscan<kFB>(hist, nbuckets, wsum, true);  // hist[nbuckets] = pool total
 #pragma unroll
-    for (int k = 0; k < kFR; ++k) {
-      const int i = tid + k * kFB;
-      if (pool[k]) ord[hist[bk[k]] + arr[k]] = (uint16_t)i;
-    }
+    for (int k = 0; k < kFR; ++k)
+      if (pool[k]) bkey[hist[bk[k]] + arr[k]] = ((uint64_t)key[k] << 32) | id[k];
     __syncthreads();
     // 2e. exact pool position: bucket offset + bucket mates of smaller (key, id)
     int pos[kFR], rr[kFR], mm[kFR];
 #pragma unroll
     for (int k = 0; k < kFR; ++k) {
-      const int i = tid + k * kFB;
       pos[k] = rr[k] = mm[k] = 0;
       if (pool[k]) {
-        const uint64_t me = skey[i];
+        const uint64_t me = ((uint64_t)key[k] << 32) | id[k];
         const int b0 = (int)hist[bk[k]], b1 = (int)hist[bk[k] + 1];
         int rib = 0;
-        for (int t = b0; t < b1; ++t) rib += skey[ord[t]] < me ? 1 : 0;
+        for (int t = b0; t < b1; ++t) rib += bkey[t] < me ? 1 : 0;
         pos[k] = b0 + rib;
         const int c0 = (int)(bki[k] & 0xffffu);
         const int pstart = (int)hist[c0];
@@ -422,8 +416,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
         rr[k] = pos[k] - pstart;
       }
     }
-    // 2f. pool order (in its own array: other wavefronts may still read the
-    // bucket lists), and the pair and triplet leaders per round and wave
+    // 2f. pool order, and the pair and triplet leaders per round and wave
 #pragma unroll
     for (int k = 0; k < kFR; ++k)
       if (pool[k]) pord[pos[k]] = (uint16_t)(tid + k * kFB);
