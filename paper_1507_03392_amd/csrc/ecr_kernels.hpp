@@ -15,11 +15,13 @@ namespace ecr {
 constexpr int kCoulCap = 256;
 constexpr int kCoulMaxE = 1024;
 // the fused step kernel's chunks: the cells whose first sorted slot falls in
-// [b*cap, (b+1)*cap), cap = step_fcap(n) (kFCap from 98 304 particles up;
-// smaller runs get smaller chunks, down to 64 slots, so that they still
-// spread over the CUs); a chunk of at most 1024 slots is stepped by its own
-// workgroup, a larger one by a handler workgroup
+// [b*cap, (b+1)*cap), cap = step_fcap(n, resident) (kFCap or kFCapLo from
+// 98 304 particles up, whichever fills the last round of resident
+// workgroups more; smaller runs get smaller chunks, down to 64 slots, so that
+// they still spread over the CUs); a chunk of at most 1024 slots is stepped
+// by its own workgroup, a larger one by a handler workgroup
 constexpr int kFCap = 768;
+constexpr int kFCapLo = 736;
 
 static_assert(kBirthNone == ECR_BIRTH_NONE, "birth sentinel");
 
@@ -107,8 +109,13 @@ void launch_sum_moments(const double *moments, int64_t nslots, DevAccum *acc, hi
 // tabulates the ordering's buckets of every other chunk: per slot
 // (bkinfo[n]) first bucket | log2(bucket count) << 16 of its cell, per chunk
 // (nbk[nchunks]) the bucket total.
-int64_t step_fcap(int64_t n);
+// resident: the step workgroups the device holds at once (step_resident_wgs;
+// 0 when unknown)
+int64_t step_fcap(int64_t n, int64_t resident);
 int64_t step_nchunks(int64_t n, int64_t cap);
+// the most chunks step_fcap can give n particles (the tables' size)
+int64_t step_nchunks_max(int64_t n);
+int64_t step_resident_wgs(bool fp32);
 // moment slots the fused step writes (one per wavefront of a chunk)
 int64_t step_moment_slots(int64_t n);
 void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, int64_t cap, uint32_t *big,

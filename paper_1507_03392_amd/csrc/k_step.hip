@@ -663,16 +663,43 @@ __global__ void k_big_list(const uint32_t *__restrict__ chunk_lo, int64_t nchunk
 // chunk's deposit box fits the LDS brick more often).  Chunks smaller than
 // kFCap cost more per particle where the GPU is full anyway (fewer pairs per
 // workgroup, more fixed work per chunk), hence kFCap from 98 304 particles.
-int64_t step_fcap(int64_t n) {
-  if (n >= 128 * (int64_t)kFCap) return kFCap;
-  int64_t p = 64;
-  while (2 * p <= n / 128 && 2 * p <= 512) p *= 2;
-  return p;
-}
-
 int64_t step_nchunks(int64_t n, int64_t cap) { return (n + cap - 1) / cap; }
 
-int64_t step_moment_slots(int64_t n) { return step_nchunks(n, step_fcap(n)) * (kFB / 64); }
+// The last of the rounds in which the device's resident workgroups take the
+// launch's workgroups is partly empty: chunks of kFCapLo slots instead of
+// kFCap, where that fills the last round more, cut the idle share of it (at
+// 2M particles on 1024 resident workgroups, 2722 workgroups fill 66% of the
+// third round where 2609 fill 55%, and the step runs 1.3% faster; at 10M,
+// 13025 fill 72% of the thirteenth where 13591 would fill 27%).
+int64_t step_fcap(int64_t n, int64_t resident) {
+  if (n < 128 * (int64_t)kFCap) {
+    int64_t p = 64;
+    while (2 * p <= n / 128 && 2 * p <= 512) p *= 2;
+    return p;
+  }
+  if (resident <= 0) return kFCap;
+  const auto fill = [&](int64_t cap) {
+    const int64_t r = (step_nchunks(n, cap) + kBigWG) % resident;
+    return r == 0 ? resident : r;  // workgroups in the last round
+  };
+  return fill(kFCapLo) > fill(kFCap) ? kFCapLo : kFCap;
+}
+
+int64_t step_nchunks_max(int64_t n) {
+  return step_nchunks(n, n < 128 * (int64_t)kFCap ? step_fcap(n, 0) : (int64_t)kFCapLo);
+}
+
+int64_t step_moment_slots(int64_t n) { return step_nchunks_max(n) * (kFB / 64); }
+
+int64_t step_resident_wgs(bool fp32) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<float, 2, false>, kFB, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<double, 2, false>, kFB, 0);
+  if (e != hipSuccess) return 0;
+  return (int64_t)cus * per;
+}
 
 void launch_step_prep(const uint32_t *cellid, const uint32_t *chunk_lo, int64_t n, int64_t cap, uint32_t *big,
                       uint32_t *bkinfo,

@@ -84,11 +84,11 @@ Layout make_layout(const ecr_params *p) {
   L.chunks = o;
   o = align_up(o + 4 * (size_t)(coul_nchunks((int64_t)N) + 2));
   L.fchunks = o;
-  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N, step_fcap((int64_t)N)) + 2));
+  o = align_up(o + 4 * (size_t)(step_nchunks_max((int64_t)N) + 2));
   L.big = o;
-  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N, step_fcap((int64_t)N)) + 1));
+  o = align_up(o + 4 * (size_t)(step_nchunks_max((int64_t)N) + 1));
   L.nbk = o;
-  o = align_up(o + 4 * (size_t)(step_nchunks((int64_t)N, step_fcap((int64_t)N)) + 1));
+  o = align_up(o + 4 * (size_t)(step_nchunks_max((int64_t)N) + 1));
   L.scratch64 = o;
   o = align_up(o + 8 * N);
   L.pairs = o;
@@ -230,6 +230,7 @@ struct ecr_run {
   char *base;
   Layout L;
   bool fp32;
+  int64_t fcap;  // the fused step's chunk size (step_fcap)
   double weight;
   int64_t ncell, nnode;
   int64_t step;
@@ -545,9 +546,9 @@ void do_sort(ecr_run *r, const uint32_t *given) {
                        at<uint32_t>(r, r->L.chunks), kCoulCap, r->stream);
     if (fused(r)) {
       launch_coul_chunks(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.cell_off), r->kp.n,
-                         at<uint32_t>(r, r->L.fchunks), step_fcap(r->kp.n), r->stream);
+                         at<uint32_t>(r, r->L.fchunks), r->fcap, r->stream);
       // the per-slot buckets go into the sort's rank array, free until the next sort
-      launch_step_prep(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks), r->kp.n, step_fcap(r->kp.n),
+      launch_step_prep(at<uint32_t>(r, r->L.cellid), at<uint32_t>(r, r->L.fchunks), r->kp.n, r->fcap,
                        at<uint32_t>(r, r->L.big), at<uint32_t>(r, r->L.rank), at<uint32_t>(r, r->L.nbk), r->stream);
     }
   }
@@ -580,7 +581,7 @@ void do_step(ecr_run *r, StepArg stepw) {
                      at<uint32_t>(r, r->L.big), at<uint32_t>(r, r->L.rank), at<uint32_t>(r, r->L.nbk),
                      (r->p.flags & ECR_FLAG_EVENTS) ? at<uint8_t>(r, r->L.evlog) : nullptr,
                      acc, (pm & ECR_P_DEPOSIT) ? at<double>(r, r->L.dens) : nullptr, at<double>(r, r->L.moments),
-                     at<uint64_t>(r, r->L.scratch64), stepw, chg_cur, chg_next, step_fcap(r->kp.n), r->stream);
+                     at<uint64_t>(r, r->L.scratch64), stepw, chg_cur, chg_next, r->fcap, r->stream);
     }
     step_tail<R>(r, stepw, grids);
     return;
@@ -691,7 +692,7 @@ void batch_step(const std::vector<ecr_run *> &rs, const std::vector<StepArg> &sa
       B.job[j] = at<StepJob<R>>(r, r->L.job) + r->cur;
       B.stepw[j] = sa[k0 + j].base;
       B.step[j] = sa[k0 + j].off;
-      B.wg0[j + 1] = B.wg0[j] + step_batch_wgs(r->kp.n, step_fcap(r->kp.n));
+      B.wg0[j + 1] = B.wg0[j] + step_batch_wgs(r->kp.n, r->fcap);
     }
     launch_step_batch<R>(B, st);
   }
@@ -926,6 +927,7 @@ ecr_status init_run(ecr_run *r, const ecr_params *params, const Layout &L, const
   r->base = (char *)(((uintptr_t)device_arena + kAlign - 1) / kAlign * kAlign);
   r->L = L;
   r->fp32 = params->precision == ECR_FP32_MIXED;
+  r->fcap = step_fcap(K.n, step_resident_wgs(r->fp32));
   r->weight = w;
   r->ncell = ncells(params);
   r->nnode = nnodes(params);
