@@ -448,20 +448,13 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
     const int np = (int)(tot & 0xffffu);
     ntri = (int)(tot >> 16);
     nitems = np + ntri;
-    // a triplet (three collisions in one lane) holds its wavefront three
-    // times as long as a pair: with two rounds of items, of which the second
-    // leaves the last wavefront idle, the triplets take that wavefront's
-    // first-round slots (the workgroup's longest wavefront then runs three
-    // collisions instead of four); else they come first
-    const int tbase = (nitems > kFB && nitems <= 2 * kFB - 64 && ntri <= 64) ? kFB - 64 : 0;
 #pragma unroll
     for (int k = 0; k < kFR; ++k) {
       const uint32_t before = (uint32_t)__builtin_amdgcn_readlane((int)excl, k * (kFB / 64) + wvu);
       if (lt[k]) {
         const int p = pos[k];
         const uint32_t a = pord[p], bb = pord[p + 1], cc = lt[k] == 2 ? pord[p + 2] : 0u;
-        const int pi = (int)(before & 0xffffu) + li[k];  // pair number (pairs precede the triplets' block)
-        const int slot = lt[k] == 2 ? tbase + (int)(before >> 16) + li[k] : (pi < tbase ? pi : pi + ntri);
+        const int slot = lt[k] == 2 ? (int)(before >> 16) + li[k] : ntri + (int)(before & 0xffffu) + li[k];
         items[slot] = make_item(a, bb, cc, (uint32_t)mm[k], lt[k] == 2);
       }
     }
@@ -479,21 +472,62 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   }
   if (coul) {
     __syncthreads();
-    // 4. collisions, one work item per lane
+    // 4. collisions, one binary collision per lane and iteration: a triplet
+    //    is three collisions in a row in its lane, a pair one.  The triplets
+    //    fill the first wavefronts one to a lane, the spare lanes of the last
+    //    of these take up to three pairs each, one after the other, and the
+    //    other wavefronts take the remaining pairs round-robin, so a
+    //    wavefront with a triplet runs three collisions.  (With more than
+    //    three wavefronts of triplets, every item goes round-robin.)  Pairs
+    //    are disjoint, so the order changes no particle.
+    int first, count, stride;
+    {
+      const int np = nitems - ntri;
+      if (ntri > kFB - 64) {
+        first = tid;
+        stride = kFB;
+        count = tid < nitems ? (nitems - 1 - tid) / kFB + 1 : 0;
+      } else {
+        const int l3 = (ntri + 63) & ~63;         // lanes of the triplet wavefronts
+        const int n3 = min(np, 3 * (l3 - ntri));  // pairs taken three to a lane
+        if (tid < ntri) {
+          first = tid;
+          count = 1;
+          stride = 1;
+        } else if (tid < l3) {
+          const int q = 3 * (tid - ntri);
+          first = ntri + q;
+          count = max(0, min(3, n3 - q));
+          stride = 1;
+        } else {
+          const int q = tid - l3;
+          stride = kFB - l3;
+          first = ntri + n3 + q;
+          count = q < np - n3 ? (np - n3 - 1 - q) / stride + 1 : 0;
+        }
+      }
+    }
+    // the lane's collisions: three per triplet item (items below ntri), one per pair
+    int ncol = 0;
+    for (int k = 0; k < count; ++k) ncol += first + k * stride < ntri ? 3 : 1;
     double cacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const LdsAcc<R> A{vs, sqs};
-    for (int it = tid; it < nitems; it += kFB) {
-      const uint64_t e = items[it];
+    int k = 0, sub = 0;  // the lane's item, and the collision within a triplet
+    for (int c = 0; c < ncol; ++c) {
+      const uint64_t e = items[first + k * stride];
+      const bool tri = ((e >> 44) & 1u) != 0;
       const uint32_t a = (uint32_t)(e & 0x7ff), bb = (uint32_t)((e >> 11) & 0x7ff);
+      const uint32_t cc = (uint32_t)((e >> 22) & 0x7ff);
+      // a triplet's collisions (a, b), (b, c), (c, a) at dt/2; the energy of
+      // the pool before counts each member once
+      const uint32_t ia = sub == 0 ? a : (sub == 1 ? bb : cc), ib = sub == 0 ? bb : (sub == 1 ? cc : a);
       const double nc = (double)((e >> 33) & 0x7ff) * P.nfac;
-      if ((e >> 44) & 1u) {
-        const uint32_t cc = (uint32_t)((e >> 22) & 0x7ff);
-        const double h = 0.5 * P.dt;
-        collide_acc<R>(P, T->lnA, A, a, bb, sid[a], nc, h, step, cacc, true, true);
-        collide_acc<R>(P, T->lnA, A, bb, cc, sid[bb], nc, h, step, cacc, false, true);
-        collide_acc<R>(P, T->lnA, A, cc, a, sid[cc], nc, h, step, cacc, false, false);
+      collide_acc<R>(P, T->lnA, A, ia, ib, sid[ia], nc, tri ? 0.5 * P.dt : P.dt, step, cacc, sub == 0, sub < 2);
+      if (tri && sub < 2) {
+        ++sub;
       } else {
-        collide_acc<R>(P, T->lnA, A, a, bb, sid[a], nc, P.dt, step, cacc, true, true);
+        sub = 0;
+        ++k;
       }
     }
     flush_moments(cacc, moments + (b * (kFB / 64) + wv) * 5);
