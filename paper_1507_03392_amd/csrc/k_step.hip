@@ -66,6 +66,7 @@ static_assert(kFLead <= 64, "per-wave counts fit one wavefront");
 // 6-7): the staging and brick over everything.
 constexpr int kBkeyOff = 0;
 constexpr int kR1Off = kBkeyOff + 8 * kFMax;
+static_assert(kR1Off + 4 * (kFMax + 2) >= kBkeyOff + 8 * (kFMax + 3), "a bucket's batch of four keys stays in the arrays");
 constexpr int kOrdOff = kR1Off + 4 * (kFMax + 2);
 constexpr int kOrdEnd = kOrdOff + 2 * kFMax;
 constexpr int align16(int v) { return (v + 15) / 16 * 16; }
@@ -407,8 +408,14 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
       if (pool[k]) {
         const uint64_t me = ((uint64_t)key[k] << 32) | id[k];
         const int b0 = (int)hist[bk[k]], b1 = (int)hist[bk[k] + 1];
-        int rib = 0;
-        for (int t = b0; t < b1; ++t) rib += bkey[t] < me ? 1 : 0;
+        // the bucket's first four entries in one batch of loads (a bucket
+        // holds one or two members mostly; entries past its end are masked,
+        // and b0 + 3 stays inside the histogram that follows the keys), the
+        // rest one by one
+        const uint64_t q0 = bkey[b0], q1 = bkey[b0 + 1], q2 = bkey[b0 + 2], q3 = bkey[b0 + 3];
+        int rib = (q0 < me ? 1 : 0) + (b0 + 1 < b1 && q1 < me ? 1 : 0) + (b0 + 2 < b1 && q2 < me ? 1 : 0) +
+                  (b0 + 3 < b1 && q3 < me ? 1 : 0);
+        for (int t = b0 + 4; t < b1; ++t) rib += bkey[t] < me ? 1 : 0;
         pos[k] = b0 + rib;
         const int c0 = (int)(bki[k] & 0xffffu);
         const int pstart = (int)hist[c0];
