@@ -828,3 +828,36 @@ def test_coulomb_in_a_cell_crowded_with_atoms():
     assert tg["coul_e"] == pytest.approx(to["coul_e"], rel=1e-12)
     moved = (a["vx"][3000:k] != st["vx"][3000:k]).mean()
     assert moved > 0.9  # the crowded cell's ions did collide
+
+
+@pytest.mark.parametrize("m,mesh", [(3, (32, 32, 32)), (5, (24, 24, 36)), (7, (20, 20, 36))])
+def test_coulomb_chunks_of_odd_pools(m, mesh):
+    # every cell holds m ions, so every pool is odd: with 736-slot chunks
+    # (from 98 304 particles up) a chunk of 3-ion cells holds about 245
+    # triplets, more than three wavefronts of them (every item
+    # round-robin); 5- and 7-ion cells give 147 and 105 triplets, whose
+    # wavefronts' spare lanes take pairs three at a time before the other
+    # wavefronts take the rest; bit for bit against the oracle
+    nx, ny, nz = mesh
+    n = m * nx * ny * nz
+    assert n >= 128 * 768
+    params = W.base_params(n, nx, ny, nz, seed=17)
+    params.update(process_mask=W.P_COULOMB, weight=2e9)
+    st = W.random_state(params, seed=71, q_max=8, v_ev=5.0, frac_atoms=0.0)
+    rng = np.random.default_rng(72)
+    hx, hy, hz = 2 * params["R0"] / nx, 2 * params["R0"] / ny, params["L"] / nz
+    c = np.repeat(np.arange(nx * ny * nz), m)
+    ix, iy, iz = c % nx, (c // nx) % ny, c // (nx * ny)
+    st["x"][:] = -params["R0"] + (ix + 0.2 + 0.6 * rng.random(n)) * hx
+    st["y"][:] = -params["R0"] + (iy + 0.2 + 0.6 * rng.random(n)) * hy
+    st["z"][:] = -params["L"] / 2 + (iz + 0.2 + 0.6 * rng.random(n)) * hz
+    st["q"][:] = rng.integers(1, 9, n)
+    g, o = run_pair(params, st, 1, step0=5)
+    a, b = g.get_state(), o.get_state()
+    assert_state_close(a, b, params, what=f"cells of {m} ions")
+    assert (np.bincount(b["cell"].astype(np.int64), minlength=nx * ny * nz) == m).all()
+    tg, to = g.tallies(), o.tallies()
+    assert tg["anomalies"] == 0
+    assert tg["coul_e"] == pytest.approx(to["coul_e"], rel=1e-12)
+    assert abs(tg["coul_de"]) <= 1e-12 * tg["coul_e"]
+    assert (a["vx"] != st["vx"]).mean() > 0.95  # every pool collided
