@@ -53,7 +53,8 @@ def describe(name, p):
         ne += ", each charge exchange ionises a tracked atom"
     return (f"{name}: {p['n']} ions, {mix}, born Q=1 in the ECR-zone ellipsoid, {prec}, {ne}, "
             f"mesh {p['nx']}x{p['ny']}x{p['nz']}, dt {p['dt']:g} s, sort every {p['sort_every']}, "
-            f"all processes on" + (", with the electron-ion heating kick" if p["process_mask"] & 32 else ""))
+            + ("all processes on" if (p["process_mask"] & 31) == 31 else f"process mask {p['process_mask']}")
+            + (", with the electron-ion heating kick" if p["process_mask"] & 32 else ""))
 
 # algorithmic HBM bytes per particle per launch (FP64 structure of arrays:
 # x y z vx vy vz 8 B each, qs 1 B, pid 4 B, birth step 4 B (moved by the sort
@@ -288,6 +289,9 @@ def main():
                     help="neutral gas of charge exchange and elastic scattering from the tracked atoms per cell")
     ap.add_argument("--pressure", action="store_true",
                     help="also deposit the ion pressure moment (its own kernel after the step)")
+    ap.add_argument("--process-mask", type=int, default=None,
+                    help="run only the processes in this mask (push 1, ionisation 2, exchange 4, Coulomb 8, "
+                         "deposit 16): a profiling aid for counters by process, not the benchmark's step")
     ap.add_argument("--heat", action="store_true",
                     help="add the electron-ion heating kick (diamagnetic bias with --self-ne)")
     ap.add_argument("--fp64", action="store_true", help="c5: serve the scan in FP64 instead of FP32-mixed")
@@ -334,6 +338,8 @@ def main():
     params, _ = W.config(args.workload)
     if args.self_ne:
         params["self_ne"] = True
+    if args.process_mask is not None:
+        params["process_mask"] = args.process_mask
     if args.heat:
         params["process_mask"] |= ecr.P_HEAT
     if args.pressure:
@@ -409,7 +415,8 @@ def main():
     step_frac = step_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS
     # the counters were taken on the default step (fixed electron background,
     # no optional physics, fused deposit): another configuration runs other code
-    default_step = not (args.self_ne or args.heat or args.split or args.self_n0 or args.cx_partner or args.pressure)
+    default_step = not (args.self_ne or args.heat or args.split or args.self_n0 or args.cx_partner or args.pressure
+                        or args.process_mask is not None)
     traffic = measured_traffic(args.workload, dom) if default_step else None
 
     drift = None
