@@ -4,8 +4,8 @@
 // ionisation or charge exchange, and the cloud-in-cell deposit.
 //
 // One workgroup (four wavefronts) owns a chunk of whole collision cells: the
-// cells whose first sorted slot lies in [b*kFCap, (b+1)*kFCap) (table rebuilt
-// at every sort).
+// cells whose first sorted slot lies in [b*c, (b+1)*c), c the run's chunk
+// size (step_fcap; the table is rebuilt at every sort).
 // Cells never straddle chunks and nothing couples two cells within a step
 // except the density grid and the tallies (atomics), so each chunk is
 // stepped start to finish by its workgroup and the state is read once and
@@ -21,9 +21,11 @@
 //     smaller (key, id); pair leaders (and odd pools' triplet leaders)
 //     write their work items to LDS, triplets first;
 //  3. the velocities go to LDS;
-//  4. one lane per work item collides the pair (or the triplet's three
-//     pairs at dt/2, in order) in LDS; momentum and energy sums go to one
-//     slot per wavefront of the chunk;
+//  4. the collisions in LDS, one binary collision per lane and iteration (a
+//     pair is one, a triplet three in a row at dt/2 in its lane; triplets
+//     one to a lane in the first wavefronts, whose spare lanes take pairs
+//     three at a time); momentum and energy sums go to one slot per
+//     wavefront of the chunk;
 //  5-6. lane = slot again: positions are loaded, the velocities read back
 //     from LDS, each particle is pushed,
 //     tested against the walls and the aperture, and draws its ionisation /
