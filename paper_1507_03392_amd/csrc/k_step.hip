@@ -353,31 +353,45 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   bool pool[kFR];
   const int nbuckets = coul ? (int)nbk[b] : 0;
   for (int i = tid; i <= nbuckets; i += kFB) hist[i] = 0u;
+  // every round's loads go out before any is used (indices clamped to the
+  // chunk, so that no load waits behind a branch): ids, charges and bucket
+  // words first, the velocities last, so that the draws and the ordering
+  // wait only for the former (the memory counter drains in issue order) and
+  // the velocities arrive during the ordering
+  int jc[kFR];
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) jc[k] = min(tid + k * kFB, nsl - 1);
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) id[k] = S.pid[jc[k]];
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) qs[k] = S.qs[jc[k]];
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) bki[k] = coul ? bkinfo[jc[k]] : 0u;
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) {
+    vr[k][0] = S.vx[jc[k]];
+    vr[k][1] = S.vy[jc[k]];
+    vr[k][2] = S.vz[jc[k]];
+  }
 #pragma unroll
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
-    qs[k] = 0;
-    id[k] = key[k] = bki[k] = 0u;
+    const bool in = i < nsl;
+    if (!in) {
+      qs[k] = 0;
+      id[k] = bki[k] = 0u;
+    }
+    key[k] = 0u;
     u[k] = 0.0;
-    pool[k] = false;
-    if (i < nsl) {
-      const int j = i;
-      qs[k] = S.qs[j];
-      id[k] = S.pid[j];
-      vr[k][0] = S.vx[j];
-      vr[k][1] = S.vy[j];
-      vr[k][2] = S.vz[j];
-      pool[k] = coul && q_of(qs[k]) >= 1;
-      if (mcc || pool[k]) {
-        const uint4 W = draw(P, id[k], step, S_STEP, 0);
-        u[k] = u53(W.x, W.y);
-        key[k] = W.z;
-      }
-      if (coul) {
-        bki[k] = bkinfo[j];
-        sid[i] = id[k];
-        sqs[i] = qs[k];
-      }
+    pool[k] = in && coul && q_of(qs[k]) >= 1;
+    if (in && (mcc || pool[k])) {
+      const uint4 W = draw(P, id[k], step, S_STEP, 0);
+      u[k] = u53(W.x, W.y);
+      key[k] = W.z;
+    }
+    if (coul && in) {
+      sid[i] = id[k];
+      sqs[i] = qs[k];
     }
   }
   int nitems = 0, ntri = 0;
@@ -553,6 +567,16 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   DepShared<R, kFMax> &dsh = *reinterpret_cast<DepShared<R, kFMax> *>(lds);
   __syncthreads();  // collisions done (the staged cells go over the items)
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
+  // every round's positions first (indices clamped to the chunk): one memory
+  // latency for all rounds instead of one per round
+  R xr[kFR][3];
+#pragma unroll
+  for (int k = 0; k < kFR; ++k) {
+    const int j = min(tid + k * kFB, nsl - 1);
+    xr[k][0] = S.x[j];
+    xr[k][1] = S.y[j];
+    xr[k][2] = S.z[j];
+  }
 #pragma unroll
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
@@ -561,7 +585,7 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
     if (i >= nsl) {
       if (DEP) dsh.st.q[i] = 0xFF;
     } else {
-      R x = S.x[j], y = S.y[j], z = S.z[j];
+      R x = xr[k][0], y = xr[k][1], z = xr[k][2];
       R vx = vs[i], vy = vs[kFMax + i], vz = vs[2 * kFMax + i];
       int Q = q_of(qs[k]);
       const int s = sp_of(qs[k]);
