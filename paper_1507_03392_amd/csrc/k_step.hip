@@ -351,13 +351,12 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
   R vr[kFR][3];  // the velocities, loaded here so that their latency overlaps the ordering
   double u[kFR];
   bool pool[kFR];
-  const int nbuckets = coul ? (int)nbk[b] : 0;
-  for (int i = tid; i <= nbuckets; i += kFB) hist[i] = 0u;
   // every round's loads go out before any is used (indices clamped to the
   // chunk, so that no load waits behind a branch): ids, charges and bucket
   // words first, the velocities last, so that the draws and the ordering
   // wait only for the former (the memory counter drains in issue order) and
-  // the velocities arrive during the ordering
+  // the velocities arrive during the ordering; the histogram is cleared
+  // while they are in flight
   int jc[kFR];
 #pragma unroll
   for (int k = 0; k < kFR; ++k) jc[k] = min(tid + k * kFB, nsl - 1);
@@ -373,6 +372,8 @@ __device__ __forceinline__ void step_wg(const KParams &P, const Tables *__restri
     vr[k][1] = S.vy[jc[k]];
     vr[k][2] = S.vz[jc[k]];
   }
+  const int nbuckets = coul ? (int)nbk[b] : 0;
+  for (int i = tid; i <= nbuckets; i += kFB) hist[i] = 0u;
 #pragma unroll
   for (int k = 0; k < kFR; ++k) {
     const int i = tid + k * kFB;
