@@ -40,7 +40,7 @@ sort periods replay as one captured graph).  A batch takes new members (a reques
 with the fewest members) and retires finished ones between its launches, up
 to max_batch runs; several batches keep the GPU busy while one of them turns
 around on the host.  Members' results are the same as alone.  Measured on
-one MI355X: a flood of 10k-100k requests is served 15% faster batched
+one MI355X: a flood of 10k-100k requests is served 15-17% faster batched
 (batch_max_n = 100 000), while the scan trace of 10k-2M requests, whose work
 is mostly in large runs with slots of their own, is served as fast either
 way, and above capacity with a lower median latency without batches (a
